@@ -1,0 +1,273 @@
+/*
+ * ns_api.h -- C ABI of the MI355X (gfx950) nested block solver for one
+ * Newton-Raphson step of the VMS / generalized-alpha incompressible
+ * Navier-Stokes discretisation (Liu, Yang, Dong, Marsden, "The nested block
+ * preconditioning technique for the incompressible Navier-Stokes equations
+ * with emphasis on hemodynamic simulations").
+ *
+ * The linear system of one Newton step is (Sec. 2.5, step 9 of the
+ * predictor multi-corrector algorithm, and the block notation of Sec. 3)
+ *
+ *     [ A  B ] [ dv_dot ]     [ R_m ]
+ *     [ C  D ] [ dp_dot ] = - [ R_p ] ,      A = F + K,
+ *     K = alpha_f gamma dt sum_k m^k a^k a^k^T   (rank-one outlet terms),
+ *
+ * solved by FGMRES(m) (Sec. 3) right-preconditioned with the Schur
+ * complement reduction P_SCR (Algorithm 3), whose Schur solve applies
+ * S x = D x - C A^{-1} (B x) matrix-free (Algorithm 2) with an inner GMRES on
+ * A, and whose A- and S-solves are GMRES(m_A), GMRES(m_S) preconditioned by
+ * AMG V-cycles on A and on S_hat = D - C diag(A)^{-1} B (Sec. 3.1).
+ *
+ * Conventions for every entry point
+ * ---------------------------------
+ * - Pointers named d_* are device pointers (HIP global memory of the device
+ *   that was current at ns_ctx_bind); h_* are host pointers.  The caller owns
+ *   all of them; the library keeps no reference to caller memory after a call
+ *   returns, except the workspace given to ns_ctx_bind.
+ * - Vectors over the 4N unknowns use the field-split layout
+ *   [velocity (3N, node-interleaved: 3*node + component) ; pressure (N)].
+ * - All device arithmetic of an entry point is enqueued on the given stream.
+ *   ns_assemble_tangent returns without waiting; the solves wait for their
+ *   stream (their stopping tests read one scalar per Krylov iteration).
+ * - Negative status: the call failed, outputs are undefined, and
+ *   ns_last_error(ctx) describes the failure.  NS_NOT_CONVERGED (> 0): the
+ *   best iterate is in the output and the statistics are filled in.
+ * - A context is not thread-safe; calls on one context must not overlap.
+ */
+#ifndef NS_API_H
+#define NS_API_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ns_ctx ns_ctx; /* opaque, owned by the library */
+
+typedef enum {
+    NS_OK = 0,
+    NS_NOT_CONVERGED = 1,   /* soft failure: tolerance not met within nmax */
+    NS_ERR_ARG = -1,        /* invalid argument or inconsistent sizes */
+    NS_ERR_HIP = -2,        /* a HIP runtime call failed */
+    NS_ERR_NAN = -3,        /* a residual estimate became NaN or Inf */
+    NS_ERR_BREAKDOWN = -4,  /* zero-norm preconditioned vector in the outer solver */
+    NS_ERR_WORKSPACE = -5,  /* workspace missing or smaller than required */
+    NS_ERR_STATE = -6       /* call order violated (e.g. solve before assembly) */
+} ns_status;
+
+/* Mesh: P1 tetrahedra (Sec. 2.3, linear basis), outlet surfaces Gamma_out^k
+ * (Sec. 2.2) and the Dirichlet partition Gamma_g.  Host arrays, read during
+ * ns_ctx_create and ns_ctx_bind only.
+ *   h_xyz        [n_nodes][3] coordinates
+ *   h_tets       [n_elems][4] vertex indices, positive orientation
+ *   h_outlet_ptr [n_outlets + 1] CSR offsets of each outlet into h_faces
+ *   h_faces      [h_outlet_ptr[n_outlets]][3] outlet triangles, right-hand
+ *                normal pointing out of the domain; outlets must have
+ *                disjoint node sets
+ *   h_dirichlet  [n_nodes][4] 1 = Dirichlet (u, v, w) or pinned pressure   */
+typedef struct {
+    int32_t n_nodes, n_elems, n_outlets;
+    const double* h_xyz;
+    const int32_t* h_tets;
+    const int32_t* h_outlet_ptr;
+    const int32_t* h_faces;
+    const uint8_t* h_dirichlet;
+} ns_mesh;
+
+/* Context options: sizes of the Krylov workspaces and the AMG hierarchy.
+ * A field set to 0 takes the default in brackets. */
+typedef struct {
+    int32_t max_m;        /* largest outer restart length m      [200] */
+    int32_t max_m_A;      /* largest m_A                          [200] */
+    int32_t max_m_S;      /* largest m_S                          [200] */
+    int32_t coarse_nodes; /* AMG coarsening stops at <= this many nodes [128] */
+    int32_t max_levels;   /* AMG levels including the coarsest    [16]  */
+} ns_ctx_opts;
+
+/* Physics of one Newton step (Sec. 2.3, 2.4.1, 2.5).
+ *   rho, mu    density and dynamic viscosity
+ *   dt         time step size dt_n
+ *   rho_inf    spectral radius of the generalized-alpha method
+ *   beta_bf    backflow coefficient beta [0.2]
+ *   c_t, c_i   C_T [4] and C_I [36] of tau_M
+ *   h_m        [n_outlets] m^k = dP^k_{n+af}/dQ^k (= R^k for a resistance)
+ *   h_P_af     [n_outlets] outlet pressures P^k_{n+af} in the traction term  */
+typedef struct {
+    double rho, mu, dt, rho_inf, beta_bf, c_t, c_i;
+    const double* h_m;
+    const double* h_P_af;
+} ns_phys;
+
+typedef enum { NS_PC_AMG = 0, NS_PC_JACOBI = 1 } ns_pc;
+typedef enum { NS_FP64 = 0, NS_FP32_INNER = 1 } ns_precision;
+
+/* Solver options (Sec. 3 and 3.1; paper defaults in brackets).  A field set
+ * to 0 takes its default. */
+typedef struct {
+    double rtol;            /* delta^r of FGMRES                      [1e-8]  */
+    double atol;            /* delta^a of every Krylov level          [1e-50] */
+    double rtol_A;          /* delta^r_A, intermediate A-solves       [1e-3]  */
+    double rtol_S;          /* delta^r_S, Schur solve                 [1e-3]  */
+    double rtol_I;          /* delta^r_I, inner A-solve of Alg. 2     [1e-3]  */
+    int32_t m, nmax;        /* FGMRES restart length / max iterations [200]   */
+    int32_t m_A, nmax_A;    /* GMRES on A                             [200]   */
+    int32_t m_S, nmax_S;    /* GMRES on S                             [200]   */
+    int32_t pc_A;           /* ns_pc: P_A                             [AMG]   */
+    int32_t precision;      /* ns_precision                           [FP64]  */
+    int32_t cheb_degree;    /* AMG Chebyshev smoother degree          [2]     */
+    int32_t reserved;
+    /* Iteration schedule.  If h_sched != NULL, the i-th Krylov call (calls
+     * numbered in the order they start: FGMRES, then each GMRES on A or S)
+     * runs exactly h_sched[i] iterations instead of testing its tolerance.
+     * If h_sched_out != NULL, the iteration count of each call is written to
+     * h_sched_out[i] for i < sched_cap, and the number of calls to
+     * ns_stats.n_calls. */
+    const int32_t* h_sched;
+    int32_t sched_len;
+    int32_t sched_cap;
+    int32_t* h_sched_out;
+} ns_solve_opts;
+
+typedef struct {
+    int32_t outer_iters;    /* FGMRES iterations */
+    int32_t a_solves, a_iters;         /* intermediate A-solves (Alg. 3 steps 1, 5) */
+    int32_t s_solves, s_iters;         /* Schur solves (Alg. 3 step 3) */
+    int32_t inner_solves, inner_iters; /* inner A-solves (Alg. 2 step 3) */
+    int32_t n_calls;        /* Krylov calls (schedule entries) */
+    int32_t amg_levels_A, amg_levels_S;
+    double true_rel_res;    /* ||r - A x|| / ||r|| recomputed in FP64 */
+    double setup_ms;        /* per-step preconditioner set-up */
+    double solve_ms;        /* Krylov iterations */
+} ns_stats;
+
+/* ns_ctx_create: symbolic set-up on the host from the mesh alone (node
+ * graph, 4x4-block BSR pattern, element colouring, element-to-block maps,
+ * S_hat pattern, AMG aggregates and Galerkin maps).  No device work.
+ * On success *out owns the context and *workspace_bytes is the size of the
+ * device workspace ns_ctx_bind needs.  Errors: NS_ERR_ARG for inconsistent
+ * sizes, indices out of range, or outlets that share nodes. */
+ns_status ns_ctx_create(const ns_mesh* mesh, const ns_ctx_opts* opts, ns_ctx** out,
+                        size_t* workspace_bytes);
+
+/* ns_ctx_bind: lay out the caller-owned device workspace d_workspace
+ * (>= workspace_bytes, 256-byte aligned) and upload the mesh, pattern and
+ * maps on `stream`; computes the outlet vectors a^k_{Ai} = int N_A n_i
+ * (Sec. 2.5).  The workspace must stay allocated until ns_ctx_destroy.
+ * Errors: NS_ERR_WORKSPACE, NS_ERR_HIP. */
+ns_status ns_ctx_bind(ns_ctx* ctx, void* d_workspace, size_t bytes, hipStream_t stream);
+
+void ns_ctx_destroy(ns_ctx* ctx);
+const char* ns_last_error(const ns_ctx* ctx);
+
+/* ns_outlet_flow: Q^k = int_{Gamma_out^k} v . n = a^k . v (Sec. 2.2 and
+ * step 1 of the multi-corrector) for d_v [n_nodes][3]; writes h_Q
+ * [n_outlets].  Waits for the stream. */
+ns_status ns_outlet_flow(ns_ctx* ctx, const double* d_v, double* h_Q, hipStream_t stream);
+
+/* ns_rank_one_dots: out[k] = a^k . x_v with the Dirichlet entries of a^k
+ * zeroed (the vectors of the rank-one term K, Sec. 2.5) for d_xv
+ * [n_nodes][3] (the velocity part of a field-split vector); writes h_out
+ * [n_outlets].  Used to contract outlet-resistance derivatives.  Waits for
+ * the stream. */
+ns_status ns_rank_one_dots(ns_ctx* ctx, const double* d_xv, double* h_out, hipStream_t stream);
+
+/* ns_assemble_tangent: residual and consistent tangent of one Newton step
+ * (Sec. 2.5, steps 6 and 8; forms of Sec. 2.3) at the intermediate states
+ *   d_v_af    [n_nodes][3] velocity y_{n+af} (Dirichlet values imposed)
+ *   d_p_af    [n_nodes]    pressure at n+af
+ *   d_vdot_am [n_nodes][3] acceleration at n+am
+ * Writes d_rhs [4 n_nodes] = -[R_m; R_p] (field-split), zero at Dirichlet
+ * entries, and keeps the eliminated blocks A (without K), B, C, D in the
+ * workspace.  Quadrature: 4-point rule on tetrahedra, 3-point rule on outlet
+ * triangles; tau_M, tau_C held fixed in the derivative; Dirichlet rows and
+ * columns replaced by the identity.  Colour-by-colour, no atomics.
+ * Asynchronous on `stream`. */
+ns_status ns_assemble_tangent(ns_ctx* ctx, const ns_phys* phys, const double* d_v_af,
+                              const double* d_p_af, const double* d_vdot_am, double* d_rhs,
+                              hipStream_t stream);
+
+/* ns_nested_solve: solve [A B; C D] x = rhs for the last assembled tangent
+ * with FGMRES + P_SCR (Algorithms 2 and 3).  d_rhs, d_x: [4 n_nodes] FP64.
+ * The per-step set-up (diag(A), S_hat, AMG numeric) runs first when the
+ * tangent changed since the previous solve.  In NS_FP32_INNER mode P_SCR runs
+ * in FP32 (inner Krylov vectors, SpMV, V-cycles, dot products) while the
+ * outer FGMRES, the Hessenberg least squares, the true residual and the AMG
+ * coarsest solve stay in FP64.  h_stats may be NULL.
+ * Errors: NS_ERR_STATE (no tangent assembled), NS_ERR_NAN, NS_ERR_BREAKDOWN,
+ * NS_ERR_HIP, NS_ERR_ARG (options beyond the context's Krylov sizes). */
+ns_status ns_nested_solve(ns_ctx* ctx, const ns_solve_opts* opts, const double* d_rhs,
+                          double* d_x, ns_stats* h_stats, hipStream_t stream);
+
+/* ns_adjoint_solve: solve the transposed system [A^T C^T; B^T D^T] lam = g
+ * with the same nested method on the transposed blocks (B' = C^T,
+ * C' = B^T, S_hat' = S_hat^T; K is symmetric).  Same conventions and errors
+ * as ns_nested_solve. */
+ns_status ns_adjoint_solve(ns_ctx* ctx, const ns_solve_opts* opts, const double* d_g,
+                           double* d_lambda, ns_stats* h_stats, hipStream_t stream);
+
+/* ns_newton_update: the update of step 10 of the multi-corrector (Sec. 2.5):
+ * y += gamma dt dy_dot, y_dot += dy_dot, on d_y, d_ydot [4 n_nodes]
+ * (field-split) with d_dx [4 n_nodes]; FP64.  Asynchronous. */
+ns_status ns_newton_update(ns_ctx* ctx, double gamma_dt, const double* d_dx, double* d_y,
+                           double* d_ydot, hipStream_t stream);
+
+/* ---- inspection entry points (used by the tests) -------------------------- */
+
+/* Sizes: [0] n_nodes, [1] nnzb, [2] nnz of S_hat, [3] colours, [4] outlet
+ * nodes, [5] AMG levels (including the coarsest). */
+ns_status ns_query(const ns_ctx* ctx, int64_t* h_sizes6);
+
+/* Node-graph pattern: h_row_ptr [n_nodes + 1], h_col [nnzb] (sorted). */
+ns_status ns_export_pattern(const ns_ctx* ctx, int32_t* h_row_ptr, int32_t* h_col);
+
+/* Aggregate map of AMG level `level` (fine node -> coarse node), [nodes of
+ * that level]. */
+ns_status ns_export_aggregates(const ns_ctx* ctx, int32_t level, int32_t* h_agg);
+
+/* Element colours h_color [n_elems]. */
+ns_status ns_export_colors(const ns_ctx* ctx, int32_t* h_color);
+
+/* Assembled blocks, d_dst [nnzb][4][4] row-major (rows: u, v, w, continuity;
+ * columns: u, v, w, p) of the tangent (transposed = 0) or of its transpose
+ * (transposed = 1, available after ns_adjoint_solve).  Synchronous. */
+ns_status ns_export_bsr(ns_ctx* ctx, int32_t transposed, double* d_dst, hipStream_t stream);
+
+/* S_hat values on its pattern: h_row_ptr [n+1], h_col [nnz], d_val [nnz]
+ * (FP64, from the last set-up of the forward system).  Synchronous. */
+ns_status ns_export_shat(ns_ctx* ctx, int32_t* h_row_ptr, int32_t* h_col, double* d_val,
+                         hipStream_t stream);
+
+/* Outlet vectors with the Dirichlet entries zeroed, d_a [n_outlets][n_nodes][3].
+ * Synchronous. */
+ns_status ns_export_outlet_vectors(ns_ctx* ctx, double* d_a, hipStream_t stream);
+
+typedef enum {
+    NS_OP_FULL = 0,   /* y = [A B; C D] x  (A = F + K), x, y: [4N]        */
+    NS_OP_A = 1,      /* y = (F + K) x,                 x, y: [3N]        */
+    NS_OP_B = 2,      /* y = B x,                       x: [N],  y: [3N]  */
+    NS_OP_C = 3,      /* y = C x,                       x: [3N], y: [N]   */
+    NS_OP_D = 4,      /* y = D x,                       x, y: [N]         */
+    NS_OP_SHAT = 5,   /* y = S_hat x,                   x, y: [N]         */
+    NS_OP_VCYCLE_A = 6, /* y = one AMG V-cycle of the A hierarchy on x [3N] */
+    NS_OP_VCYCLE_S = 7, /* y = one AMG V-cycle of the S_hat hierarchy [N]  */
+    NS_OP_SCHUR = 8,  /* y = Algorithm 2 applied to x [N] (inner rtol_I)  */
+    NS_OP_PSCR = 9,   /* y = Algorithm 3 applied to x [4N]                */
+    NS_OP_SOLVE_A = 10 /* y = GMRES(m_A) solution of A y = x to rtol_A    */
+} ns_op;
+
+/* ns_apply: one operator of the forward system, after the per-step set-up
+ * (which it runs if needed).  d_x, d_y: FP64 device vectors; with precision
+ * NS_FP32_INNER the operator runs in FP32 on rounded inputs.  opts may be
+ * NULL for the plain operators (0-5).  Synchronous. */
+ns_status ns_apply(ns_ctx* ctx, int32_t op, const ns_solve_opts* opts, const double* d_x,
+                   double* d_y, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NS_API_H */

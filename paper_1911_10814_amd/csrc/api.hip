@@ -1,0 +1,1151 @@
+// Host orchestration and the C ABI of the nested block solver.
+//
+// One Newton step = tangent assembly (Sec. 2.5, steps 6 and 8), per-step
+// preconditioner set-up, and FGMRES(m) (Sec. 3) right-preconditioned by the
+// Schur complement reduction P_SCR (Algorithm 3) whose Schur solve uses the
+// matrix-free action of Algorithm 2.  All vector, matrix and reduction work
+// runs in HIP kernels; the host drives the Krylov loops and reads one status
+// record per Krylov iteration for the stopping test.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <functional>
+#include <stdexcept>
+#include <string>
+#include <type_traits>
+
+#include "kernels.h"
+
+using namespace ns;
+
+namespace {
+
+thread_local std::string g_create_err;
+
+struct Fail {
+    ns_status st;
+    std::string msg;
+};
+
+#define HIPCHK(x)                                                                                  \
+    do {                                                                                           \
+        hipError_t e_ = (x);                                                                       \
+        if (e_ != hipSuccess)                                                                      \
+            throw Fail{NS_ERR_HIP, std::string(#x) + ": " + hipGetErrorString(e_) + " (line " +     \
+                                       std::to_string(__LINE__) + ")"};                            \
+    } while (0)
+
+inline void check_launch() { HIPCHK(hipGetLastError()); }
+
+template <typename T>
+inline T* as(double* p) {
+    return reinterpret_cast<T*>(p);
+}
+
+int dflt(int v, int d) { return v > 0 ? v : d; }
+double dfltd(double v, double d) { return v > 0 ? v : d; }
+
+// ---------------------------------------------------------------------------
+// workspace layout (measured with a null base, then applied to the real one)
+// ---------------------------------------------------------------------------
+
+template <typename T>
+T* up(Arena& A, const std::vector<T>& v) {
+    return A.take<T>(std::max<size_t>(v.size(), 1));
+}
+
+void layout(ns_ctx* c, Arena& A) {
+    const Symbolic& S = c->sym;
+    const int N = S.N;
+    const int64_t nnzb = S.g.nnz();
+    const int64_t nS = S.shat.nnz();
+    const int nslot = (int)S.onode.size();
+    const int NO = S.n_out;
+    c->d_rp = up(A, S.g.rp);
+    c->d_col = up(A, S.g.col);
+    c->d_diag = up(A, S.diag_pos);
+    c->d_rowof = up(A, S.row_of);
+    c->d_tmap = up(A, S.tmap);
+    c->d_tets = up(A, S.tets);
+    c->d_emap = up(A, S.emap);
+    c->d_faces = up(A, S.faces);
+    c->d_fmap = up(A, S.fmap);
+    c->d_fslot = up(A, S.fslot);
+    c->d_face_out = up(A, S.face_out);
+    c->d_onode = up(A, S.onode);
+    c->d_oid = up(A, S.oid);
+    c->d_slot_of = up(A, S.slot_of);
+    c->d_optr = up(A, S.optr);
+    c->d_srp = up(A, S.shat.rp);
+    c->d_scol = up(A, S.shat.col);
+    c->d_mask = A.take<uint8_t>((size_t)N * 4);
+    c->d_xyz = A.take<double>((size_t)N * 3);
+    c->d_a_raw = A.take<double>(std::max(1, nslot * 3));
+    c->d_a_msk = A.take<double>(std::max(1, nslot * 3));
+    c->d_a_msk32 = A.take<float>(std::max(1, nslot * 3));
+    c->d_aos = A.take<double>((size_t)nnzb * 16);
+    c->d_res = A.take<double>((size_t)N * 4);
+    c->d_ck = A.take<double>(std::max(1, NO));
+    c->d_ck32 = A.take<float>(std::max(1, NO));
+    c->d_s = A.take<double>(std::max(1, NO));
+    c->d_Paf = A.take<double>(std::max(1, NO));
+    const int mo = dflt(c->opts.max_m, 200), ma = dflt(c->opts.max_m_A, 200), ms = dflt(c->opts.max_m_S, 200);
+    const int mmax = std::max(mo, std::max(ma, ms));
+    c->d_red = A.take<double>((size_t)(mmax + 4) * kMaxRedBlocks);
+    c->d_counter = A.take<uint32_t>(64);
+
+    // AMG patterns (shared by the forward and transposed systems)
+    const int L = (int)S.lv.size();
+    for (int s = 0; s < 2; ++s) {
+        c->sys[s].A.assign(L, AmgLevelDev{});
+        c->sys[s].S.assign(L, AmgLevelDev{});
+    }
+    for (int l = 0; l < L; ++l) {
+        const AmgLevelSym& ls = S.lv[l];
+        AmgLevelDev& a = c->sys[0].A[l];
+        AmgLevelDev& sd = c->sys[0].S[l];
+        a.n = sd.n = ls.n;
+        a.bs = 3;
+        sd.bs = 1;
+        a.nnz = ls.a.nnz();
+        sd.nnz = ls.s.nnz();
+        if (l == 0) {
+            a.rp = c->d_rp;
+            a.col = c->d_col;
+            sd.rp = c->d_srp;
+            sd.col = c->d_scol;
+        } else {
+            a.rp = up(A, ls.a.rp);
+            a.col = up(A, ls.a.col);
+            sd.rp = up(A, ls.s.rp);
+            sd.col = up(A, ls.s.col);
+            a.gptr = up(A, ls.gptr);
+            a.gidx = up(A, ls.gidx);
+            a.qrow = up(A, ls.a_qrow);
+            sd.gptr = up(A, ls.sgptr);
+            sd.gidx = up(A, ls.sgidx);
+            sd.qrow = a.qrow;  // unused for S
+        }
+        if (l + 1 < L) {
+            a.agg = sd.agg = up(A, ls.agg);
+            a.aptr = sd.aptr = up(A, ls.aptr);
+            a.anodes = sd.anodes = up(A, ls.anodes);
+        }
+        for (AmgLevelDev* d : {&a, &sd}) {
+            const int64_t nv = (int64_t)d->n * d->bs;
+            d->x0 = A.take<double>(nv);
+            d->x1 = A.take<double>(nv);
+            d->d = A.take<double>(nv);
+            d->r = A.take<double>(nv);
+            d->b = A.take<double>(nv);
+        }
+        c->sys[1].A[l] = a;
+        c->sys[1].S[l] = sd;
+    }
+    // numeric values per system
+    for (int s = 0; s < 2; ++s) {
+        SystemDev& y = c->sys[s];
+        y.V64 = A.take<double>((size_t)nnzb * 16);
+        y.V32 = A.take<float>((size_t)nnzb * 16);
+        y.dK64 = A.take<double>((size_t)N * 3);
+        y.diagA64 = A.take<double>((size_t)N * 3);
+        y.dinvA64 = A.take<double>((size_t)N * 3);
+        y.dK32 = A.take<float>((size_t)N * 3);
+        y.dinvA32 = A.take<float>((size_t)N * 3);
+        y.shat64 = A.take<double>(nS);
+        y.shat32 = A.take<float>(nS);
+        for (int l = 0; l < L; ++l) {
+            for (int h = 0; h < 2; ++h) {
+                AmgLevelDev& d = h == 0 ? y.A[l] : y.S[l];
+                const int64_t nv = (int64_t)d.n * d.bs;
+                if (l == 0) {
+                    if (h == 0) {
+                        d.v64 = y.V64;
+                        d.v32 = y.V32;
+                        d.rstride = 4 * nnzb;
+                        d.cstride = nnzb;
+                        d.dinv64 = y.dinvA64;
+                        d.dinv32 = y.dinvA32;
+                        d.dextra64 = y.dK64;
+                        d.dextra32 = y.dK32;
+                    } else {
+                        d.v64 = y.shat64;
+                        d.v32 = y.shat32;
+                        d.dinv64 = A.take<double>(nv);
+                        d.dinv32 = A.take<float>(nv);
+                    }
+                } else {
+                    d.v64 = A.take<double>((size_t)d.nnz * d.bs * d.bs);
+                    d.v32 = A.take<float>((size_t)d.nnz * d.bs * d.bs);
+                    d.rstride = d.bs * d.nnz;
+                    d.cstride = d.nnz;
+                    d.dinv64 = A.take<double>(nv);
+                    d.dinv32 = A.take<float>(nv);
+                }
+                if (l == L - 1) {
+                    d.inv = A.take<double>((size_t)nv * nv);
+                    d.work = A.take<double>((size_t)nv * 2 * nv);
+                }
+            }
+        }
+    }
+    // Krylov workspaces
+    auto kry = [&](KrylovWs& k, int m, int64_t n, bool outer) {
+        k.m = m;
+        k.n = n;
+        k.V = A.take<double>((size_t)(m + 1) * n);
+        k.Z = outer ? A.take<double>((size_t)m * n) : nullptr;
+        k.tmp = A.take<double>(n);
+        k.H = A.take<double>((size_t)(m + 1) * m);
+        k.cs = A.take<double>(m);
+        k.sn = A.take<double>(m);
+        k.g = A.take<double>(m + 1);
+        k.y = A.take<double>(m);
+        k.h = A.take<double>(2 * (size_t)(m + 2));
+        k.status = A.take<double>(8);
+    };
+    kry(c->kw_out, mo, 4 * (int64_t)N, true);
+    kry(c->kw_A, ma, 3 * (int64_t)N, false);
+    kry(c->kw_S, ms, (int64_t)N, false);
+    c->t_s = A.take<double>(4 * (size_t)N);
+    c->t_yhat = A.take<double>(3 * (size_t)N);
+    c->t_tp = A.take<double>(N);
+    c->t_yp = A.take<double>(4 * (size_t)N);
+    c->t_tv = A.take<double>(3 * (size_t)N);
+    c->t_yv = A.take<double>(3 * (size_t)N);
+    c->t_xhat = A.take<double>(N);
+    c->t_xbar = A.take<double>(3 * (size_t)N);
+    c->t_xt = A.take<double>(3 * (size_t)N);
+    c->t_r4 = A.take<double>(4 * (size_t)N);
+    A.take<char>(256);
+}
+
+template <typename T>
+void h2d(T* d, const std::vector<T>& v, hipStream_t st) {
+    if (!v.empty()) HIPCHK(hipMemcpyAsync(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st));
+}
+
+// ---------------------------------------------------------------------------
+// Schedule of Krylov iteration counts
+// ---------------------------------------------------------------------------
+
+struct Sched {
+    const int32_t* replay = nullptr;
+    int replay_len = 0;
+    std::vector<int32_t> log;
+    int begin(int& forced) {
+        const int idx = (int)log.size();
+        log.push_back(0);
+        forced = -1;
+        if (replay) {
+            if (idx >= replay_len) throw Fail{NS_ERR_ARG, "iteration schedule shorter than the solve"};
+            forced = replay[idx];
+        }
+        return idx;
+    }
+    void end(int idx, int count) { log[idx] = count; }
+};
+
+// ---------------------------------------------------------------------------
+// The solver for one system (forward or transposed), precision T inside P_SCR
+// ---------------------------------------------------------------------------
+
+template <typename T>
+struct Typed;
+template <>
+struct Typed<double> {
+    static const double* V(const SystemDev& y) { return y.V64; }
+    static const double* lv(const AmgLevelDev& d) { return d.v64; }
+    static const double* dinv(const AmgLevelDev& d) { return d.dinv64; }
+    static const double* dextra(const AmgLevelDev& d) { return d.dextra64; }
+    static const double* amsk(const ns_ctx* c) { return c->d_a_msk; }
+    static const double* ck(const ns_ctx* c) { return c->d_ck; }
+};
+template <>
+struct Typed<float> {
+    static const float* V(const SystemDev& y) { return y.V32; }
+    static const float* lv(const AmgLevelDev& d) { return d.v32; }
+    static const float* dinv(const AmgLevelDev& d) { return d.dinv32; }
+    static const float* dextra(const AmgLevelDev& d) { return d.dextra32; }
+    static const float* amsk(const ns_ctx* c) { return c->d_a_msk32; }
+    static const float* ck(const ns_ctx* c) { return c->d_ck32; }
+};
+
+struct Ctl {
+    ns_ctx* c;
+    SystemDev* sy;
+    ns_solve_opts o;
+    Sched sc;
+    hipStream_t st;
+    ns_stats stats{};
+};
+
+void read_status(ns_ctx* c, const double* d_status, int n, hipStream_t st) {
+    HIPCHK(hipMemcpyAsync(c->h_pinned, d_status, n * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+}
+
+template <typename T>
+double dev_norm(ns_ctx* c, int64_t n, const T* x, double* slot, hipStream_t st) {
+    norm2<T>(n, x, slot, c->d_red, c->d_counter, st);
+    check_launch();
+    read_status(c, slot, 1, st);
+    return c->h_pinned[0];
+}
+
+// One Arnoldi step on column j: w (already in V_{j+1}) is orthogonalised
+// against V_0..V_j by two classical Gram-Schmidt passes; the Hessenberg column
+// and Givens rotation are updated on the device; returns |g_{j+1}| and the
+// breakdown flag.
+template <typename T>
+void arnoldi_orth(ns_ctx* c, KrylovWs& kw, int64_t n, int j, T* V, hipStream_t st, double& resid, bool& bd) {
+    T* w = V + (int64_t)(j + 1) * n;
+    double* h1 = kw.h;
+    double* h2 = kw.h + (kw.m + 2);
+    multidot<T>(n, j + 1, V, n, w, true, h1, c->d_red, c->d_counter, st);
+    orth_update<T>(n, j + 1, V, n, h1, w, nullptr, c->d_red, c->d_counter, st);
+    multidot<T>(n, j + 1, V, n, w, false, h2, c->d_red, c->d_counter, st);
+    GivensArgs ga;
+    ga.j = j;
+    ga.ldh = kw.m + 1;
+    ga.h1 = h1;
+    ga.h2 = h2;
+    ga.H = kw.H;
+    ga.cs = kw.cs;
+    ga.sn = kw.sn;
+    ga.g = kw.g;
+    ga.status = kw.status;
+    orth_update<T>(n, j + 1, V, n, h2, w, &ga, c->d_red, c->d_counter, st);
+    scale_by_status<T>(n, w, kw.status, st);
+    check_launch();
+    read_status(c, kw.status, 4, st);
+    resid = c->h_pinned[0];
+    bd = c->h_pinned[1] != 0.0;
+    if (!std::isfinite(resid)) throw Fail{NS_ERR_NAN, "residual estimate is not finite"};
+}
+
+// Left-preconditioned GMRES(m) for M x = b from x = 0 (Sec. 3.1; stopping on
+// the preconditioned residual relative to ||P^{-1} b||).
+template <typename T>
+int gmres_left(Ctl& K, KrylovWs& kw, int64_t n, const std::function<void(const T*, T*)>& applyM,
+               const std::function<void(const T*, T*)>& applyP, const T* b, T* x, double rtol, int m, int nmax) {
+    ns_ctx* c = K.c;
+    hipStream_t st = K.st;
+    int forced;
+    const int idx = K.sc.begin(forced);
+    T* V = as<T>(kw.V);
+    T* tmp = as<T>(kw.tmp);
+    applyP(b, V);
+    const double beta0 = dev_norm<T>(c, n, V, kw.status + 4, st);
+    int total = 0;
+    if (beta0 == 0.0 || forced == 0) {
+        fill<T>(n, T(0), x, st);
+        K.sc.end(idx, 0);
+        return 0;
+    }
+    const double tol = std::max(rtol * beta0, K.o.atol);
+    double beta = beta0;
+    bool first = true;
+    while (true) {
+        scale_by<T>(n, V, kw.status + 4, true, V, st);
+        init_g(kw.g, m + 1, beta, st);
+        int k = 0;
+        bool finished = false;
+        for (int j = 0; j < m; ++j) {
+            applyM(V + (int64_t)j * n, tmp);
+            applyP(tmp, V + (int64_t)(j + 1) * n);
+            double resid;
+            bool bd;
+            arnoldi_orth<T>(c, kw, n, j, V, st, resid, bd);
+            ++total;
+            k = j + 1;
+            const bool done = forced >= 0 ? total >= forced : resid <= tol;
+            if (done || bd || total >= nmax) {
+                finished = true;
+                break;
+            }
+        }
+        backsolve(k, m + 1, kw.H, kw.g, kw.y, st);
+        combine<T, T>(n, k, V, n, kw.y, x, !first, st);
+        check_launch();
+        first = false;
+        if (finished) break;
+        // restart: r = P (b - M x)
+        applyM(x, tmp);
+        axpby<T>(n, T(-1), tmp, T(1), b, tmp, st);
+        applyP(tmp, V);
+        beta = dev_norm<T>(c, n, V, kw.status + 4, st);
+        if (beta == 0.0 || (forced < 0 && beta <= tol)) break;
+    }
+    K.sc.end(idx, total);
+    return total;
+}
+
+template <typename T>
+struct Nested {
+    Ctl& K;
+    ns_ctx* c;
+    SystemDev& sy;
+    int N;
+    int64_t nnzb;
+    Nested(Ctl& k) : K(k), c(k.c), sy(*k.sy), N(k.c->sym.N), nnzb(k.c->sym.g.nnz()) {}
+
+    const T* V() const { return Typed<T>::V(sy); }
+    BlockOp<T> op(int r0, int c0) const {
+        BlockOp<T> M;
+        M.n = N;
+        M.rp = c->d_rp;
+        M.col = c->d_col;
+        M.v = V() + (4 * r0 + c0) * nnzb;
+        M.rs = 4 * nnzb;
+        M.cs = nnzb;
+        return M;
+    }
+    BlockOp<T> level_op(const AmgLevelDev& d) const {
+        BlockOp<T> M;
+        M.n = d.n;
+        M.rp = d.rp;
+        M.col = d.col;
+        M.v = Typed<T>::lv(d);
+        M.rs = d.rstride;
+        M.cs = d.cstride;
+        M.dextra = Typed<T>::dextra(d);
+        return M;
+    }
+    RankOne<T> rank_one() const {
+        RankOne<T> r;
+        if (c->sym.n_out == 0) return r;
+        r.slot_of = c->d_slot_of;
+        r.oid = c->d_oid;
+        r.aval = Typed<T>::amsk(c);
+        r.s = as<T>(c->d_s);
+        return r;
+    }
+    // y = (F + K) x
+    void applyA(const T* x, T* y) {
+        RankOne<T> r = rank_one();
+        if (r.slot_of)
+            outlet_dot<T>(c->sym.n_out, c->d_optr, c->d_onode, Typed<T>::amsk(c), Typed<T>::ck(c), x, as<T>(c->d_s),
+                          K.st);
+        spmv<T>(3, 3, op(0, 0), x, y, T(1), nullptr, T(0), nullptr, r.slot_of ? &r : nullptr, K.st);
+    }
+    void vcycle(std::vector<AmgLevelDev>& H, int l, const T* b, T* xout) {
+        AmgLevelDev& L = H[l];
+        const int bs = L.bs;
+        const int64_t nv = (int64_t)L.n * bs;
+        hipStream_t st = K.st;
+        if (l + 1 == (int)H.size()) {
+            dense_gemv<T>((int)nv, L.inv, b, xout, st);
+            return;
+        }
+        const int deg = dflt(K.o.cheb_degree, 2);
+        const BlockOp<T> M = level_op(L);
+        const T* dinv = Typed<T>::dinv(L);
+        const double lmax = L.lmax, lmin = lmax / 30.0;
+        const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin), sigma = theta / delta;
+        T* a = as<T>(L.x0);  // 2*deg-1 ping-pong flips: start in the scratch buffer, end in xout
+        T* bb = xout;
+        T* d = as<T>(L.d);
+        // pre-smoothing from x = 0
+        double rho = 1.0 / sigma;
+        cheb_first<T>(nv, b, dinv, T(1.0 / theta), a, d, st);
+        for (int i = 1; i < deg; ++i) {
+            const double rn = 1.0 / (2.0 * sigma - rho);
+            cheb_step<T>(bs, M, a, bb, d, b, dinv, T(rn * rho), T(2.0 * rn / delta), st);
+            std::swap(a, bb);
+            rho = rn;
+        }
+        // coarse-grid correction
+        AmgLevelDev& C = H[l + 1];
+        spmv<T>(bs, bs, M, a, as<T>(L.r), T(-1), b, T(1), nullptr, nullptr, st);
+        restrict_agg<T>(C.n, bs, L.aptr, L.anodes, as<T>(L.r), as<T>(C.b), st);
+        vcycle(H, l + 1, as<T>(C.b), as<T>(C.x1));
+        prolong_add<T>(L.n, bs, L.agg, as<T>(C.x1), a, st);
+        // post-smoothing
+        rho = 1.0 / sigma;
+        cheb_step<T>(bs, M, a, bb, d, b, dinv, T(0), T(1.0 / theta), st);
+        std::swap(a, bb);
+        for (int i = 1; i < deg; ++i) {
+            const double rn = 1.0 / (2.0 * sigma - rho);
+            cheb_step<T>(bs, M, a, bb, d, b, dinv, T(rn * rho), T(2.0 * rn / delta), st);
+            std::swap(a, bb);
+            rho = rn;
+        }
+    }
+    void applyPA(const T* r, T* z) {
+        if (K.o.pc_A == NS_PC_JACOBI)
+            mul<T>(3 * (int64_t)N, Typed<T>::dinv(sy.A[0]), r, z, K.st);
+        else
+            vcycle(sy.A, 0, r, z);
+    }
+    void applyPS(const T* r, T* z) { vcycle(sy.S, 0, r, z); }
+
+    int solveA(const T* b, T* x, double rtol) {
+        return gmres_left<T>(
+            K, c->kw_A, 3 * (int64_t)N, [this](const T* in, T* out) { applyA(in, out); },
+            [this](const T* in, T* out) { applyPA(in, out); }, b, x, rtol, dflt(K.o.m_A, 200),
+            dflt(K.o.nmax_A, 200));
+    }
+    // Algorithm 2: y = D x - C A^{-1} (B x)
+    void schur(const T* xp, T* y) {
+        hipStream_t st = K.st;
+        spmv<T>(1, 1, op(3, 3), xp, as<T>(c->t_xhat), T(1), nullptr, T(0), nullptr, nullptr, st);
+        spmv<T>(3, 1, op(0, 3), xp, as<T>(c->t_xbar), T(1), nullptr, T(0), nullptr, nullptr, st);
+        const int it = solveA(as<T>(c->t_xbar), as<T>(c->t_xt), dfltd(K.o.rtol_I, 1e-3));
+        K.stats.inner_solves++;
+        K.stats.inner_iters += it;
+        spmv<T>(1, 3, op(3, 0), as<T>(c->t_xt), y, T(-1), as<T>(c->t_xhat), T(1), nullptr, nullptr, st);
+    }
+    int solveS(const T* b, T* x) {
+        return gmres_left<T>(
+            K, c->kw_S, N, [this](const T* in, T* out) { schur(in, out); },
+            [this](const T* in, T* out) { applyPS(in, out); }, b, x, dfltd(K.o.rtol_S, 1e-3), dflt(K.o.m_S, 200),
+            dflt(K.o.nmax_S, 200));
+    }
+    // Algorithm 3: y = P_SCR^{-1} s   (s, y: [4N], field-split)
+    void scr(const T* s, T* y) {
+        hipStream_t st = K.st;
+        const T* sv = s;
+        const T* sp = s + 3 * (int64_t)N;
+        T* yhat = as<T>(c->t_yhat);
+        int it = solveA(sv, yhat, dfltd(K.o.rtol_A, 1e-3));
+        K.stats.a_solves++;
+        K.stats.a_iters += it;
+        spmv<T>(1, 3, op(3, 0), yhat, as<T>(c->t_tp), T(-1), sp, T(1), nullptr, nullptr, st);
+        T* yp = y + 3 * (int64_t)N;
+        it = solveS(as<T>(c->t_tp), yp);
+        K.stats.s_solves++;
+        K.stats.s_iters += it;
+        spmv<T>(3, 1, op(0, 3), yp, as<T>(c->t_tv), T(-1), sv, T(1), nullptr, nullptr, st);
+        it = solveA(as<T>(c->t_tv), y, dfltd(K.o.rtol_A, 1e-3));
+        K.stats.a_solves++;
+        K.stats.a_iters += it;
+    }
+};
+
+// Outer FGMRES(m), right preconditioned, FP64 (Sec. 3).
+template <typename T>
+ns_status fgmres(Ctl& K, const double* b, double* x) {
+    ns_ctx* c = K.c;
+    hipStream_t st = K.st;
+    KrylovWs& kw = c->kw_out;
+    const int N = c->sym.N;
+    const int64_t n = 4 * (int64_t)N;
+    const int m = dflt(K.o.m, 200), nmax = dflt(K.o.nmax, 200);
+    Nested<T> P(K);
+    Nested<double> P64(K);
+    RankOne<double> r1 = P64.rank_one();
+    auto applyFull = [&](const double* in, double* out, double alpha, const double* z, double beta) {
+        if (r1.slot_of)
+            outlet_dot<double>(c->sym.n_out, c->d_optr, c->d_onode, c->d_a_msk, c->d_ck, in, c->d_s, st);
+        spmv_full<double>(N, c->d_rp, c->d_col, K.sy->V64, c->sym.g.nnz(), in, out, alpha, z, beta,
+                          r1.slot_of ? &r1 : nullptr, st);
+    };
+    int forced;
+    const int idx = K.sc.begin(forced);
+    double* V = kw.V;
+    double* Z = kw.Z;
+    const double bnorm = dev_norm<double>(c, n, b, kw.status + 4, st);
+    if (bnorm == 0.0 || forced == 0) {
+        fill<double>(n, 0.0, x, st);
+        K.sc.end(idx, 0);
+        K.stats.true_rel_res = 0.0;
+        HIPCHK(hipStreamSynchronize(st));
+        return NS_OK;
+    }
+    const double tol = std::max(dfltd(K.o.rtol, 1e-8) * bnorm, K.o.atol);
+    fill<double>(n, 0.0, x, st);
+    convert<double, double>(n, b, V, st);  // V_0 = b / ||b|| (the norm is already in status[4])
+    double beta = bnorm;
+    int total = 0;
+    while (true) {
+        scale_by<double>(n, V, kw.status + 4, true, V, st);
+        init_g(kw.g, m + 1, beta, st);
+        int k = 0;
+        for (int j = 0; j < m; ++j) {
+            double* vj = V + (int64_t)j * n;
+            double* zj = Z + (int64_t)j * n;
+            if (std::is_same<T, double>::value) {
+                P.scr(reinterpret_cast<const T*>(vj), reinterpret_cast<T*>(zj));
+            } else {
+                convert<double, T>(n, vj, as<T>(c->t_s), st);
+                P.scr(as<T>(c->t_s), as<T>(c->t_yp));
+                convert<T, double>(n, as<T>(c->t_yp), zj, st);
+            }
+            applyFull(zj, V + (int64_t)(j + 1) * n, 1.0, nullptr, 0.0);
+            double resid;
+            bool bd;
+            arnoldi_orth<double>(c, kw, n, j, V, st, resid, bd);
+            ++total;
+            k = j + 1;
+            const bool done = forced >= 0 ? total >= forced : resid <= tol;
+            if (done || bd || total >= nmax) break;
+        }
+        backsolve(k, m + 1, kw.H, kw.g, kw.y, st);
+        combine<double, double>(n, k, Z, n, kw.y, x, true, st);
+        // true residual in FP64
+        applyFull(x, V, -1.0, b, 1.0);
+        check_launch();
+        beta = dev_norm<double>(c, n, V, kw.status + 4, st);
+        if (!std::isfinite(beta)) throw Fail{NS_ERR_NAN, "true residual is not finite"};
+        if (forced >= 0) {
+            if (total >= forced || beta == 0.0) break;
+        } else if (beta <= tol || total >= nmax || beta == 0.0) {
+            break;
+        }
+    }
+    K.sc.end(idx, total);
+    K.stats.outer_iters = total;
+    K.stats.true_rel_res = beta / bnorm;
+    return beta <= tol || forced >= 0 ? NS_OK : NS_NOT_CONVERGED;
+}
+
+// ---------------------------------------------------------------------------
+// per-step set-up: diag(A) with the lumped rank-one diagonal, S_hat, AMG
+// numeric (Galerkin sums, Jacobi diagonals, lambda_max, coarsest inverse)
+// ---------------------------------------------------------------------------
+
+double power_lambda(ns_ctx* c, const BlockOp<double>& M, int bs, const double* dinv, double* x, double* y,
+                    hipStream_t st) {
+    const int64_t n = (int64_t)M.n * bs;
+    power_start(n, x, st);
+    double* nrm = c->kw_out.status + 6;
+    norm2<double>(n, x, nrm, c->d_red, c->d_counter, st);
+    scale_by<double>(n, x, nrm, true, x, st);
+    for (int it = 0; it < 10; ++it) {
+        spmv<double>(bs, bs, M, x, y, 1.0, nullptr, 0.0, dinv, nullptr, st);
+        norm2<double>(n, y, nrm, c->d_red, c->d_counter, st);
+        scale_by<double>(n, y, nrm, true, x, st);
+    }
+    check_launch();
+    read_status(c, nrm, 1, st);
+    return c->h_pinned[0];
+}
+
+void setup_system(ns_ctx* c, SystemDev& y, bool need32, hipStream_t st) {
+    const Symbolic& S = c->sym;
+    const int N = S.N;
+    const int64_t nnzb = S.g.nnz();
+    const int L = (int)S.lv.size();
+    if (!y.ready || y.version != c->version) {
+        fill<double>(3 * (int64_t)N, 0.0, y.dK64, st);
+        rank_one_diag((int)S.onode.size(), c->d_onode, c->d_oid, c->d_a_msk, c->d_ck, y.dK64, st);
+        block_dinv(N, 3, c->d_rp, c->d_col, y.V64, 4 * nnzb, nnzb, y.dK64, y.dinvA64, y.diagA64, st);
+        shat_numeric(N, c->d_rp, c->d_col, y.V64, nnzb, y.dinvA64, c->d_srp, c->d_scol, y.shat64, st);
+        block_dinv(N, 1, c->d_srp, c->d_scol, y.shat64, 0, 0, nullptr, y.S[0].dinv64, nullptr, st);
+        for (int l = 1; l < L; ++l) {
+            AmgLevelDev& f = y.A[l - 1];
+            AmgLevelDev& a = y.A[l];
+            galerkin(a.nnz, 3, 3, a.gptr, a.gidx, f.v64, f.rstride, f.cstride, a.v64, a.rstride, a.cstride, a.qrow,
+                     a.col, l == 1 ? y.dK64 : nullptr, f.aptr, f.anodes, st);
+            block_dinv(a.n, 3, a.rp, a.col, a.v64, a.rstride, a.cstride, nullptr, a.dinv64, nullptr, st);
+            AmgLevelDev& fs = y.S[l - 1];
+            AmgLevelDev& s = y.S[l];
+            galerkin(s.nnz, 1, 1, s.gptr, s.gidx, fs.v64, 0, 0, s.v64, 0, 0, nullptr, s.col, nullptr, nullptr,
+                     nullptr, st);
+            block_dinv(s.n, 1, s.rp, s.col, s.v64, 0, 0, nullptr, s.dinv64, nullptr, st);
+        }
+        check_launch();
+        for (int h = 0; h < 2; ++h) {
+            std::vector<AmgLevelDev>& H = h == 0 ? y.A : y.S;
+            for (int l = 0; l < L; ++l) {
+                AmgLevelDev& d = H[l];
+                BlockOp<double> M;
+                M.n = d.n;
+                M.rp = d.rp;
+                M.col = d.col;
+                M.v = d.v64;
+                M.rs = d.rstride;
+                M.cs = d.cstride;
+                M.dextra = d.dextra64;
+                if (l + 1 < L) {
+                    d.lmax = 1.1 * power_lambda(c, M, d.bs, d.dinv64, d.x0, d.r, st);
+                } else {
+                    dense_from_csr(d.n, d.bs, d.rp, d.col, d.v64, d.rstride, d.cstride, d.dextra64, d.work, st);
+                    gauss_jordan_inverse(d.n * d.bs, d.work, d.inv, st);
+                    check_launch();
+                }
+            }
+        }
+        y.ready = true;
+        y.have32 = false;
+        y.version = c->version;
+    }
+    if (need32 && !y.have32) {
+        convert<double, float>(nnzb * 16, y.V64, y.V32, st);
+        convert<double, float>(3 * (int64_t)N, y.dK64, y.dK32, st);
+        convert<double, float>(3 * (int64_t)N, y.dinvA64, y.dinvA32, st);
+        convert<double, float>(S.shat.nnz(), y.shat64, y.shat32, st);
+        for (int h = 0; h < 2; ++h) {
+            std::vector<AmgLevelDev>& H = h == 0 ? y.A : y.S;
+            for (int l = 0; l < L; ++l) {
+                AmgLevelDev& d = H[l];
+                if (l > 0) convert<double, float>(d.nnz * d.bs * d.bs, d.v64, d.v32, st);
+                if (!(h == 0 && l == 0)) convert<double, float>((int64_t)d.n * d.bs, d.dinv64, d.dinv32, st);
+            }
+        }
+        const int nslot = (int)S.onode.size();
+        convert<double, float>(3 * (int64_t)nslot, c->d_a_msk, c->d_a_msk32, st);
+        convert<double, float>(S.n_out, c->d_ck, c->d_ck32, st);
+        check_launch();
+        y.have32 = true;
+    }
+}
+
+void ensure_transposed(ns_ctx* c, hipStream_t st) {
+    SystemDev& t = c->sys[1];
+    if (t.ready && t.version == c->version) return;
+    transpose_values(c->sym.g.nnz(), c->d_tmap, c->sys[0].V64, t.V64, st);
+    check_launch();
+    t.ready = false;
+}
+
+ns_status run_solve(ns_ctx* c, int which, const ns_solve_opts* opts, const double* b, double* x, ns_stats* hs,
+                    hipStream_t st) {
+    if (!c->bound) throw Fail{NS_ERR_STATE, "context not bound"};
+    if (!c->assembled) throw Fail{NS_ERR_STATE, "no tangent assembled"};
+    if (!b || !x) throw Fail{NS_ERR_ARG, "null vector"};
+    Ctl K{};
+    K.c = c;
+    K.st = st;
+    if (opts) K.o = *opts;
+    K.o.atol = K.o.atol > 0 ? K.o.atol : 1e-50;
+    if (dflt(K.o.m, 200) > c->kw_out.m || dflt(K.o.m_A, 200) > c->kw_A.m || dflt(K.o.m_S, 200) > c->kw_S.m)
+        throw Fail{NS_ERR_ARG, "restart length exceeds the context's Krylov workspace"};
+    if (K.o.precision != NS_FP64 && K.o.precision != NS_FP32_INNER) throw Fail{NS_ERR_ARG, "unknown precision"};
+    K.sc.replay = K.o.h_sched;
+    K.sc.replay_len = K.o.sched_len;
+    HIPCHK(hipSetDevice(c->device));
+    auto t0 = std::chrono::steady_clock::now();
+    if (which == 1) ensure_transposed(c, st);
+    K.sy = &c->sys[which];
+    setup_system(c, *K.sy, K.o.precision == NS_FP32_INNER, st);
+    HIPCHK(hipStreamSynchronize(st));
+    auto t1 = std::chrono::steady_clock::now();
+    ns_status rs = K.o.precision == NS_FP32_INNER ? fgmres<float>(K, b, x) : fgmres<double>(K, b, x);
+    HIPCHK(hipStreamSynchronize(st));
+    auto t2 = std::chrono::steady_clock::now();
+    K.stats.setup_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+    K.stats.solve_ms = std::chrono::duration<double, std::milli>(t2 - t1).count();
+    K.stats.n_calls = (int)K.sc.log.size();
+    K.stats.amg_levels_A = K.stats.amg_levels_S = (int)c->sym.lv.size();
+    if (K.o.h_sched_out)
+        for (int i = 0; i < (int)K.sc.log.size() && i < K.o.sched_cap; ++i) K.o.h_sched_out[i] = K.sc.log[i];
+    if (hs) *hs = K.stats;
+    return rs;
+}
+
+template <typename F>
+ns_status guard(ns_ctx* c, F&& f) {
+    try {
+        return f();
+    } catch (const Fail& e) {
+        if (c) c->err = e.msg;
+        return e.st;
+    } catch (const std::exception& e) {
+        if (c) c->err = e.what();
+        return NS_ERR_ARG;
+    }
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+
+extern "C" {
+
+ns_status ns_ctx_create(const ns_mesh* mesh, const ns_ctx_opts* opts, ns_ctx** out, size_t* workspace_bytes) {
+    if (!mesh || !out || !workspace_bytes) {
+        g_create_err = "null argument";
+        return NS_ERR_ARG;
+    }
+    *out = nullptr;
+    ns_ctx* c = new ns_ctx();
+    if (opts) c->opts = *opts;
+    try {
+        std::string e = build_symbolic(mesh, c->opts, c->sym);
+        if (!e.empty()) {
+            g_create_err = e;
+            delete c;
+            return NS_ERR_ARG;
+        }
+        c->h_xyz.assign(mesh->h_xyz, mesh->h_xyz + 3 * (size_t)mesh->n_nodes);
+        c->h_mask.assign(mesh->h_dirichlet, mesh->h_dirichlet + 4 * (size_t)mesh->n_nodes);
+        Arena A;
+        layout(c, A);
+        c->ws_bytes = A.off + 256;
+    } catch (const std::exception& ex) {
+        g_create_err = ex.what();
+        delete c;
+        return NS_ERR_ARG;
+    }
+    *workspace_bytes = c->ws_bytes;
+    *out = c;
+    return NS_OK;
+}
+
+ns_status ns_ctx_bind(ns_ctx* c, void* ws, size_t bytes, hipStream_t st) {
+    if (!c) return NS_ERR_ARG;
+    return guard(c, [&]() -> ns_status {
+        if (!ws || bytes < c->ws_bytes) throw Fail{NS_ERR_WORKSPACE, "workspace missing or too small"};
+        if (reinterpret_cast<uintptr_t>(ws) % 256 != 0) throw Fail{NS_ERR_WORKSPACE, "workspace not 256-byte aligned"};
+        HIPCHK(hipGetDevice(&c->device));
+        Arena A;
+        A.base = static_cast<char*>(ws);
+        layout(c, A);
+        const Symbolic& S = c->sym;
+        h2d(c->d_rp, S.g.rp, st);
+        h2d(c->d_col, S.g.col, st);
+        h2d(c->d_diag, S.diag_pos, st);
+        h2d(c->d_rowof, S.row_of, st);
+        h2d(c->d_tmap, S.tmap, st);
+        h2d(c->d_tets, S.tets, st);
+        h2d(c->d_emap, S.emap, st);
+        h2d(c->d_faces, S.faces, st);
+        h2d(c->d_fmap, S.fmap, st);
+        h2d(c->d_fslot, S.fslot, st);
+        h2d(c->d_face_out, S.face_out, st);
+        h2d(c->d_onode, S.onode, st);
+        h2d(c->d_oid, S.oid, st);
+        h2d(c->d_slot_of, S.slot_of, st);
+        h2d(c->d_optr, S.optr, st);
+        h2d(c->d_srp, S.shat.rp, st);
+        h2d(c->d_scol, S.shat.col, st);
+        h2d(c->d_xyz, c->h_xyz, st);
+        h2d(c->d_mask, c->h_mask, st);
+        for (int l = 1; l < (int)S.lv.size(); ++l) {
+            const AmgLevelSym& ls = S.lv[l];
+            AmgLevelDev& a = c->sys[0].A[l];
+            AmgLevelDev& s = c->sys[0].S[l];
+            h2d(a.rp, ls.a.rp, st);
+            h2d(a.col, ls.a.col, st);
+            h2d(s.rp, ls.s.rp, st);
+            h2d(s.col, ls.s.col, st);
+            h2d(a.gptr, ls.gptr, st);
+            h2d(a.gidx, ls.gidx, st);
+            h2d(a.qrow, ls.a_qrow, st);
+            h2d(s.gptr, ls.sgptr, st);
+            h2d(s.gidx, ls.sgidx, st);
+        }
+        for (int l = 0; l + 1 < (int)S.lv.size(); ++l) {
+            const AmgLevelSym& ls = S.lv[l];
+            AmgLevelDev& a = c->sys[0].A[l];
+            h2d(a.agg, ls.agg, st);
+            h2d(a.aptr, ls.aptr, st);
+            h2d(a.anodes, ls.anodes, st);
+        }
+        fill<uint32_t>(64, 0u, c->d_counter, st);
+        // outlet vectors a^k (geometry only)
+        const int nslot = (int)S.onode.size();
+        fill<double>(std::max(1, 3 * nslot), 0.0, c->d_a_raw, st);
+        for (int fc = 0; fc < S.n_fcolors; ++fc)
+            outlet_vectors(S.fcolor_ptr[fc], S.fcolor_ptr[fc + 1] - S.fcolor_ptr[fc], c->d_faces, c->d_fslot,
+                           c->d_xyz, c->d_a_raw, st);
+        mask_outlet(nslot, c->d_onode, c->d_mask, c->d_a_raw, c->d_a_msk, st);
+        check_launch();
+        if (!c->h_pinned) HIPCHK(hipHostMalloc((void**)&c->h_pinned, 64 * sizeof(double), hipHostMallocDefault));
+        HIPCHK(hipStreamSynchronize(st));
+        c->bound = true;
+        return NS_OK;
+    });
+}
+
+void ns_ctx_destroy(ns_ctx* c) {
+    if (!c) return;
+    if (c->h_pinned) (void)hipHostFree(c->h_pinned);
+    delete c;
+}
+
+const char* ns_last_error(const ns_ctx* c) { return c ? c->err.c_str() : g_create_err.c_str(); }
+
+ns_status ns_outlet_flow(ns_ctx* c, const double* d_v, double* h_Q, hipStream_t st) {
+    if (!c) return NS_ERR_ARG;
+    return guard(c, [&]() -> ns_status {
+        if (!c->bound) throw Fail{NS_ERR_STATE, "context not bound"};
+        const int NO = c->sym.n_out;
+        if (NO == 0) return NS_OK;
+        if (!d_v || !h_Q) throw Fail{NS_ERR_ARG, "null argument"};
+        outlet_dot<double>(NO, c->d_optr, c->d_onode, c->d_a_raw, nullptr, d_v, c->d_s, st);
+        check_launch();
+        HIPCHK(hipMemcpyAsync(h_Q, c->d_s, NO * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        return NS_OK;
+    });
+}
+
+ns_status ns_rank_one_dots(ns_ctx* c, const double* d_xv, double* h_out, hipStream_t st) {
+    if (!c) return NS_ERR_ARG;
+    return guard(c, [&]() -> ns_status {
+        if (!c->bound) throw Fail{NS_ERR_STATE, "context not bound"};
+        const int NO = c->sym.n_out;
+        if (NO == 0) return NS_OK;
+        if (!d_xv || !h_out) throw Fail{NS_ERR_ARG, "null argument"};
+        outlet_dot<double>(NO, c->d_optr, c->d_onode, c->d_a_msk, nullptr, d_xv, c->d_s, st);
+        check_launch();
+        HIPCHK(hipMemcpyAsync(h_out, c->d_s, NO * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        return NS_OK;
+    });
+}
+
+ns_status ns_assemble_tangent(ns_ctx* c, const ns_phys* ph, const double* d_v, const double* d_p,
+                              const double* d_vdot, double* d_rhs, hipStream_t st) {
+    if (!c) return NS_ERR_ARG;
+    return guard(c, [&]() -> ns_status {
+        if (!c->bound) throw Fail{NS_ERR_STATE, "context not bound"};
+        if (!ph || !d_v || !d_p || !d_vdot || !d_rhs) throw Fail{NS_ERR_ARG, "null argument"};
+        const Symbolic& S = c->sym;
+        if (S.n_out > 0 && (!ph->h_m || !ph->h_P_af)) throw Fail{NS_ERR_ARG, "outlet data missing"};
+        if (!(ph->rho > 0) || !(ph->dt > 0) || ph->mu < 0 || ph->rho_inf < 0 || ph->rho_inf > 1)
+            throw Fail{NS_ERR_ARG, "invalid physical parameters"};
+        HIPCHK(hipSetDevice(c->device));
+        const double am = 0.5 * (3.0 - ph->rho_inf) / (1.0 + ph->rho_inf);
+        const double af = 1.0 / (1.0 + ph->rho_inf), gam = af;
+        const double cf = af * gam * ph->dt;
+        const double beta = ph->beta_bf > 0 ? ph->beta_bf : 0.2;
+        const int64_t nnzb = S.g.nnz();
+        fill<double>(nnzb * 16, 0.0, c->d_aos, st);
+        fill<double>(4 * (int64_t)S.N, 0.0, c->d_res, st);
+        AsmArgs a;
+        a.tets = c->d_tets;
+        a.emap = c->d_emap;
+        a.xyz = c->d_xyz;
+        a.v = d_v;
+        a.p = d_p;
+        a.vdot = d_vdot;
+        a.aos = c->d_aos;
+        a.res = c->d_res;
+        a.N = S.N;
+        a.rho = ph->rho;
+        a.mu = ph->mu;
+        a.dt = ph->dt;
+        a.c_m = am;
+        a.c_f = cf;
+        a.c_t = ph->c_t > 0 ? ph->c_t : 4.0;
+        a.c_i = ph->c_i > 0 ? ph->c_i : 36.0;
+        for (int col = 0; col < S.n_colors; ++col) {
+            a.E0 = S.color_ptr[col];
+            a.count = S.color_ptr[col + 1] - S.color_ptr[col];
+            assemble_elements(a, st);
+        }
+        if (S.n_out > 0) {
+            std::vector<double> paf(ph->h_P_af, ph->h_P_af + S.n_out);
+            c->ck_host.resize(S.n_out);
+            for (int k = 0; k < S.n_out; ++k) c->ck_host[k] = cf * ph->h_m[k];
+            h2d(c->d_Paf, paf, st);
+            h2d(c->d_ck, c->ck_host, st);
+            FaceArgs fa;
+            fa.faces = c->d_faces;
+            fa.fmap = c->d_fmap;
+            fa.face_out = c->d_face_out;
+            fa.xyz = c->d_xyz;
+            fa.v = d_v;
+            fa.P_af = c->d_Paf;
+            fa.aos = c->d_aos;
+            fa.res = c->d_res;
+            fa.rho = ph->rho;
+            fa.beta = beta;
+            fa.c_f = cf;
+            for (int fc = 0; fc < S.n_fcolors; ++fc) {
+                fa.F0 = S.fcolor_ptr[fc];
+                fa.count = S.fcolor_ptr[fc + 1] - S.fcolor_ptr[fc];
+                assemble_faces(fa, st);
+            }
+            add_traction((int)S.onode.size(), c->d_onode, c->d_oid, c->d_Paf, c->d_a_raw, c->d_res, st);
+            // the host copies must outlive the asynchronous uploads
+            HIPCHK(hipStreamSynchronize(st));
+        }
+        finalize_tangent(nnzb, c->d_rowof, c->d_col, c->d_mask, c->d_aos, c->sys[0].V64, st);
+        finalize_rhs(S.N, c->d_mask, c->d_res, d_rhs, st);
+        check_launch();
+        c->c_f = cf;
+        c->version++;
+        c->sys[0].ready = c->sys[1].ready = false;
+        c->assembled = true;
+        return NS_OK;
+    });
+}
+
+ns_status ns_nested_solve(ns_ctx* c, const ns_solve_opts* o, const double* d_rhs, double* d_x, ns_stats* hs,
+                          hipStream_t st) {
+    if (!c) return NS_ERR_ARG;
+    return guard(c, [&]() { return run_solve(c, 0, o, d_rhs, d_x, hs, st); });
+}
+
+ns_status ns_adjoint_solve(ns_ctx* c, const ns_solve_opts* o, const double* d_g, double* d_lambda, ns_stats* hs,
+                           hipStream_t st) {
+    if (!c) return NS_ERR_ARG;
+    return guard(c, [&]() { return run_solve(c, 1, o, d_g, d_lambda, hs, st); });
+}
+
+ns_status ns_newton_update(ns_ctx* c, double gamma_dt, const double* d_dx, double* d_y, double* d_ydot,
+                           hipStream_t st) {
+    if (!c) return NS_ERR_ARG;
+    return guard(c, [&]() -> ns_status {
+        if (!c->bound) throw Fail{NS_ERR_STATE, "context not bound"};
+        if (!d_dx || !d_y || !d_ydot) throw Fail{NS_ERR_ARG, "null argument"};
+        newton_update(4 * (int64_t)c->sym.N, gamma_dt, d_dx, d_y, d_ydot, st);
+        check_launch();
+        return NS_OK;
+    });
+}
+
+ns_status ns_query(const ns_ctx* c, int64_t* h) {
+    if (!c || !h) return NS_ERR_ARG;
+    h[0] = c->sym.N;
+    h[1] = c->sym.g.nnz();
+    h[2] = c->sym.shat.nnz();
+    h[3] = c->sym.n_colors;
+    h[4] = (int64_t)c->sym.onode.size();
+    h[5] = (int64_t)c->sym.lv.size();
+    return NS_OK;
+}
+
+ns_status ns_export_pattern(const ns_ctx* c, int32_t* rp, int32_t* col) {
+    if (!c || !rp || !col) return NS_ERR_ARG;
+    std::copy(c->sym.g.rp.begin(), c->sym.g.rp.end(), rp);
+    std::copy(c->sym.g.col.begin(), c->sym.g.col.end(), col);
+    return NS_OK;
+}
+
+ns_status ns_export_aggregates(const ns_ctx* c, int32_t level, int32_t* agg) {
+    if (!c || !agg || level < 0 || level + 1 >= (int)c->sym.lv.size()) return NS_ERR_ARG;
+    std::copy(c->sym.lv[level].agg.begin(), c->sym.lv[level].agg.end(), agg);
+    return NS_OK;
+}
+
+ns_status ns_export_colors(const ns_ctx* c, int32_t* color) {
+    if (!c || !color) return NS_ERR_ARG;
+    std::copy(c->sym.color_of.begin(), c->sym.color_of.end(), color);
+    return NS_OK;
+}
+
+ns_status ns_export_bsr(ns_ctx* c, int32_t transposed, double* d_dst, hipStream_t st) {
+    if (!c) return NS_ERR_ARG;
+    return guard(c, [&]() -> ns_status {
+        if (!c->assembled) throw Fail{NS_ERR_STATE, "no tangent assembled"};
+        if (!d_dst) throw Fail{NS_ERR_ARG, "null argument"};
+        if (transposed) ensure_transposed(c, st);
+        export_aos(c->sym.g.nnz(), c->sys[transposed ? 1 : 0].V64, d_dst, st);
+        check_launch();
+        HIPCHK(hipStreamSynchronize(st));
+        return NS_OK;
+    });
+}
+
+ns_status ns_export_shat(ns_ctx* c, int32_t* rp, int32_t* col, double* d_val, hipStream_t st) {
+    if (!c) return NS_ERR_ARG;
+    return guard(c, [&]() -> ns_status {
+        if (!c->assembled) throw Fail{NS_ERR_STATE, "no tangent assembled"};
+        if (rp) std::copy(c->sym.shat.rp.begin(), c->sym.shat.rp.end(), rp);
+        if (col) std::copy(c->sym.shat.col.begin(), c->sym.shat.col.end(), col);
+        if (d_val) {
+            setup_system(c, c->sys[0], false, st);
+            HIPCHK(hipMemcpyAsync(d_val, c->sys[0].shat64, c->sym.shat.nnz() * sizeof(double),
+                                  hipMemcpyDeviceToDevice, st));
+        }
+        HIPCHK(hipStreamSynchronize(st));
+        return NS_OK;
+    });
+}
+
+ns_status ns_export_outlet_vectors(ns_ctx* c, double* d_a, hipStream_t st) {
+    if (!c) return NS_ERR_ARG;
+    return guard(c, [&]() -> ns_status {
+        if (!c->bound) throw Fail{NS_ERR_STATE, "context not bound"};
+        const int N = c->sym.N;
+        for (int k = 0; k < c->sym.n_out; ++k) {
+            fill<double>(3 * (int64_t)N, 0.0, d_a + 3 * (int64_t)N * k, st);
+        }
+        // scatter slots into dense vectors (host loop over slots; tiny)
+        std::vector<double> a(3 * c->sym.onode.size());
+        if (!a.empty())
+            HIPCHK(hipMemcpyAsync(a.data(), c->d_a_msk, a.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        for (size_t sl = 0; sl < c->sym.onode.size(); ++sl) {
+            const int k = c->sym.oid[sl];
+            HIPCHK(hipMemcpyAsync(d_a + 3 * (int64_t)N * k + 3 * (int64_t)c->sym.onode[sl], &a[3 * sl],
+                                  3 * sizeof(double), hipMemcpyHostToDevice, st));
+        }
+        HIPCHK(hipStreamSynchronize(st));
+        return NS_OK;
+    });
+}
+
+ns_status ns_apply(ns_ctx* c, int32_t op, const ns_solve_opts* opts, const double* d_x, double* d_y,
+                   hipStream_t st) {
+    if (!c) return NS_ERR_ARG;
+    return guard(c, [&]() -> ns_status {
+        if (!c->assembled) throw Fail{NS_ERR_STATE, "no tangent assembled"};
+        if (!d_x || !d_y) throw Fail{NS_ERR_ARG, "null argument"};
+        HIPCHK(hipSetDevice(c->device));
+        Ctl K{};
+        K.c = c;
+        K.st = st;
+        if (opts) K.o = *opts;
+        K.o.atol = K.o.atol > 0 ? K.o.atol : 1e-50;
+        K.sc.replay = K.o.h_sched;
+        K.sc.replay_len = K.o.sched_len;
+        K.sy = &c->sys[0];
+        const bool f32 = K.o.precision == NS_FP32_INNER;
+        setup_system(c, c->sys[0], f32, st);
+        const int N = c->sym.N;
+        const int64_t nin[] = {4L * N, 3L * N, N, 3L * N, N, N, 3L * N, N, N, 4L * N, 3L * N};
+        const int64_t nout[] = {4L * N, 3L * N, 3L * N, N, N, N, 3L * N, N, N, 4L * N, 3L * N};
+        if (op < 0 || op > NS_OP_SOLVE_A) throw Fail{NS_ERR_ARG, "unknown operator"};
+        auto run = [&](auto tag) {
+            using T = decltype(tag);
+            Nested<T> P(K);
+            const T* x;
+            T* y;
+            if (std::is_same<T, double>::value) {
+                x = reinterpret_cast<const T*>(d_x);
+                y = reinterpret_cast<T*>(d_y);
+            } else {
+                convert<double, T>(nin[op], d_x, as<T>(c->t_s), st);
+                x = as<T>(c->t_s);
+                y = as<T>(c->t_r4);
+            }
+            switch (op) {
+                case NS_OP_FULL: {
+                    RankOne<T> r = P.rank_one();
+                    if (r.slot_of)
+                        outlet_dot<T>(c->sym.n_out, c->d_optr, c->d_onode, Typed<T>::amsk(c), Typed<T>::ck(c), x,
+                                      as<T>(c->d_s), st);
+                    spmv_full<T>(N, c->d_rp, c->d_col, P.V(), c->sym.g.nnz(), x, y, T(1), nullptr, T(0),
+                                 r.slot_of ? &r : nullptr, st);
+                    break;
+                }
+                case NS_OP_A: P.applyA(x, y); break;
+                case NS_OP_B: spmv<T>(3, 1, P.op(0, 3), x, y, T(1), nullptr, T(0), nullptr, nullptr, st); break;
+                case NS_OP_C: spmv<T>(1, 3, P.op(3, 0), x, y, T(1), nullptr, T(0), nullptr, nullptr, st); break;
+                case NS_OP_D: spmv<T>(1, 1, P.op(3, 3), x, y, T(1), nullptr, T(0), nullptr, nullptr, st); break;
+                case NS_OP_SHAT: {
+                    BlockOp<T> M = P.level_op(c->sys[0].S[0]);
+                    spmv<T>(1, 1, M, x, y, T(1), nullptr, T(0), nullptr, nullptr, st);
+                    break;
+                }
+                case NS_OP_VCYCLE_A: P.vcycle(c->sys[0].A, 0, x, y); break;
+                case NS_OP_VCYCLE_S: P.vcycle(c->sys[0].S, 0, x, y); break;
+                case NS_OP_SCHUR: P.schur(x, y); break;
+                case NS_OP_PSCR: P.scr(x, y); break;
+                case NS_OP_SOLVE_A: P.solveA(x, y, dfltd(K.o.rtol_A, 1e-3)); break;
+            }
+            if (!std::is_same<T, double>::value) convert<T, double>(nout[op], y, d_y, st);
+        };
+        if (f32) run(float{});
+        else run(double{});
+        check_launch();
+        HIPCHK(hipStreamSynchronize(st));
+        if (K.o.h_sched_out)
+            for (int i = 0; i < (int)K.sc.log.size() && i < K.o.sched_cap; ++i) K.o.h_sched_out[i] = K.sc.log[i];
+        return NS_OK;
+    });
+}
+
+}  // extern "C"

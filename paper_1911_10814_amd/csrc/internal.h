@@ -1,0 +1,181 @@
+// Internal declarations of the nested block solver library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "ns_api.h"
+
+namespace ns {
+
+// ---------------------------------------------------------------------------
+// Host-side symbolic structures (built once per mesh in ns_ctx_create)
+// ---------------------------------------------------------------------------
+
+struct Csr {
+    int n = 0;
+    std::vector<int32_t> rp, col;  // sorted columns, diagonal included
+    int64_t nnz() const { return (int64_t)col.size(); }
+};
+
+struct AmgLevelSym {
+    int n = 0;            // nodes at this level
+    Csr a;                // pattern of the A-hierarchy operator (3x3 blocks)
+    Csr s;                // pattern of the S_hat-hierarchy operator (scalars)
+    std::vector<int32_t> a_qrow;  // row of every nnz of `a` (levels >= 1)
+    // aggregation to the next level (empty on the coarsest level)
+    std::vector<int32_t> agg;            // node -> coarse node
+    std::vector<int32_t> aptr, anodes;   // coarse node -> its fine nodes (CSR)
+    // Galerkin gather lists of THIS level's operators from the finer level:
+    // coarse nnz q sums fine nnz gidx[gptr[q] .. gptr[q+1])
+    std::vector<int32_t> gptr, gidx;     // A hierarchy
+    std::vector<int32_t> sgptr, sgidx;   // S_hat hierarchy
+};
+
+struct Symbolic {
+    int N = 0, E = 0, n_out = 0, F = 0;
+    Csr g;                               // node graph = BSR pattern
+    std::vector<int32_t> diag_pos;       // [N]
+    std::vector<int32_t> row_of;         // [nnzb]
+    std::vector<int32_t> tmap;           // [nnzb] index of the transposed block
+    // elements sorted by colour
+    int n_colors = 0;
+    std::vector<int32_t> color_ptr;      // [n_colors+1]
+    std::vector<int32_t> elem_perm;      // sorted position -> original element
+    std::vector<int32_t> tets;           // [E][4] in sorted order
+    std::vector<int32_t> emap;           // [E][16] block index of pair (a,b) = a*4+b
+    std::vector<int32_t> color_of;       // [E] colour of each original element
+    // outlets
+    std::vector<int32_t> onode;          // [n_onodes] node of each outlet slot
+    std::vector<int32_t> oid;            // [n_onodes] outlet of each slot
+    std::vector<int32_t> optr;           // [n_out+1] slot ranges per outlet
+    std::vector<int32_t> slot_of;        // [N] slot of node or -1
+    int n_fcolors = 0;
+    std::vector<int32_t> fcolor_ptr;
+    std::vector<int32_t> faces;          // [F][3] sorted by colour
+    std::vector<int32_t> face_out;       // [F] outlet of each face
+    std::vector<int32_t> fmap;           // [F][9] block index of pair (a,b) = a*3+b
+    std::vector<int32_t> fslot;          // [F][3] slot of each face node
+    // S_hat pattern (distance-2 node graph)
+    Csr shat;
+    // AMG hierarchy (level 0 = fine)
+    std::vector<AmgLevelSym> lv;
+};
+
+std::string build_symbolic(const ns_mesh* mesh, const ns_ctx_opts& o, Symbolic& S);
+
+// ---------------------------------------------------------------------------
+// Device buffers
+// ---------------------------------------------------------------------------
+
+struct Arena {
+    char* base = nullptr;
+    size_t off = 0;
+    template <typename T>
+    T* take(size_t count) {
+        off = (off + 255) & ~size_t(255);
+        T* p = reinterpret_cast<T*>(base + off);
+        off += count * sizeof(T);
+        return base ? p : nullptr;
+    }
+};
+
+struct AmgLevelDev {
+    int n = 0, bs = 0;
+    // pattern (device)
+    int32_t *rp = nullptr, *col = nullptr;
+    int64_t nnz = 0;
+    // numeric values: planes [bs*bs][nnz] (level 0 of the A hierarchy points
+    // into the tangent storage instead)
+    double* v64 = nullptr;
+    float* v32 = nullptr;
+    int64_t rstride = 0, cstride = 0;   // plane strides between block rows / columns
+    double* dinv64 = nullptr;
+    float* dinv32 = nullptr;
+    const double* dextra64 = nullptr;   // extra diagonal (level 0 of A: lumped diag K)
+    const float* dextra32 = nullptr;
+    double lmax = 0.0;
+    // Galerkin gather lists from the finer level (levels >= 1)
+    int32_t *gptr = nullptr, *gidx = nullptr, *qrow = nullptr;
+    // restriction/prolongation to the next level
+    int32_t *agg = nullptr, *aptr = nullptr, *anodes = nullptr;
+    // work vectors (sized for FP64, reused for FP32): x0, x1, d, r, b
+    double *x0 = nullptr, *x1 = nullptr, *d = nullptr, *r = nullptr, *b = nullptr;
+    // coarsest level: dense inverse [n*bs][n*bs] FP64 and its work matrix
+    double* inv = nullptr;
+    double* work = nullptr;
+};
+
+struct SystemDev {
+    // tangent in SoA planes [16][nnzb] (plane 4r+c; r,c = u,v,w,p)
+    double* V64 = nullptr;
+    float* V32 = nullptr;
+    double *dK64 = nullptr, *diagA64 = nullptr, *dinvA64 = nullptr;  // [3N]
+    float *dK32 = nullptr, *dinvA32 = nullptr;
+    double* shat64 = nullptr;  // [nnz S_hat]
+    float* shat32 = nullptr;
+    std::vector<AmgLevelDev> A, S;   // hierarchies
+    bool ready = false;              // per-step set-up done for the current tangent
+    bool have32 = false;
+    uint64_t version = 0;            // tangent version the set-up belongs to
+};
+
+struct KrylovWs {
+    int m = 0;
+    int64_t n = 0;
+    double* V = nullptr;    // [(m+1)][n] (FP64 size; reused as FP32)
+    double* Z = nullptr;    // [m][n] (outer level only)
+    double* tmp = nullptr;  // [n]
+    double* H = nullptr;    // [(m+1)*m] column-major, leading dim m+1
+    double* cs = nullptr;
+    double* sn = nullptr;
+    double* g = nullptr;    // [m+1]
+    double* y = nullptr;    // [m]
+    double* h = nullptr;    // [2][m+2] dot results of the two CGS passes (FP64 or FP32)
+    double* status = nullptr;  // [4]: |g_{j+1}|, breakdown flag, 1/h_{j+1,j}, ||w_pre||
+};
+
+}  // namespace ns
+
+struct ns_ctx {
+    ns::Symbolic sym;
+    ns_ctx_opts opts{};
+    std::string err;
+    size_t ws_bytes = 0;
+    bool bound = false;
+    int device = -1;
+    // device copies of the symbolic data
+    int32_t *d_rp = nullptr, *d_col = nullptr, *d_diag = nullptr, *d_rowof = nullptr, *d_tmap = nullptr;
+    int32_t *d_tets = nullptr, *d_emap = nullptr;
+    int32_t *d_faces = nullptr, *d_fmap = nullptr, *d_fslot = nullptr, *d_face_out = nullptr;
+    int32_t *d_onode = nullptr, *d_oid = nullptr, *d_slot_of = nullptr, *d_optr = nullptr;
+    double* d_Paf = nullptr;     // [n_out] outlet pressures of the last assembly
+    int32_t *d_srp = nullptr, *d_scol = nullptr;
+    uint8_t* d_mask = nullptr;
+    double* d_xyz = nullptr;
+    double* d_a_raw = nullptr;   // [n_onodes][3] a^k (Dirichlet entries kept)
+    double* d_a_msk = nullptr;   // [n_onodes][3] a^k with Dirichlet entries zeroed
+    float* d_a_msk32 = nullptr;
+    double* d_aos = nullptr;     // [nnzb][16] assembly accumulator
+    double* d_res = nullptr;     // [4N] residual accumulator
+    double* d_ck = nullptr;      // [n_out] rank-one weights c_k = alpha_f gamma dt m^k
+    float* d_ck32 = nullptr;
+    double* d_s = nullptr;       // [n_out] rank-one dot results
+    double* d_red = nullptr;     // reduction partials
+    uint32_t* d_counter = nullptr;
+    ns::SystemDev sys[2];        // 0: forward, 1: transposed
+    ns::KrylovWs kw_out, kw_A, kw_S;
+    // P_SCR / Algorithm 2 temporaries (FP64-sized)
+    double *t_s = nullptr, *t_yhat = nullptr, *t_tp = nullptr, *t_yp = nullptr, *t_tv = nullptr,
+           *t_yv = nullptr, *t_xhat = nullptr, *t_xbar = nullptr, *t_xt = nullptr, *t_r4 = nullptr;
+    double* h_pinned = nullptr;  // pinned host scalars
+    std::vector<double> h_xyz;   // host copies uploaded by ns_ctx_bind
+    std::vector<uint8_t> h_mask;
+    uint64_t version = 0;        // incremented by every assembly
+    bool assembled = false;
+    double c_f = 0.0;            // alpha_f gamma dt of the last assembly
+    std::vector<double> ck_host;
+};

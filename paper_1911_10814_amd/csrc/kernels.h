@@ -1,0 +1,155 @@
+// Launch wrappers of the HIP kernels (internal).
+#pragma once
+
+#include "internal.h"
+
+namespace ns {
+
+constexpr int kBlock = 256;
+constexpr int kMaxRedBlocks = 1024;
+
+// Rank-one epilogue of the A-operator: y_i += s_k a^k_i for outlet slots.
+template <typename T>
+struct RankOne {
+    const int32_t* slot_of = nullptr;  // [N] slot of node or -1
+    const int32_t* oid = nullptr;      // [slots] outlet of slot
+    const T* aval = nullptr;           // [slots][3]
+    const T* s = nullptr;              // [n_out] c_k (a^k . x)
+};
+
+// Block-sparse operator: rows of BR, columns of BC unknowns; value of block k
+// at (r, c) is v[r*rs + c*cs + k].
+template <typename T>
+struct BlockOp {
+    int n = 0;
+    const int32_t* rp = nullptr;
+    const int32_t* col = nullptr;
+    const T* v = nullptr;
+    int64_t rs = 0, cs = 0;
+    const T* dextra = nullptr;  // optional extra diagonal [BR*n]
+};
+
+// y = alpha * (M x [+ dextra x] [+ rank one]) + beta * z, then y *= rscale
+template <typename T>
+void spmv(int br, int bc, const BlockOp<T>& M, const T* x, T* y, T alpha, const T* z, T beta,
+          const T* rscale, const RankOne<T>* ro, hipStream_t st);
+
+// Full 4x4 field-split operator: y = alpha [A B; C D] x + beta z.
+template <typename T>
+void spmv_full(int n, const int32_t* rp, const int32_t* col, const T* V, int64_t nnzb, const T* x, T* y,
+               T alpha, const T* z, T beta, const RankOne<T>* ro, hipStream_t st);
+
+// s[k] = c[k] * sum_{slots of k} a . x
+template <typename T>
+void outlet_dot(int n_out, const int32_t* optr, const int32_t* onode, const T* aval, const T* c, const T* x,
+                T* s, hipStream_t st);
+
+template <typename T>
+void axpby(int64_t n, T a, const T* x, T b, const T* y, T* out, hipStream_t st);  // out = a x + b y
+template <typename Tin, typename Tout>
+void convert(int64_t n, const Tin* x, Tout* y, hipStream_t st);
+template <typename T>
+void fill(int64_t n, T val, T* y, hipStream_t st);
+template <typename T>
+void mul(int64_t n, const T* a, const T* x, T* y, hipStream_t st);  // y = a .* x
+
+// Arnoldi step support.  Dot results go to `h` (FP64), reductions use the
+// partial buffer `red` and `counter` (last block finalises).
+template <typename T>
+void multidot(int64_t n, int k, const T* V, int64_t ldv, const T* w, bool with_self, double* h, double* red,
+              uint32_t* counter, hipStream_t st);
+struct GivensArgs {
+    int j = 0, ldh = 0;
+    const double* h1 = nullptr;  // [j+2] pass-1 dots (h1[j+1] = ||w_pre||^2)
+    const double* h2 = nullptr;  // [j+1] pass-2 dots
+    double *H = nullptr, *cs = nullptr, *sn = nullptr, *g = nullptr, *status = nullptr;
+};
+// w -= V h; if givens != nullptr also ||w||^2 and the Givens update (last block)
+template <typename T>
+void orth_update(int64_t n, int k, const T* V, int64_t ldv, const double* h, T* w, const GivensArgs* givens,
+                 double* red, uint32_t* counter, hipStream_t st);
+template <typename T>
+void scale_by_status(int64_t n, T* w, const double* status, hipStream_t st);  // w *= status[2]
+void backsolve(int k, int ldh, const double* H, const double* g, double* y, hipStream_t st);
+void init_g(double* g, int len, double beta, hipStream_t st);  // g = [beta, 0, ...]
+// x = (accumulate ? x : 0) + sum_i V_i y_i
+template <typename T, typename TX>
+void combine(int64_t n, int k, const T* V, int64_t ldv, const double* y, TX* x, bool accumulate,
+             hipStream_t st);
+template <typename T>
+void norm2(int64_t n, const T* x, double* out, double* red, uint32_t* counter, hipStream_t st);
+template <typename T>
+void scale_by(int64_t n, const T* x, const double* s, bool inverse, T* y, hipStream_t st);
+
+// AMG kernels
+template <typename T>
+void cheb_first(int64_t n, const T* b, const T* dinv, T c2, T* x, T* d, hipStream_t st);
+template <typename T>
+void cheb_step(int bs, const BlockOp<T>& M, const T* xin, T* xout, T* d, const T* b, const T* dinv, T c1, T c2,
+               hipStream_t st);
+template <typename T>
+void restrict_agg(int nc, int bs, const int32_t* aptr, const int32_t* anodes, const T* r, T* bc, hipStream_t st);
+template <typename T>
+void prolong_add(int n, int bs, const int32_t* agg, const T* ec, T* x, hipStream_t st);
+template <typename T>
+void dense_gemv(int n, const double* Minv, const T* b, T* x, hipStream_t st);
+
+// Set-up kernels (FP64)
+void galerkin(int64_t nq, int np_r, int np_c, const int32_t* gptr, const int32_t* gidx, const double* vf,
+              int64_t frs, int64_t fcs, double* vc, int64_t crs, int64_t ccs, const int32_t* qrow,
+              const int32_t* ccol, const double* dextra, const int32_t* aptr, const int32_t* anodes,
+              hipStream_t st);
+void block_dinv(int n, int bs, const int32_t* rp, const int32_t* col, const double* v, int64_t rs, int64_t cs,
+                const double* dextra, double* dinv, double* diag, hipStream_t st);
+void shat_numeric(int n, const int32_t* rp, const int32_t* col, const double* V, int64_t nnzb,
+                  const double* dinvA, const int32_t* srp, const int32_t* scol, double* shat, hipStream_t st);
+void gauss_jordan_inverse(int n, double* work, double* inv, hipStream_t st);
+void dense_from_csr(int nb, int bs, const int32_t* rp, const int32_t* col, const double* v, int64_t rs,
+                    int64_t cs, const double* dextra, double* work, hipStream_t st);
+void power_start(int64_t n, double* x, hipStream_t st);
+void rank_one_diag(int n_slots, const int32_t* onode, const int32_t* oid, const double* amsk, const double* ck,
+                   double* dK, hipStream_t st);
+void transpose_values(int64_t nnzb, const int32_t* tmap, const double* V, double* Vt, hipStream_t st);
+void export_aos(int64_t nnzb, const double* V, double* dst, hipStream_t st);
+
+// Assembly
+struct AsmArgs {
+    int E0 = 0, count = 0;            // element range of one colour
+    const int32_t* tets = nullptr;    // [E][4] (sorted by colour)
+    const int32_t* emap = nullptr;    // [E][16]
+    const double* xyz = nullptr;
+    const double* v = nullptr;
+    const double* p = nullptr;
+    const double* vdot = nullptr;
+    double* aos = nullptr;            // [nnzb][16]
+    double* res = nullptr;            // [4N]
+    int N = 0;
+    double rho = 0, mu = 0, dt = 0, c_m = 0, c_f = 0, c_t = 0, c_i = 0;
+};
+void assemble_elements(const AsmArgs& a, hipStream_t st);
+struct FaceArgs {
+    int F0 = 0, count = 0;
+    const int32_t* faces = nullptr;   // [F][3]
+    const int32_t* fmap = nullptr;    // [F][9]
+    const int32_t* face_out = nullptr;
+    const double* xyz = nullptr;
+    const double* v = nullptr;
+    const double* P_af = nullptr;     // [n_out] device
+    double* aos = nullptr;
+    double* res = nullptr;
+    double rho = 0, beta = 0, c_f = 0;
+};
+void assemble_faces(const FaceArgs& a, hipStream_t st);
+void outlet_vectors(int F0, int count, const int32_t* faces, const int32_t* fslot, const double* xyz,
+                    double* a_raw, hipStream_t st);
+void mask_outlet(int n_slots, const int32_t* onode, const uint8_t* mask, const double* a_raw, double* a_msk,
+                 hipStream_t st);
+void finalize_tangent(int64_t nnzb, const int32_t* row_of, const int32_t* col, const uint8_t* mask,
+                      const double* aos, double* V, hipStream_t st);
+void finalize_rhs(int N, const uint8_t* mask, const double* res, double* rhs, hipStream_t st);
+// res[3 node + c] += P_af[outlet] a^k_{node,c}  (traction term of the outlets)
+void add_traction(int n_slots, const int32_t* onode, const int32_t* oid, const double* P_af, const double* a_raw,
+                  double* res, hipStream_t st);
+void newton_update(int64_t n, double gdt, const double* dx, double* y, double* ydot, hipStream_t st);
+
+}  // namespace ns

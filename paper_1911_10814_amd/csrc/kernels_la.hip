@@ -1,0 +1,876 @@
+// Bandwidth-bound linear-algebra kernels for gfx950 (64-lane wavefronts):
+// block-sparse SpMV family, rank-one outlet terms, CGS2 pieces with the
+// Hessenberg/Givens update on the device, Chebyshev/aggregation V-cycle
+// pieces, and the per-step set-up numerics.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "kernels.h"
+
+namespace ns {
+
+namespace {
+
+inline unsigned grid_for(int64_t threads) { return (unsigned)((threads + kBlock - 1) / kBlock); }
+
+inline unsigned red_grid(int64_t n) {
+    int64_t g = (n + kBlock * 4 - 1) / (kBlock * 4);
+    if (g < 1) g = 1;
+    if (g > kMaxRedBlocks) g = kMaxRedBlocks;
+    return (unsigned)g;
+}
+
+template <typename T>
+__device__ inline T wave_sum(T v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Sum over the block (256 threads = 4 waves); result valid in thread 0.
+template <typename T>
+__device__ inline T block_sum(T v, T* lds) {
+    v = wave_sum(v);
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    if (l == 0) lds[w] = v;
+    __syncthreads();
+    T r = 0;
+    if (threadIdx.x == 0) r = lds[0] + lds[1] + lds[2] + lds[3];
+    __syncthreads();
+    return r;
+}
+
+// Returns true in the block that finishes last (after all partials are visible).
+__device__ inline bool last_block(uint32_t* counter, unsigned total) {
+    __shared__ bool is_last;
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned prev = atomicAdd(counter, 1u);
+        is_last = (prev == total - 1);
+    }
+    __syncthreads();
+    if (is_last) __threadfence();
+    return is_last;
+}
+
+__device__ inline int lower_bound_dev(const int32_t* a, int lo, int hi, int key) {
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (a[mid] < key) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// SpMV: W lanes per block row, lanes stride over the row's blocks (consecutive
+// lanes read consecutive blocks of every value plane: coalesced), x gathered
+// through L2, butterfly reduction of the BR partial sums inside the group.
+// ---------------------------------------------------------------------------
+
+template <typename T, int BR, int BC, int W>
+__global__ __launch_bounds__(kBlock) void k_spmv(BlockOp<T> M, const T* __restrict__ x, T* __restrict__ y, T alpha,
+                                                 const T* __restrict__ z, T beta, const T* __restrict__ rscale,
+                                                 RankOne<T> ro) {
+    const int64_t tid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int row = (int)(tid / W);
+    const int lane = threadIdx.x % W;
+    const bool valid = row < M.n;
+    T acc[BR];
+#pragma unroll
+    for (int r = 0; r < BR; ++r) acc[r] = 0;
+    if (valid) {
+        const int k1 = M.rp[row + 1];
+        for (int k = M.rp[row] + lane; k < k1; k += W) {
+            const int j = M.col[k];
+            T xj[BC];
+#pragma unroll
+            for (int c = 0; c < BC; ++c) xj[c] = x[(int64_t)BC * j + c];
+#pragma unroll
+            for (int r = 0; r < BR; ++r)
+#pragma unroll
+                for (int c = 0; c < BC; ++c) acc[r] += M.v[r * M.rs + c * M.cs + k] * xj[c];
+        }
+    }
+#pragma unroll
+    for (int off = W / 2; off > 0; off >>= 1)
+#pragma unroll
+        for (int r = 0; r < BR; ++r) acc[r] += __shfl_xor(acc[r], off, W);
+    if (!valid || lane >= BR) return;
+    T s = acc[0];
+#pragma unroll
+    for (int r = 1; r < BR; ++r)
+        if (lane == r) s = acc[r];
+    const int64_t i = (int64_t)BR * row + lane;
+    if (M.dextra) s += M.dextra[i] * x[i];
+    if (ro.slot_of) {
+        const int sl = ro.slot_of[row];
+        if (sl >= 0) s += ro.s[ro.oid[sl]] * ro.aval[3 * (int64_t)sl + lane];
+    }
+    T out = alpha * s;
+    if (z) out += beta * z[i];
+    if (rscale) out *= rscale[i];
+    y[i] = out;
+}
+
+template <typename T>
+void spmv(int br, int bc, const BlockOp<T>& M, const T* x, T* y, T alpha, const T* z, T beta, const T* rscale,
+          const RankOne<T>* ro, hipStream_t st) {
+    RankOne<T> r1 = ro ? *ro : RankOne<T>{};
+    if (M.n <= 0) return;
+    if (br == 3 && bc == 3) {
+        hipLaunchKernelGGL((k_spmv<T, 3, 3, 8>), dim3(grid_for((int64_t)M.n * 8)), dim3(kBlock), 0, st, M, x, y,
+                           alpha, z, beta, rscale, r1);
+    } else if (br == 3 && bc == 1) {
+        hipLaunchKernelGGL((k_spmv<T, 3, 1, 8>), dim3(grid_for((int64_t)M.n * 8)), dim3(kBlock), 0, st, M, x, y,
+                           alpha, z, beta, rscale, r1);
+    } else if (br == 1 && bc == 3) {
+        hipLaunchKernelGGL((k_spmv<T, 1, 3, 8>), dim3(grid_for((int64_t)M.n * 8)), dim3(kBlock), 0, st, M, x, y,
+                           alpha, z, beta, rscale, r1);
+    } else {
+        hipLaunchKernelGGL((k_spmv<T, 1, 1, 16>), dim3(grid_for((int64_t)M.n * 16)), dim3(kBlock), 0, st, M, x, y,
+                           alpha, z, beta, rscale, r1);
+    }
+}
+
+// Full field-split 4x4 operator (outer Arnoldi and true residual).
+template <typename T, int W>
+__global__ __launch_bounds__(kBlock) void k_spmv_full(int n, const int32_t* __restrict__ rp,
+                                                      const int32_t* __restrict__ col, const T* __restrict__ V,
+                                                      int64_t nnzb, const T* __restrict__ x, T* __restrict__ y,
+                                                      T alpha, const T* __restrict__ z, T beta, RankOne<T> ro) {
+    const int64_t tid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int row = (int)(tid / W);
+    const int lane = threadIdx.x % W;
+    const bool valid = row < n;
+    const T* xp = x + 3 * (int64_t)n;
+    T acc[4] = {0, 0, 0, 0};
+    if (valid) {
+        const int k1 = rp[row + 1];
+        for (int k = rp[row] + lane; k < k1; k += W) {
+            const int j = col[k];
+            T xj[4] = {x[3 * (int64_t)j], x[3 * (int64_t)j + 1], x[3 * (int64_t)j + 2], xp[j]};
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) acc[r] += V[(4 * r + c) * nnzb + k] * xj[c];
+        }
+    }
+#pragma unroll
+    for (int off = W / 2; off > 0; off >>= 1)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[r] += __shfl_xor(acc[r], off, W);
+    if (!valid || lane >= 4) return;
+    T s = acc[0];
+    if (lane == 1) s = acc[1];
+    if (lane == 2) s = acc[2];
+    if (lane == 3) s = acc[3];
+    const int64_t i = lane < 3 ? 3 * (int64_t)row + lane : 3 * (int64_t)n + row;
+    if (lane < 3 && ro.slot_of) {
+        const int sl = ro.slot_of[row];
+        if (sl >= 0) s += ro.s[ro.oid[sl]] * ro.aval[3 * (int64_t)sl + lane];
+    }
+    T out = alpha * s;
+    if (z) out += beta * z[i];
+    y[i] = out;
+}
+
+template <typename T>
+void spmv_full(int n, const int32_t* rp, const int32_t* col, const T* V, int64_t nnzb, const T* x, T* y, T alpha,
+               const T* z, T beta, const RankOne<T>* ro, hipStream_t st) {
+    RankOne<T> r1 = ro ? *ro : RankOne<T>{};
+    hipLaunchKernelGGL((k_spmv_full<T, 8>), dim3(grid_for((int64_t)n * 8)), dim3(kBlock), 0, st, n, rp, col, V,
+                       nnzb, x, y, alpha, z, beta, r1);
+}
+
+// s[k] = c[k] * sum over outlet k's slots of a . x   (one block per outlet)
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_outlet_dot(const int32_t* optr, const int32_t* onode, const T* aval,
+                                                       const T* c, const T* x, T* s) {
+    __shared__ T lds[4];
+    const int k = blockIdx.x;
+    T acc = 0;
+    for (int sl = optr[k] + threadIdx.x; sl < optr[k + 1]; sl += kBlock) {
+        const int64_t nd = onode[sl];
+        acc += aval[3 * (int64_t)sl] * x[3 * nd] + aval[3 * (int64_t)sl + 1] * x[3 * nd + 1] +
+               aval[3 * (int64_t)sl + 2] * x[3 * nd + 2];
+    }
+    T tot = block_sum(acc, lds);
+    if (threadIdx.x == 0) s[k] = (c ? c[k] : T(1)) * tot;
+}
+
+template <typename T>
+void outlet_dot(int n_out, const int32_t* optr, const int32_t* onode, const T* aval, const T* c, const T* x, T* s,
+                hipStream_t st) {
+    if (n_out <= 0) return;
+    hipLaunchKernelGGL((k_outlet_dot<T>), dim3(n_out), dim3(kBlock), 0, st, optr, onode, aval, c, x, s);
+}
+
+// ---------------------------------------------------------------------------
+// BLAS-1
+// ---------------------------------------------------------------------------
+
+template <typename T>
+__global__ void k_axpby(int64_t n, T a, const T* x, T b, const T* y, T* out) {
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
+        out[i] = a * x[i] + (y ? b * y[i] : T(0));
+}
+template <typename T>
+void axpby(int64_t n, T a, const T* x, T b, const T* y, T* out, hipStream_t st) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL((k_axpby<T>), dim3(std::min<int64_t>(grid_for(n), 65535)), dim3(kBlock), 0, st, n, a, x, b,
+                       y, out);
+}
+
+template <typename Tin, typename Tout>
+__global__ void k_convert(int64_t n, const Tin* x, Tout* y) {
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
+        y[i] = (Tout)x[i];
+}
+template <typename Tin, typename Tout>
+void convert(int64_t n, const Tin* x, Tout* y, hipStream_t st) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL((k_convert<Tin, Tout>), dim3(std::min<int64_t>(grid_for(n), 65535)), dim3(kBlock), 0, st, n,
+                       x, y);
+}
+
+template <typename T>
+__global__ void k_fill(int64_t n, T v, T* y) {
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) y[i] = v;
+}
+template <typename T>
+void fill(int64_t n, T val, T* y, hipStream_t st) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL((k_fill<T>), dim3(std::min<int64_t>(grid_for(n), 65535)), dim3(kBlock), 0, st, n, val, y);
+}
+
+template <typename T>
+__global__ void k_mul(int64_t n, const T* a, const T* x, T* y) {
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
+        y[i] = a[i] * x[i];
+}
+template <typename T>
+void mul(int64_t n, const T* a, const T* x, T* y, hipStream_t st) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL((k_mul<T>), dim3(std::min<int64_t>(grid_for(n), 65535)), dim3(kBlock), 0, st, n, a, x, y);
+}
+
+// ---------------------------------------------------------------------------
+// CGS2 pieces.  multidot: h_i = V_i . w for i < k (+ w . w), 8 vectors per
+// blockIdx.y, grid-stride over blockIdx.x; partials [k+1][gx] reduced in a
+// fixed order by the last block (deterministic).
+// ---------------------------------------------------------------------------
+
+constexpr int kDotGroup = 8;
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_multidot(int64_t n, int k, const T* __restrict__ V, int64_t ldv,
+                                                     const T* __restrict__ w, int with_self, double* h, T* red,
+                                                     uint32_t* counter) {
+    __shared__ T lds[4];
+    const int nv = k + with_self;
+    const int i0 = blockIdx.y * kDotGroup;
+    T acc[kDotGroup];
+#pragma unroll
+    for (int q = 0; q < kDotGroup; ++q) acc[q] = 0;
+    for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < n; t += (int64_t)gridDim.x * kBlock) {
+        const T wt = w[t];
+#pragma unroll
+        for (int q = 0; q < kDotGroup; ++q) {
+            const int i = i0 + q;
+            if (i < k) acc[q] += V[i * ldv + t] * wt;
+            else if (i == k && with_self) acc[q] += wt * wt;
+        }
+    }
+    for (int q = 0; q < kDotGroup; ++q) {
+        const int i = i0 + q;
+        if (i >= nv) break;
+        T s = block_sum(acc[q], lds);
+        if (threadIdx.x == 0) red[(int64_t)i * gridDim.x + blockIdx.x] = s;
+    }
+    if (last_block(counter, gridDim.x * gridDim.y)) {
+        const volatile T* vr = red;
+        for (int i = threadIdx.x; i < nv; i += kBlock) {
+            T s = 0;
+            for (unsigned b = 0; b < gridDim.x; ++b) s += vr[(int64_t)i * gridDim.x + b];
+            h[i] = (double)s;
+        }
+        if (threadIdx.x == 0) *counter = 0;
+    }
+}
+
+template <typename T>
+void multidot(int64_t n, int k, const T* V, int64_t ldv, const T* w, bool with_self, double* h, double* red,
+              uint32_t* counter, hipStream_t st) {
+    const int nv = k + (with_self ? 1 : 0);
+    dim3 grid(red_grid(n), (nv + kDotGroup - 1) / kDotGroup);
+    hipLaunchKernelGGL((k_multidot<T>), grid, dim3(kBlock), 0, st, n, k, V, ldv, w, with_self ? 1 : 0, h,
+                       reinterpret_cast<T*>(red), counter);
+}
+
+// Givens update of Hessenberg column j (FP64, one thread).
+__device__ void givens_step(const GivensArgs& a, double hn2) {
+    const int j = a.j, ld = a.ldh;
+    double* Hc = a.H + (int64_t)j * ld;
+    for (int i = 0; i <= j; ++i) Hc[i] = a.h1[i] + a.h2[i];
+    const double hn = sqrt(hn2);
+    const double wpre = sqrt(a.h1[j + 1]);
+    Hc[j + 1] = hn;
+    for (int i = 0; i < j; ++i) {
+        const double t = a.cs[i] * Hc[i] + a.sn[i] * Hc[i + 1];
+        Hc[i + 1] = -a.sn[i] * Hc[i] + a.cs[i] * Hc[i + 1];
+        Hc[i] = t;
+    }
+    const double rho = hypot(Hc[j], Hc[j + 1]);
+    if (rho == 0.0) {
+        a.cs[j] = 1.0;
+        a.sn[j] = 0.0;
+    } else {
+        a.cs[j] = Hc[j] / rho;
+        a.sn[j] = Hc[j + 1] / rho;
+    }
+    Hc[j] = rho;
+    Hc[j + 1] = 0.0;
+    a.g[j + 1] = -a.sn[j] * a.g[j];
+    a.g[j] = a.cs[j] * a.g[j];
+    const bool bd = !(hn > 1e-14 * wpre);
+    a.status[0] = fabs(a.g[j + 1]);
+    a.status[1] = bd ? 1.0 : 0.0;
+    a.status[2] = bd ? 0.0 : 1.0 / hn;
+    a.status[3] = wpre;
+}
+
+// w -= sum_i V_i h_i; optional ||w||^2 + Givens (last block)
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_orth_update(int64_t n, int k, const T* __restrict__ V, int64_t ldv,
+                                                        const double* __restrict__ h, T* __restrict__ w,
+                                                        int do_givens, GivensArgs ga, T* red, uint32_t* counter) {
+    __shared__ T hs[256];
+    __shared__ T lds[4];
+    T acc = 0;
+    for (int c0 = 0; c0 < k; c0 += 256) {
+        // process vectors in chunks of 256 staged in LDS
+        const int cnt = min(256, k - c0);
+        __syncthreads();
+        if ((int)threadIdx.x < cnt) hs[threadIdx.x] = (T)h[c0 + threadIdx.x];
+        __syncthreads();
+        for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < n; t += (int64_t)gridDim.x * kBlock) {
+            T s = 0;
+            for (int i = 0; i < cnt; ++i) s += V[(c0 + i) * ldv + t] * hs[i];
+            w[t] -= s;
+        }
+    }
+    if (!do_givens) return;
+    for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < n; t += (int64_t)gridDim.x * kBlock)
+        acc += w[t] * w[t];
+    T s = block_sum(acc, lds);
+    if (threadIdx.x == 0) red[blockIdx.x] = s;
+    if (last_block(counter, gridDim.x)) {
+        if (threadIdx.x == 0) {
+            const volatile T* vr = red;
+            T tot = 0;
+            for (unsigned b = 0; b < gridDim.x; ++b) tot += vr[b];
+            givens_step(ga, (double)tot);
+            *counter = 0;
+        }
+    }
+}
+
+template <typename T>
+void orth_update(int64_t n, int k, const T* V, int64_t ldv, const double* h, T* w, const GivensArgs* givens,
+                 double* red, uint32_t* counter, hipStream_t st) {
+    GivensArgs ga = givens ? *givens : GivensArgs{};
+    hipLaunchKernelGGL((k_orth_update<T>), dim3(red_grid(n)), dim3(kBlock), 0, st, n, k, V, ldv, h, w,
+                       givens ? 1 : 0, ga, reinterpret_cast<T*>(red), counter);
+}
+
+template <typename T>
+__global__ void k_scale_status(int64_t n, T* w, const double* status) {
+    if (status[1] != 0.0) return;
+    const T s = (T)status[2];
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) w[i] *= s;
+}
+template <typename T>
+void scale_by_status(int64_t n, T* w, const double* status, hipStream_t st) {
+    hipLaunchKernelGGL((k_scale_status<T>), dim3(std::min<int64_t>(grid_for(n), 4096)), dim3(kBlock), 0, st, n, w,
+                       status);
+}
+
+__global__ void k_init_g(double* g, int len, double beta) {
+    for (int i = threadIdx.x; i < len; i += blockDim.x) g[i] = (i == 0) ? beta : 0.0;
+}
+void init_g(double* g, int len, double beta, hipStream_t st) {
+    hipLaunchKernelGGL(k_init_g, dim3(1), dim3(kBlock), 0, st, g, len, beta);
+}
+
+__global__ void k_backsolve(int k, int ld, const double* H, const double* g, double* y) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    for (int i = k - 1; i >= 0; --i) {
+        double s = g[i];
+        for (int c = i + 1; c < k; ++c) s -= H[(int64_t)c * ld + i] * y[c];
+        y[i] = s / H[(int64_t)i * ld + i];
+    }
+}
+void backsolve(int k, int ldh, const double* H, const double* g, double* y, hipStream_t st) {
+    hipLaunchKernelGGL(k_backsolve, dim3(1), dim3(64), 0, st, k, ldh, H, g, y);
+}
+
+template <typename T, typename TX>
+__global__ __launch_bounds__(kBlock) void k_combine(int64_t n, int k, const T* __restrict__ V, int64_t ldv,
+                                                    const double* __restrict__ y, TX* __restrict__ x, int acc) {
+    __shared__ double ys[256];
+    for (int64_t t0 = (int64_t)blockIdx.x * kBlock; t0 < n; t0 += (int64_t)gridDim.x * kBlock) {
+        const int64_t t = t0 + threadIdx.x;
+        double s = 0.0;
+        for (int c0 = 0; c0 < k; c0 += 256) {
+            const int cnt = min(256, k - c0);
+            __syncthreads();
+            if ((int)threadIdx.x < cnt) ys[threadIdx.x] = y[c0 + threadIdx.x];
+            __syncthreads();
+            if (t < n)
+                for (int i = 0; i < cnt; ++i) s += (double)V[(c0 + i) * ldv + t] * ys[i];
+        }
+        if (t < n) x[t] = acc ? (TX)((double)x[t] + s) : (TX)s;
+    }
+}
+template <typename T, typename TX>
+void combine(int64_t n, int k, const T* V, int64_t ldv, const double* y, TX* x, bool accumulate, hipStream_t st) {
+    hipLaunchKernelGGL((k_combine<T, TX>), dim3(red_grid(n)), dim3(kBlock), 0, st, n, k, V, ldv, y, x,
+                       accumulate ? 1 : 0);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_norm2(int64_t n, const T* x, double* out, T* red, uint32_t* counter) {
+    __shared__ T lds[4];
+    T acc = 0;
+    for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < n; t += (int64_t)gridDim.x * kBlock)
+        acc += x[t] * x[t];
+    T s = block_sum(acc, lds);
+    if (threadIdx.x == 0) red[blockIdx.x] = s;
+    if (last_block(counter, gridDim.x)) {
+        if (threadIdx.x == 0) {
+            const volatile T* vr = red;
+            T tot = 0;
+            for (unsigned b = 0; b < gridDim.x; ++b) tot += vr[b];
+            out[0] = sqrt((double)tot);
+            *counter = 0;
+        }
+    }
+}
+template <typename T>
+void norm2(int64_t n, const T* x, double* out, double* red, uint32_t* counter, hipStream_t st) {
+    hipLaunchKernelGGL((k_norm2<T>), dim3(red_grid(n)), dim3(kBlock), 0, st, n, x, out, reinterpret_cast<T*>(red),
+                       counter);
+}
+
+template <typename T>
+__global__ void k_scale_by(int64_t n, const T* x, const double* s, int inverse, T* y) {
+    const double sv = inverse ? 1.0 / s[0] : s[0];
+    const T f = (T)sv;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
+        y[i] = x[i] * f;
+}
+template <typename T>
+void scale_by(int64_t n, const T* x, const double* s, bool inverse, T* y, hipStream_t st) {
+    hipLaunchKernelGGL((k_scale_by<T>), dim3(std::min<int64_t>(grid_for(n), 4096)), dim3(kBlock), 0, st, n, x, s,
+                       inverse ? 1 : 0, y);
+}
+
+// ---------------------------------------------------------------------------
+// V-cycle pieces
+// ---------------------------------------------------------------------------
+
+template <typename T>
+__global__ void k_cheb_first(int64_t n, const T* b, const T* dinv, T c2, T* x, T* d) {
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+        const T di = c2 * dinv[i] * b[i];
+        d[i] = di;
+        x[i] = di;
+    }
+}
+template <typename T>
+void cheb_first(int64_t n, const T* b, const T* dinv, T c2, T* x, T* d, hipStream_t st) {
+    hipLaunchKernelGGL((k_cheb_first<T>), dim3(std::min<int64_t>(grid_for(n), 65535)), dim3(kBlock), 0, st, n, b,
+                       dinv, c2, x, d);
+}
+
+// Fused residual + Chebyshev update: r = b - M xin; d = c1 d + c2 dinv r; xout = xin + d
+template <typename T, int BS, int W>
+__global__ __launch_bounds__(kBlock) void k_cheb_step(BlockOp<T> M, const T* __restrict__ xin, T* __restrict__ xout,
+                                                      T* __restrict__ d, const T* __restrict__ b,
+                                                      const T* __restrict__ dinv, T c1, T c2) {
+    const int64_t tid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int row = (int)(tid / W);
+    const int lane = threadIdx.x % W;
+    const bool valid = row < M.n;
+    T acc[BS];
+#pragma unroll
+    for (int r = 0; r < BS; ++r) acc[r] = 0;
+    if (valid) {
+        const int k1 = M.rp[row + 1];
+        for (int k = M.rp[row] + lane; k < k1; k += W) {
+            const int j = M.col[k];
+            T xj[BS];
+#pragma unroll
+            for (int c = 0; c < BS; ++c) xj[c] = xin[(int64_t)BS * j + c];
+#pragma unroll
+            for (int r = 0; r < BS; ++r)
+#pragma unroll
+                for (int c = 0; c < BS; ++c) acc[r] += M.v[r * M.rs + c * M.cs + k] * xj[c];
+        }
+    }
+#pragma unroll
+    for (int off = W / 2; off > 0; off >>= 1)
+#pragma unroll
+        for (int r = 0; r < BS; ++r) acc[r] += __shfl_xor(acc[r], off, W);
+    if (!valid || lane >= BS) return;
+    T s = acc[0];
+#pragma unroll
+    for (int r = 1; r < BS; ++r)
+        if (lane == r) s = acc[r];
+    const int64_t i = (int64_t)BS * row + lane;
+    if (M.dextra) s += M.dextra[i] * xin[i];
+    const T ri = b[i] - s;
+    T di = c2 * dinv[i] * ri;
+    if (c1 != T(0)) di += c1 * d[i];
+    d[i] = di;
+    xout[i] = xin[i] + di;
+}
+
+template <typename T>
+void cheb_step(int bs, const BlockOp<T>& M, const T* xin, T* xout, T* d, const T* b, const T* dinv, T c1, T c2,
+               hipStream_t st) {
+    if (bs == 3)
+        hipLaunchKernelGGL((k_cheb_step<T, 3, 8>), dim3(grid_for((int64_t)M.n * 8)), dim3(kBlock), 0, st, M, xin,
+                           xout, d, b, dinv, c1, c2);
+    else
+        hipLaunchKernelGGL((k_cheb_step<T, 1, 16>), dim3(grid_for((int64_t)M.n * 16)), dim3(kBlock), 0, st, M, xin,
+                           xout, d, b, dinv, c1, c2);
+}
+
+template <typename T>
+__global__ void k_restrict(int nc, int bs, const int32_t* aptr, const int32_t* anodes, const T* r, T* bc) {
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= (int64_t)nc * bs) return;
+    const int I = (int)(t / bs), c = (int)(t % bs);
+    T s = 0;
+    for (int q = aptr[I]; q < aptr[I + 1]; ++q) s += r[(int64_t)bs * anodes[q] + c];
+    bc[t] = s;
+}
+template <typename T>
+void restrict_agg(int nc, int bs, const int32_t* aptr, const int32_t* anodes, const T* r, T* bc, hipStream_t st) {
+    hipLaunchKernelGGL((k_restrict<T>), dim3(grid_for((int64_t)nc * bs)), dim3(kBlock), 0, st, nc, bs, aptr, anodes,
+                       r, bc);
+}
+
+template <typename T>
+__global__ void k_prolong(int n, int bs, const int32_t* agg, const T* ec, T* x) {
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= (int64_t)n * bs) return;
+    const int i = (int)(t / bs), c = (int)(t % bs);
+    x[t] += ec[(int64_t)bs * agg[i] + c];
+}
+template <typename T>
+void prolong_add(int n, int bs, const int32_t* agg, const T* ec, T* x, hipStream_t st) {
+    hipLaunchKernelGGL((k_prolong<T>), dim3(grid_for((int64_t)n * bs)), dim3(kBlock), 0, st, n, bs, agg, ec, x);
+}
+
+// x = Minv b (FP64 arithmetic), one wavefront per row
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_dense_gemv(int n, const double* Minv, const T* b, T* x) {
+    const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int l = threadIdx.x & 63;
+    if (row >= n) return;
+    double s = 0.0;
+    for (int c = l; c < n; c += 64) s += Minv[(int64_t)row * n + c] * (double)b[c];
+    s = wave_sum(s);
+    if (l == 0) x[row] = (T)s;
+}
+template <typename T>
+void dense_gemv(int n, const double* Minv, const T* b, T* x, hipStream_t st) {
+    hipLaunchKernelGGL((k_dense_gemv<T>), dim3((n + 3) / 4), dim3(kBlock), 0, st, n, Minv, b, x);
+}
+
+// ---------------------------------------------------------------------------
+// Set-up numerics (FP64)
+// ---------------------------------------------------------------------------
+
+// Coarse value q of every plane (r < np_r, c < np_c) = sum of the listed fine
+// values; on the coarse diagonal also the fine extra diagonal of the aggregate.
+__global__ void k_galerkin(int64_t nq, int np_r, int np_c, const int32_t* gptr, const int32_t* gidx,
+                           const double* vf, int64_t frs, int64_t fcs, double* vc, int64_t crs, int64_t ccs,
+                           const int32_t* qrow, const int32_t* ccol, const double* dextra, const int32_t* aptr,
+                           const int32_t* anodes) {
+    const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (q >= nq) return;
+    const int t0 = gptr[q], t1 = gptr[q + 1];
+    const bool on_diag = dextra && qrow[q] == ccol[q];
+    for (int r = 0; r < np_r; ++r)
+        for (int c = 0; c < np_c; ++c) {
+            double s = 0.0;
+            const double* p = vf + r * frs + c * fcs;
+            for (int t = t0; t < t1; ++t) s += p[gidx[t]];
+            if (on_diag && r == c) {
+                const int I = qrow[q];
+                for (int a = aptr[I]; a < aptr[I + 1]; ++a) s += dextra[(int64_t)np_r * anodes[a] + r];
+            }
+            vc[r * crs + c * ccs + q] = s;
+        }
+}
+void galerkin(int64_t nq, int np_r, int np_c, const int32_t* gptr, const int32_t* gidx, const double* vf,
+              int64_t frs, int64_t fcs, double* vc, int64_t crs, int64_t ccs, const int32_t* qrow,
+              const int32_t* ccol, const double* dextra, const int32_t* aptr, const int32_t* anodes,
+              hipStream_t st) {
+    if (nq <= 0) return;
+    hipLaunchKernelGGL(k_galerkin, dim3(grid_for(nq)), dim3(kBlock), 0, st, nq, np_r, np_c, gptr, gidx, vf, frs,
+                       fcs, vc, crs, ccs, qrow, ccol, dextra, aptr, anodes);
+}
+
+__global__ void k_block_dinv(int n, int bs, const int32_t* rp, const int32_t* col, const double* v, int64_t rs,
+                             int64_t cs, const double* dextra, double* dinv, double* diag) {
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= (int64_t)n * bs) return;
+    const int i = (int)(t / bs), r = (int)(t % bs);
+    const int k = lower_bound_dev(col, rp[i], rp[i + 1], i);
+    double d = v[r * rs + r * cs + k];
+    if (dextra) d += dextra[t];
+    if (diag) diag[t] = d;
+    dinv[t] = 1.0 / d;
+}
+void block_dinv(int n, int bs, const int32_t* rp, const int32_t* col, const double* v, int64_t rs, int64_t cs,
+                const double* dextra, double* dinv, double* diag, hipStream_t st) {
+    hipLaunchKernelGGL(k_block_dinv, dim3(grid_for((int64_t)n * bs)), dim3(kBlock), 0, st, n, bs, rp, col, v, rs,
+                       cs, dextra, dinv, diag);
+}
+
+// S_hat_ij = D_ij - sum_{k in N(i)} sum_c C_{i,k,c} B_{k,j,c} / diag(A)_{3k+c}
+// one wavefront per row i, lanes over the entries of row i of S_hat.
+__global__ __launch_bounds__(kBlock) void k_shat(int n, const int32_t* __restrict__ rp,
+                                                 const int32_t* __restrict__ col, const double* __restrict__ V,
+                                                 int64_t nnzb, const double* __restrict__ dinvA,
+                                                 const int32_t* __restrict__ srp, const int32_t* __restrict__ scol,
+                                                 double* __restrict__ shat) {
+    const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int l = threadIdx.x & 63;
+    if (row >= n) return;
+    const int r0 = rp[row], r1 = rp[row + 1];
+    for (int e = srp[row] + l; e < srp[row + 1]; e += 64) {
+        const int j = scol[e];
+        double s = 0.0;
+        const int pd = lower_bound_dev(col, r0, r1, j);
+        if (pd < r1 && col[pd] == j) s = V[15 * nnzb + pd];
+        for (int q = r0; q < r1; ++q) {
+            const int k = col[q];
+            const int k0 = rp[k], k1 = rp[k + 1];
+            const int p2 = lower_bound_dev(col, k0, k1, j);
+            if (p2 < k1 && col[p2] == j) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+                    s -= V[(12 + c) * nnzb + q] * V[(4 * c + 3) * nnzb + p2] * dinvA[3 * (int64_t)k + c];
+            }
+        }
+        shat[e] = s;
+    }
+}
+void shat_numeric(int n, const int32_t* rp, const int32_t* col, const double* V, int64_t nnzb, const double* dinvA,
+                  const int32_t* srp, const int32_t* scol, double* shat, hipStream_t st) {
+    hipLaunchKernelGGL(k_shat, dim3((n + 3) / 4), dim3(kBlock), 0, st, n, rp, col, V, nnzb, dinvA, srp, scol, shat);
+}
+
+// Dense copy of a block-sparse matrix into the left half of work [n][2n]
+// (right half: identity) for the Gauss-Jordan inverse.
+__global__ void k_dense_from_csr(int nb, int bs, const int32_t* rp, const int32_t* col, const double* v, int64_t rs,
+                                 int64_t cs, const double* dextra, double* work) {
+    const int n = nb * bs;
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= (int64_t)n * 2 * n) return;
+    const int r = (int)(t / (2 * n)), c = (int)(t % (2 * n));
+    double val = 0.0;
+    if (c >= n) {
+        val = (c - n == r) ? 1.0 : 0.0;
+    } else {
+        const int I = r / bs, rr = r % bs, J = c / bs, cc = c % bs;
+        const int k = lower_bound_dev(col, rp[I], rp[I + 1], J);
+        if (k < rp[I + 1] && col[k] == J) val = v[rr * rs + cc * cs + k];
+        if (dextra && r == c) val += dextra[r];
+    }
+    work[t] = val;
+}
+void dense_from_csr(int nb, int bs, const int32_t* rp, const int32_t* col, const double* v, int64_t rs, int64_t cs,
+                    const double* dextra, double* work, hipStream_t st) {
+    const int64_t n = (int64_t)nb * bs;
+    hipLaunchKernelGGL(k_dense_from_csr, dim3(grid_for(n * 2 * n)), dim3(kBlock), 0, st, nb, bs, rp, col, v, rs, cs,
+                       dextra, work);
+}
+
+// Gauss-Jordan with partial pivoting on work [n][2n], one workgroup of 1024.
+__global__ __launch_bounds__(1024) void k_gauss_jordan(int n, double* work, double* inv) {
+    __shared__ double sval[1024];
+    __shared__ int sidx[1024];
+    __shared__ int piv;
+    const int n2 = 2 * n;
+    for (int k = 0; k < n; ++k) {
+        double best = -1.0;
+        int bi = k;
+        for (int r = k + threadIdx.x; r < n; r += 1024) {
+            const double a = fabs(work[(int64_t)r * n2 + k]);
+            if (a > best) {
+                best = a;
+                bi = r;
+            }
+        }
+        sval[threadIdx.x] = best;
+        sidx[threadIdx.x] = bi;
+        __syncthreads();
+        for (int s = 512; s > 0; s >>= 1) {
+            if ((int)threadIdx.x < s) {
+                const double o = sval[threadIdx.x + s];
+                const int oi = sidx[threadIdx.x + s];
+                if (o > sval[threadIdx.x] || (o == sval[threadIdx.x] && oi < sidx[threadIdx.x])) {
+                    sval[threadIdx.x] = o;
+                    sidx[threadIdx.x] = oi;
+                }
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) piv = sidx[0];
+        __syncthreads();
+        const int p = piv;
+        if (p != k)
+            for (int c = threadIdx.x; c < n2; c += 1024) {
+                const double t = work[(int64_t)k * n2 + c];
+                work[(int64_t)k * n2 + c] = work[(int64_t)p * n2 + c];
+                work[(int64_t)p * n2 + c] = t;
+            }
+        __syncthreads();
+        const double inv_p = 1.0 / work[(int64_t)k * n2 + k];
+        __syncthreads();
+        for (int c = threadIdx.x; c < n2; c += 1024) work[(int64_t)k * n2 + c] *= inv_p;
+        __syncthreads();
+        // eliminate column k from all other rows, 1024 rows at a time (factors first)
+        for (int r0 = 0; r0 < n; r0 += 1024) {
+            const int r = r0 + threadIdx.x;
+            double f = 0.0;
+            if (r < n && r != k) f = work[(int64_t)r * n2 + k];
+            __syncthreads();
+            sval[threadIdx.x] = f;
+            __syncthreads();
+            const int rows = min(1024, n - r0);
+            for (int e = threadIdx.x; e < rows * n2; e += 1024) {
+                const int rr = e / n2, c = e % n2;
+                const double fr = sval[rr];
+                if (fr != 0.0) work[(int64_t)(r0 + rr) * n2 + c] -= fr * work[(int64_t)k * n2 + c];
+            }
+            __syncthreads();
+        }
+    }
+    for (int e = threadIdx.x; e < n * n; e += 1024) inv[e] = work[(int64_t)(e / n) * n2 + n + e % n];
+}
+void gauss_jordan_inverse(int n, double* work, double* inv, hipStream_t st) {
+    hipLaunchKernelGGL(k_gauss_jordan, dim3(1), dim3(1024), 0, st, n, work, inv);
+}
+
+__global__ void k_power_start(int64_t n, double* x) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const uint64_t h = ((uint64_t)i * 2654435761ull) & 0xffffffffull;
+    x[i] = 0.5 + (double)h / 4294967296.0;
+}
+void power_start(int64_t n, double* x, hipStream_t st) {
+    hipLaunchKernelGGL(k_power_start, dim3(grid_for(n)), dim3(kBlock), 0, st, n, x);
+}
+
+// dK_{3 node + c} = sum_k c_k (a^k_{node,c})^2 over outlet slots (outlets are disjoint)
+__global__ void k_rank_one_diag(int n_slots, const int32_t* onode, const int32_t* oid, const double* amsk,
+                                const double* ck, double* dK) {
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= (int64_t)n_slots * 3) return;
+    const int sl = (int)(t / 3), c = (int)(t % 3);
+    const double a = amsk[t];
+    dK[3 * (int64_t)onode[sl] + c] = ck[oid[sl]] * a * a;
+}
+void rank_one_diag(int n_slots, const int32_t* onode, const int32_t* oid, const double* amsk, const double* ck,
+                   double* dK, hipStream_t st) {
+    if (n_slots <= 0) return;
+    hipLaunchKernelGGL(k_rank_one_diag, dim3(grid_for((int64_t)n_slots * 3)), dim3(kBlock), 0, st, n_slots, onode,
+                       oid, amsk, ck, dK);
+}
+
+// Transposed system: plane (r,c) of block (i,j) = plane (c,r) of block (j,i)
+__global__ void k_transpose_values(int64_t nnzb, const int32_t* tmap, const double* V, double* Vt) {
+    const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (k >= nnzb) return;
+    const int64_t kt = tmap[k];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) Vt[(4 * r + c) * nnzb + k] = V[(4 * c + r) * nnzb + kt];
+}
+void transpose_values(int64_t nnzb, const int32_t* tmap, const double* V, double* Vt, hipStream_t st) {
+    hipLaunchKernelGGL(k_transpose_values, dim3(grid_for(nnzb)), dim3(kBlock), 0, st, nnzb, tmap, V, Vt);
+}
+
+__global__ void k_export_aos(int64_t nnzb, const double* V, double* dst) {
+    const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (k >= nnzb) return;
+#pragma unroll
+    for (int p = 0; p < 16; ++p) dst[16 * k + p] = V[p * nnzb + k];
+}
+void export_aos(int64_t nnzb, const double* V, double* dst, hipStream_t st) {
+    hipLaunchKernelGGL(k_export_aos, dim3(grid_for(nnzb)), dim3(kBlock), 0, st, nnzb, V, dst);
+}
+
+__global__ void k_newton_update(int64_t n, double gdt, const double* dx, double* y, double* ydot) {
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+        const double d = dx[i];
+        y[i] += gdt * d;
+        ydot[i] += d;
+    }
+}
+void newton_update(int64_t n, double gdt, const double* dx, double* y, double* ydot, hipStream_t st) {
+    hipLaunchKernelGGL(k_newton_update, dim3(std::min<int64_t>(grid_for(n), 65535)), dim3(kBlock), 0, st, n, gdt, dx,
+                       y, ydot);
+}
+
+// ---------------------------------------------------------------------------
+// explicit instantiations
+// ---------------------------------------------------------------------------
+#define NS_INST(T)                                                                                                   \
+    template void spmv<T>(int, int, const BlockOp<T>&, const T*, T*, T, const T*, T, const T*, const RankOne<T>*,   \
+                          hipStream_t);                                                                              \
+    template void spmv_full<T>(int, const int32_t*, const int32_t*, const T*, int64_t, const T*, T*, T, const T*, T, \
+                               const RankOne<T>*, hipStream_t);                                                      \
+    template void outlet_dot<T>(int, const int32_t*, const int32_t*, const T*, const T*, const T*, T*, hipStream_t);  \
+    template void axpby<T>(int64_t, T, const T*, T, const T*, T*, hipStream_t);                                      \
+    template void fill<T>(int64_t, T, T*, hipStream_t);                                                              \
+    template void mul<T>(int64_t, const T*, const T*, T*, hipStream_t);                                              \
+    template void multidot<T>(int64_t, int, const T*, int64_t, const T*, bool, double*, double*, uint32_t*,          \
+                              hipStream_t);                                                                          \
+    template void orth_update<T>(int64_t, int, const T*, int64_t, const double*, T*, const GivensArgs*, double*,     \
+                                 uint32_t*, hipStream_t);                                                            \
+    template void scale_by_status<T>(int64_t, T*, const double*, hipStream_t);                                       \
+    template void norm2<T>(int64_t, const T*, double*, double*, uint32_t*, hipStream_t);                            \
+    template void scale_by<T>(int64_t, const T*, const double*, bool, T*, hipStream_t);                             \
+    template void cheb_first<T>(int64_t, const T*, const T*, T, T*, T*, hipStream_t);                                \
+    template void cheb_step<T>(int, const BlockOp<T>&, const T*, T*, T*, const T*, const T*, T, T, hipStream_t);     \
+    template void restrict_agg<T>(int, int, const int32_t*, const int32_t*, const T*, T*, hipStream_t);              \
+    template void prolong_add<T>(int, int, const int32_t*, const T*, T*, hipStream_t);                               \
+    template void dense_gemv<T>(int, const double*, const T*, T*, hipStream_t);
+
+NS_INST(double)
+NS_INST(float)
+template void fill<uint32_t>(int64_t, uint32_t, uint32_t*, hipStream_t);
+template void convert<double, float>(int64_t, const double*, float*, hipStream_t);
+template void convert<float, double>(int64_t, const float*, double*, hipStream_t);
+template void convert<double, double>(int64_t, const double*, double*, hipStream_t);
+template void convert<float, float>(int64_t, const float*, float*, hipStream_t);
+template void combine<double, double>(int64_t, int, const double*, int64_t, const double*, double*, bool,
+                                      hipStream_t);
+template void combine<float, float>(int64_t, int, const float*, int64_t, const double*, float*, bool, hipStream_t);
+template void combine<float, double>(int64_t, int, const float*, int64_t, const double*, double*, bool,
+                                     hipStream_t);
+
+}  // namespace ns

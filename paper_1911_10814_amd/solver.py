@@ -1,0 +1,307 @@
+"""Python binding of the nested block solver: device memory and streams from
+PyTorch, every computation in the HIP library (``libns_hip.so``).
+
+``NsContext``       one mesh: symbolic set-up, workspace, assembly, solves.
+``SolveOptions``    mirror of ``ns_solve_opts`` (paper defaults, Sec. 3.1).
+``NestedSolveFn``   torch.autograd.Function R -> x(R) whose backward runs the
+                    transposed nested solve (adjoint) on the device.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import NsError
+
+
+@dataclasses.dataclass
+class SolveOptions:
+    rtol: float = 1e-8
+    atol: float = 1e-50
+    rtol_A: float = 1e-3
+    rtol_S: float = 1e-3
+    rtol_I: float = 1e-3
+    m: int = 200
+    nmax: int = 200
+    m_A: int = 200
+    nmax_A: int = 200
+    m_S: int = 200
+    nmax_S: int = 200
+    pc_A: str = "amg"            # "amg" | "jacobi"
+    precision: str = "fp64"      # "fp64" | "fp32_inner"
+    cheb_degree: int = 2
+    schedule: list | None = None  # fixed iteration counts per Krylov call (replay)
+    record: bool = True           # record the iteration count of every Krylov call
+
+    def to_c(self):
+        o = _lib.NsSolveOpts()
+        for f in ("rtol", "atol", "rtol_A", "rtol_S", "rtol_I", "m", "nmax", "m_A", "nmax_A", "m_S", "nmax_S",
+                  "cheb_degree"):
+            setattr(o, f, getattr(self, f))
+        o.pc_A = {"amg": 0, "jacobi": 1}[self.pc_A]
+        o.precision = {"fp64": 0, "fp32_inner": 1}[self.precision]
+        keep = []
+        if self.schedule is not None:
+            arr = np.ascontiguousarray(self.schedule, dtype=np.int32)
+            keep.append(arr)
+            o.h_sched = arr.ctypes.data_as(_lib.PI)
+            o.sched_len = len(arr)
+        out = None
+        if self.record:
+            out = np.zeros(1 << 16, dtype=np.int32)
+            keep.append(out)
+            o.h_sched_out = out.ctypes.data_as(_lib.PI)
+            o.sched_cap = len(out)
+        return o, keep, out
+
+
+def _stream_handle(device) -> C.c_void_p:
+    return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _ptr(t: torch.Tensor) -> C.c_void_p:
+    return C.c_void_p(t.data_ptr())
+
+
+class NsContext:
+    """A mesh bound to one GPU.
+
+    ``case`` is any object with the fields of ``ns_inputs.Case`` (xyz, tets,
+    mask, outlet_ptr, faces; n_nodes, n_elems, n_outlets)."""
+
+    def __init__(self, case, *, max_m=200, max_m_A=200, max_m_S=200, coarse_nodes=128, max_levels=16,
+                 device="cuda:0"):
+        self.lib = _lib.load()
+        self.device = torch.device(device)
+        self.N = int(case.n_nodes)
+        self.n_out = int(case.n_outlets)
+        self._xyz = np.ascontiguousarray(case.xyz, dtype=np.float64)
+        self._tets = np.ascontiguousarray(case.tets, dtype=np.int32)
+        self._optr = np.ascontiguousarray(case.outlet_ptr, dtype=np.int32)
+        self._faces = np.ascontiguousarray(case.faces, dtype=np.int32).reshape(-1, 3)
+        self._mask = np.ascontiguousarray(case.mask, dtype=np.uint8)
+        mesh = _lib.NsMesh(self.N, int(case.n_elems), self.n_out, self._xyz.ctypes.data_as(_lib.PD),
+                           self._tets.ctypes.data_as(_lib.PI), self._optr.ctypes.data_as(_lib.PI),
+                           self._faces.ctypes.data_as(_lib.PI),
+                           self._mask.ctypes.data_as(C.POINTER(C.c_uint8)))
+        opts = _lib.NsCtxOpts(max_m, max_m_A, max_m_S, coarse_nodes, max_levels)
+        handle = C.c_void_p()
+        nbytes = C.c_size_t()
+        st = self.lib.ns_ctx_create(C.byref(mesh), C.byref(opts), C.byref(handle), C.byref(nbytes))
+        if st != 0:
+            raise NsError(st, self.lib.ns_last_error(None).decode())
+        self.h = handle
+        self.workspace_bytes = int(nbytes.value)
+        self.ws = None
+        self.sizes = self.query()
+        self.nnzb = self.sizes[1]
+
+    # ------------------------------------------------------------------ basics
+    def _check(self, st):
+        if st < 0:
+            raise NsError(st, self.lib.ns_last_error(self.h).decode())
+        return st
+
+    def query(self):
+        out = (C.c_int64 * 6)()
+        self._check(self.lib.ns_query(self.h, out))
+        return list(out)
+
+    def bind(self):
+        """Allocate the device workspace (one uint8 tensor) and upload the mesh."""
+        if self.ws is not None:
+            return self
+        self.ws = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=self.device)
+        self._check(self.lib.ns_ctx_bind(self.h, _ptr(self.ws), self.workspace_bytes, _stream_handle(self.device)))
+        return self
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.ns_ctx_destroy(self.h)
+            self.h = None
+        self.ws = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _dev(self, a, shape=None):
+        t = torch.as_tensor(a, dtype=torch.float64, device=self.device)
+        if shape is not None:
+            t = t.reshape(shape)
+        return t.contiguous()
+
+    # ------------------------------------------------------------------ symbolic (host) views
+    def pattern(self):
+        rp = np.zeros(self.N + 1, np.int32)
+        col = np.zeros(self.nnzb, np.int32)
+        self._check(self.lib.ns_export_pattern(self.h, rp.ctypes.data_as(_lib.PI), col.ctypes.data_as(_lib.PI)))
+        return rp, col
+
+    def aggregates(self, level):
+        n = self.N
+        for lev in range(level):
+            n = int(self.aggregates(lev).max()) + 1
+        agg = np.zeros(n, np.int32)
+        self._check(self.lib.ns_export_aggregates(self.h, level, agg.ctypes.data_as(_lib.PI)))
+        return agg
+
+    def colors(self):
+        col = np.zeros(len(self._tets), np.int32)
+        self._check(self.lib.ns_export_colors(self.h, col.ctypes.data_as(_lib.PI)))
+        return col
+
+    # ------------------------------------------------------------------ device work
+    def outlet_flow(self, v):
+        v = self._dev(v, (self.N, 3))
+        out = np.zeros(max(1, self.n_out))
+        self._check(self.lib.ns_outlet_flow(self.h, _ptr(v), out.ctypes.data_as(_lib.PD),
+                                            _stream_handle(self.device)))
+        return out[:self.n_out]
+
+    def rank_one_dots(self, xv):
+        xv = self._dev(xv).reshape(-1)[:3 * self.N].contiguous()
+        out = np.zeros(max(1, self.n_out))
+        self._check(self.lib.ns_rank_one_dots(self.h, _ptr(xv), out.ctypes.data_as(_lib.PD),
+                                              _stream_handle(self.device)))
+        return out[:self.n_out]
+
+    def assemble(self, v, p, vdot, *, rho, mu, dt, rho_inf, m=None, P_af=None, beta_bf=0.2, c_t=4.0, c_i=36.0,
+                 rhs=None):
+        """Residual and tangent (Sec. 2.5); returns rhs = -[R_m; R_p] (device, [4N])."""
+        self.bind()
+        v = self._dev(v, (self.N, 3))
+        p = self._dev(p, (self.N,))
+        vdot = self._dev(vdot, (self.N, 3))
+        mk = np.ascontiguousarray(m if m is not None else np.zeros(self.n_out), dtype=np.float64)
+        pk = np.ascontiguousarray(P_af if P_af is not None else np.zeros(self.n_out), dtype=np.float64)
+        if len(mk) != self.n_out or len(pk) != self.n_out:
+            raise ValueError("one m and one P_af per outlet")
+        ph = _lib.NsPhys(rho, mu, dt, rho_inf, beta_bf, c_t, c_i, mk.ctypes.data_as(_lib.PD),
+                         pk.ctypes.data_as(_lib.PD))
+        if rhs is None:
+            rhs = torch.empty(4 * self.N, dtype=torch.float64, device=self.device)
+        self._check(self.lib.ns_assemble_tangent(self.h, C.byref(ph), _ptr(v), _ptr(p), _ptr(vdot), _ptr(rhs),
+                                                 _stream_handle(self.device)))
+        self._keep = (v, p, vdot, mk, pk)  # inputs stay alive until the stream has consumed them
+        return rhs
+
+    def _solve(self, fn, b, opts: SolveOptions | None, x=None):
+        opts = opts or SolveOptions()
+        b = self._dev(b).reshape(-1)
+        if b.numel() != 4 * self.N:
+            raise ValueError("rhs must have 4N entries")
+        if x is None:
+            x = torch.empty_like(b)
+        co, keep, out = opts.to_c()
+        stats = _lib.NsStats()
+        st = self._check(fn(self.h, C.byref(co), _ptr(b), _ptr(x), C.byref(stats), _stream_handle(self.device)))
+        info = stats.as_dict()
+        info["status"] = _lib.STATUS_NAMES[st]
+        info["converged"] = st == 0
+        if out is not None:
+            info["schedule"] = out[:stats.n_calls].tolist()
+        return x, info
+
+    def solve(self, rhs, opts: SolveOptions | None = None, x=None):
+        """Nested FGMRES + P_SCR solve of the last assembled tangent."""
+        return self._solve(self.lib.ns_nested_solve, rhs, opts, x)
+
+    def adjoint(self, g, opts: SolveOptions | None = None, x=None):
+        """Solve the transposed system with the transposed nested preconditioner."""
+        return self._solve(self.lib.ns_adjoint_solve, g, opts, x)
+
+    def newton_update(self, gamma_dt, dx, y, ydot):
+        self._check(self.lib.ns_newton_update(self.h, float(gamma_dt), _ptr(dx), _ptr(y), _ptr(ydot),
+                                              _stream_handle(self.device)))
+
+    def export_bsr(self, transposed=False):
+        out = torch.empty((self.nnzb, 4, 4), dtype=torch.float64, device=self.device)
+        self._check(self.lib.ns_export_bsr(self.h, int(transposed), _ptr(out), _stream_handle(self.device)))
+        return out
+
+    def export_shat(self):
+        nS = self.sizes[2]
+        rp = np.zeros(self.N + 1, np.int32)
+        col = np.zeros(nS, np.int32)
+        val = torch.empty(nS, dtype=torch.float64, device=self.device)
+        self._check(self.lib.ns_export_shat(self.h, rp.ctypes.data_as(_lib.PI), col.ctypes.data_as(_lib.PI),
+                                            _ptr(val), _stream_handle(self.device)))
+        return rp, col, val
+
+    def outlet_vectors(self):
+        out = torch.empty((max(1, self.n_out), self.N, 3), dtype=torch.float64, device=self.device)
+        self._check(self.lib.ns_export_outlet_vectors(self.h, _ptr(out), _stream_handle(self.device)))
+        return out[:self.n_out]
+
+    def apply(self, op: str, x, opts: SolveOptions | None = None):
+        """One operator of the forward system (see ``ns_op``); returns (y, schedule)."""
+        sizes_in = {"full": 4, "A": 3, "B": 1, "C": 3, "D": 1, "shat": 1, "vcycle_A": 3, "vcycle_S": 1,
+                    "schur": 1, "pscr": 4, "solve_A": 3}
+        sizes_out = {"full": 4, "A": 3, "B": 3, "C": 1, "D": 1, "shat": 1, "vcycle_A": 3, "vcycle_S": 1,
+                     "schur": 1, "pscr": 4, "solve_A": 3}
+        x = self._dev(x).reshape(-1)
+        if x.numel() != sizes_in[op] * self.N:
+            raise ValueError(f"operator {op} takes {sizes_in[op]}N entries")
+        y = torch.empty(sizes_out[op] * self.N, dtype=torch.float64, device=self.device)
+        opts = opts or SolveOptions()
+        co, keep, out = opts.to_c()
+        self._check(self.lib.ns_apply(self.h, _lib.OPS[op], C.byref(co), _ptr(x), _ptr(y),
+                                      _stream_handle(self.device)))
+        return y, out
+
+
+def context_for(case, **kw) -> NsContext:
+    return NsContext(case, **kw).bind()
+
+
+def gen_alpha(rho_inf):
+    am = 0.5 * (3.0 - rho_inf) / (1.0 + rho_inf)
+    af = 1.0 / (1.0 + rho_inf)
+    return am, af, af
+
+
+class NestedSolveFn(torch.autograd.Function):
+    """x(R) = A(R)^{-1} r(R) for one Newton step at a frozen state.
+
+    R enters the tangent through the rank-one term K (m^k = R^k, Sec. 2.5)
+    and the residual through P^k_{n+af} = (1 - alpha_f) P^k_n + alpha_f R^k Q^k
+    with P^k_n held fixed.  backward solves A^T lam = dL/dx with the
+    transposed nested preconditioner and returns
+    dL/dR_k = -(lam_v . a^k) (alpha_f Q^k + alpha_f gamma dt a^k . x_v).
+
+    apply(R, ctx, case, P_n, Q, fwd_opts, adj_opts) -> x  (R: CPU float64 [n_out])
+    """
+
+    @staticmethod
+    def forward(fctx, R, ctx: NsContext, case, P_n, Q, fwd_opts=None, adj_opts=None):
+        Rn = R.detach().cpu().double().numpy()
+        am, af, g = gen_alpha(case.rho_inf)
+        P_af = (1.0 - af) * np.asarray(P_n) + af * Rn * np.asarray(Q)
+        rhs = ctx.assemble(case.v, case.p, case.vdot, rho=case.rho, mu=case.mu, dt=case.dt,
+                           rho_inf=case.rho_inf, m=Rn, P_af=P_af)
+        x, info = ctx.solve(rhs, fwd_opts)
+        fctx.ctx = ctx
+        fctx.af = af
+        fctx.cf = af * g * case.dt
+        fctx.Q = np.asarray(Q, dtype=np.float64)
+        fctx.adj_opts = adj_opts
+        fctx.info = info
+        fctx.save_for_backward(x)
+        return x
+
+    @staticmethod
+    def backward(fctx, grad_x):
+        (x,) = fctx.saved_tensors
+        ctx = fctx.ctx
+        lam, info = ctx.adjoint(grad_x.contiguous(), fctx.adj_opts)
+        s_lam = ctx.rank_one_dots(lam)
+        s_x = ctx.rank_one_dots(x)
+        grad_R = -s_lam * (fctx.af * fctx.Q + fctx.cf * s_x)
+        return (torch.as_tensor(grad_R, dtype=torch.float64), None, None, None, None, None, None)

@@ -1,0 +1,71 @@
+"""CPU checks of the C ABI boundary: the library loads, exports every entry
+point ``include/ns_api.h`` declares, and the host-side symbolic set-up
+(pattern, colouring, aggregates) agrees exactly with the oracle's."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from conftest import ROOT, get_case
+from oracle import amg
+
+
+def declared_functions():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", fn)).read()
+            names |= set(re.findall(r"^\s*(?:ns_status|void|const char\*)\s+(ns_\w+)\s*\(", txt, re.M))
+    return names
+
+
+def test_header_declares_the_three_entry_points():
+    names = declared_functions()
+    assert {"ns_assemble_tangent", "ns_nested_solve", "ns_adjoint_solve"} <= names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1911_10814_amd import _lib
+    lib = _lib.load()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    assert set(_lib.SIGNATURES) == declared_functions()
+
+
+@pytest.mark.parametrize("name", ["cube", "channel2", "pipe_tiny"])
+def test_symbolic_setup_matches_oracle(name):
+    from paper_1911_10814_amd import NsContext
+    c = get_case(name)
+    ctx = NsContext(c)
+    rp, col = ctx.pattern()
+    adj = amg.node_adjacency(c.n_nodes, c.tets)
+    for i in range(c.n_nodes):
+        row = col[rp[i]:rp[i + 1]]
+        assert list(row) == sorted(set(adj[i].tolist()) | {i})
+    aggs = amg.build_aggregates(adj)
+    assert ctx.sizes[5] == len(aggs) + 1
+    for lev, a in enumerate(aggs):
+        assert np.array_equal(ctx.aggregates(lev), a)
+    colors = ctx.colors()
+    for k in range(colors.max() + 1):
+        t = c.tets[colors == k]
+        assert len(np.unique(t)) == t.size  # no shared node inside a colour
+
+
+def test_invalid_mesh_is_rejected():
+    from paper_1911_10814_amd import NsContext, NsError
+    c = get_case("channel2")
+    import copy
+    bad = copy.copy(c)
+    bad.tets = c.tets.copy()
+    bad.tets[0, 0] = c.n_nodes + 5
+    with pytest.raises(NsError, match="out of range"):
+        NsContext(bad)
+    bad2 = copy.copy(c)
+    # two outlets sharing a node
+    bad2.faces = np.concatenate([c.faces, c.faces[:1]])
+    bad2.outlet_ptr = np.array([0, len(c.faces) - 0, len(c.faces) + 1], np.int32)
+    bad2.outlet_ptr[1] = c.outlet_ptr[2]
+    with pytest.raises(NsError, match="share"):
+        NsContext(bad2)
