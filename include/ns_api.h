@@ -215,6 +215,23 @@ ns_status ns_adjoint_solve(ns_ctx* ctx, const ns_solve_opts* opts, const double*
 ns_status ns_newton_update(ns_ctx* ctx, double gamma_dt, const double* d_dx, double* d_y,
                            double* d_ydot, hipStream_t stream);
 
+/* ---- kernel timing ----------------------------------------------------------
+ * Kernel classes that can be timed with HIP events on the solve's stream:
+ *   NS_KT_SPMV_A    the A-operator SpMV (F x + rank-one epilogue), 3x3 blocks
+ *   NS_KT_CHEB_A0   the fused residual + Chebyshev step on the finest level of
+ *                   the A hierarchy
+ *   NS_KT_SPMV_FULL the 4x4 field-split SpMV of the outer FGMRES
+ * ns_kernel_timing(ctx, mask) enables timing of the classes in `mask` (bit
+ * 1 << class) for later solves (0 disables); every timed launch is bracketed
+ * by two events from a pool of 16384 pairs (launches beyond it are not
+ * timed).  ns_kernel_timing_read(ctx, class, out3) returns and clears
+ * out3 = {launches, total milliseconds, algorithmic bytes moved}; the bytes
+ * count one read of the matrix values, column indices and row pointers, one
+ * read of every input vector entry and one write of every output entry. */
+typedef enum { NS_KT_SPMV_A = 0, NS_KT_CHEB_A0 = 1, NS_KT_SPMV_FULL = 2, NS_KT_COUNT = 3 } ns_kernel_class;
+ns_status ns_kernel_timing(ns_ctx* ctx, int32_t mask);
+ns_status ns_kernel_timing_read(ns_ctx* ctx, int32_t kclass, double* h_out3);
+
 /* ---- inspection entry points (used by the tests) -------------------------- */
 
 /* Sizes: [0] n_nodes, [1] nnzb, [2] nnz of S_hat, [3] colours, [4] outlet

@@ -11,6 +11,8 @@ NS_OK, NS_NOT_CONVERGED = 0, 1
 STATUS_NAMES = {0: "NS_OK", 1: "NS_NOT_CONVERGED", -1: "NS_ERR_ARG", -2: "NS_ERR_HIP", -3: "NS_ERR_NAN",
                 -4: "NS_ERR_BREAKDOWN", -5: "NS_ERR_WORKSPACE", -6: "NS_ERR_STATE"}
 
+KERNEL_CLASSES = {"spmv_A": 0, "cheb_A0": 1, "spmv_full": 2}
+
 OPS = {"full": 0, "A": 1, "B": 2, "C": 3, "D": 4, "shat": 5, "vcycle_A": 6, "vcycle_S": 7, "schur": 8,
        "pscr": 9, "solve_A": 10}
 
@@ -70,6 +72,8 @@ SIGNATURES = {
                                    C.POINTER(NsStats), C.c_void_p]),
     "ns_newton_update": (C.c_int, [C.c_void_p, C.c_double, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "ns_query": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
+    "ns_kernel_timing": (C.c_int, [C.c_void_p, C.c_int32]),
+    "ns_kernel_timing_read": (C.c_int, [C.c_void_p, C.c_int32, PD]),
     "ns_export_pattern": (C.c_int, [C.c_void_p, PI, PI]),
     "ns_export_aggregates": (C.c_int, [C.c_void_p, C.c_int32, PI]),
     "ns_export_colors": (C.c_int, [C.c_void_p, PI]),

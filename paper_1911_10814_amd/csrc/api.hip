@@ -95,7 +95,6 @@ void layout(ns_ctx* c, Arena& A) {
     const int mo = dflt(c->opts.max_m, 200), ma = dflt(c->opts.max_m_A, 200), ms = dflt(c->opts.max_m_S, 200);
     const int mmax = std::max(mo, std::max(ma, ms));
     c->d_red = A.take<double>((size_t)(mmax + 4) * kMaxRedBlocks);
-    c->d_counter = A.take<uint32_t>(64);
 
     // AMG patterns (shared by the forward and transposed systems)
     const int L = (int)S.lv.size();
@@ -229,6 +228,43 @@ void h2d(T* d, const std::vector<T>& v, hipStream_t st) {
 }
 
 // ---------------------------------------------------------------------------
+// Kernel timing: bracket launches of selected classes with event pairs
+// ---------------------------------------------------------------------------
+
+constexpr size_t kTimingPairs = 16384;
+
+template <typename F>
+void timed(ns_ctx* c, int cls, double bytes, hipStream_t st, F&& launch) {
+    const size_t used = c->kt_pending.size();
+    if (!(c->kt_mask & (1 << cls)) || used >= kTimingPairs) {
+        launch();
+        return;
+    }
+    while (c->kt_ev.size() < 2 * (used + 1)) {
+        hipEvent_t e;
+        HIPCHK(hipEventCreate(&e));
+        c->kt_ev.push_back(e);
+    }
+    HIPCHK(hipEventRecord(c->kt_ev[2 * used], st));
+    launch();
+    HIPCHK(hipEventRecord(c->kt_ev[2 * used + 1], st));
+    c->kt_pending.emplace_back(cls, bytes);
+}
+
+// after the stream has been synchronised: fold the recorded pairs into the totals
+void timing_collect(ns_ctx* c) {
+    for (size_t i = 0; i < c->kt_pending.size(); ++i) {
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, c->kt_ev[2 * i], c->kt_ev[2 * i + 1]));
+        const int cls = c->kt_pending[i].first;
+        c->kt_acc[cls][0] += 1.0;
+        c->kt_acc[cls][1] += ms;
+        c->kt_acc[cls][2] += c->kt_pending[i].second;
+    }
+    c->kt_pending.clear();
+}
+
+// ---------------------------------------------------------------------------
 // Schedule of Krylov iteration counts
 // ---------------------------------------------------------------------------
 
@@ -290,7 +326,7 @@ void read_status(ns_ctx* c, const double* d_status, int n, hipStream_t st) {
 
 template <typename T>
 double dev_norm(ns_ctx* c, int64_t n, const T* x, double* slot, hipStream_t st) {
-    norm2<T>(n, x, slot, c->d_red, c->d_counter, st);
+    norm2<T>(n, x, slot, c->d_red, st);
     check_launch();
     read_status(c, slot, 1, st);
     return c->h_pinned[0];
@@ -303,23 +339,17 @@ double dev_norm(ns_ctx* c, int64_t n, const T* x, double* slot, hipStream_t st) 
 template <typename T>
 void arnoldi_orth(ns_ctx* c, KrylovWs& kw, int64_t n, int j, T* V, hipStream_t st, double& resid, bool& bd) {
     T* w = V + (int64_t)(j + 1) * n;
-    double* h1 = kw.h;
-    double* h2 = kw.h + (kw.m + 2);
-    multidot<T>(n, j + 1, V, n, w, true, h1, c->d_red, c->d_counter, st);
-    orth_update<T>(n, j + 1, V, n, h1, w, nullptr, c->d_red, c->d_counter, st);
-    multidot<T>(n, j + 1, V, n, w, false, h2, c->d_red, c->d_counter, st);
     GivensArgs ga;
     ga.j = j;
     ga.ldh = kw.m + 1;
-    ga.h1 = h1;
-    ga.h2 = h2;
+    ga.h1 = kw.h;
+    ga.h2 = kw.h + (kw.m + 2);
     ga.H = kw.H;
     ga.cs = kw.cs;
     ga.sn = kw.sn;
     ga.g = kw.g;
     ga.status = kw.status;
-    orth_update<T>(n, j + 1, V, n, h2, w, &ga, c->d_red, c->d_counter, st);
-    scale_by_status<T>(n, w, kw.status, st);
+    arnoldi_cgs2<T>(n, j, V, n, w, kw.h, kw.h + (kw.m + 2), ga, c->d_red, st);
     check_launch();
     read_status(c, kw.status, 4, st);
     resid = c->h_pinned[0];
@@ -430,8 +460,16 @@ struct Nested {
         if (r.slot_of)
             outlet_dot<T>(c->sym.n_out, c->d_optr, c->d_onode, Typed<T>::amsk(c), Typed<T>::ck(c), x, as<T>(c->d_s),
                           K.st);
-        spmv<T>(3, 3, op(0, 0), x, y, T(1), nullptr, T(0), nullptr, r.slot_of ? &r : nullptr, K.st);
+        const double s = sizeof(T);
+        const double bytes = (double)nnzb * (9 * s + 4) + 4.0 * (N + 1) + 6 * s * N;
+        timed(c, NS_KT_SPMV_A, bytes, K.st, [&] {
+            spmv<T>(3, 3, op(0, 0), x, y, T(1), nullptr, T(0), nullptr, r.slot_of ? &r : nullptr, K.st);
+        });
     }
+    // One V-cycle on level l for right-hand side b, result in xout.  On levels
+    // l > 0 the caller has already done the first pre-smoothing step
+    // (x = d = dinv b / theta into L.x0, L.d) inside the fused
+    // residual/restriction kernel of the finer level.
     void vcycle(std::vector<AmgLevelDev>& H, int l, const T* b, T* xout) {
         AmgLevelDev& L = H[l];
         const int bs = L.bs;
@@ -449,28 +487,43 @@ struct Nested {
         T* a = as<T>(L.x0);  // 2*deg-1 ping-pong flips: start in the scratch buffer, end in xout
         T* bb = xout;
         T* d = as<T>(L.d);
+        const bool tme = (l == 0 && bs == 3);
+        const double sz = sizeof(T);
+        // algorithmic bytes: matrix values, columns and row pointers once; reads
+        // x, b, dinv, the extra diagonal and d (when c1 != 0); writes d and x
+        auto cheb = [&](const T* xi, T* xo, T c1, T c2, const int32_t* agg, const T* ec) {
+            const double bytes = (double)L.nnz * (9 * sz + 4) + 4.0 * (L.n + 1) +
+                                 sz * nv * (c1 != T(0) ? 7 : 6);
+            if (tme)
+                timed(c, NS_KT_CHEB_A0, bytes, st,
+                      [&] { cheb_step<T>(bs, M, xi, xo, d, b, dinv, c1, c2, agg, ec, st); });
+            else
+                cheb_step<T>(bs, M, xi, xo, d, b, dinv, c1, c2, agg, ec, st);
+        };
         // pre-smoothing from x = 0
         double rho = 1.0 / sigma;
-        cheb_first<T>(nv, b, dinv, T(1.0 / theta), a, d, st);
+        if (l == 0) cheb_first<T>(nv, b, dinv, T(1.0 / theta), a, d, st);
         for (int i = 1; i < deg; ++i) {
             const double rn = 1.0 / (2.0 * sigma - rho);
-            cheb_step<T>(bs, M, a, bb, d, b, dinv, T(rn * rho), T(2.0 * rn / delta), st);
+            cheb(a, bb, T(rn * rho), T(2.0 * rn / delta), nullptr, nullptr);
             std::swap(a, bb);
             rho = rn;
         }
-        // coarse-grid correction
+        // coarse-grid correction: residual, restriction (+ first coarse step)
         AmgLevelDev& C = H[l + 1];
+        const bool child_coarsest = (l + 2 == (int)H.size());
+        const double cth = 0.5 * (C.lmax + C.lmax / 30.0);
         spmv<T>(bs, bs, M, a, as<T>(L.r), T(-1), b, T(1), nullptr, nullptr, st);
-        restrict_agg<T>(C.n, bs, L.aptr, L.anodes, as<T>(L.r), as<T>(C.b), st);
+        restrict_first<T>(C.n, bs, L.aptr, L.anodes, as<T>(L.r), as<T>(C.b), child_coarsest ? nullptr : as<T>(C.x0),
+                          as<T>(C.d), Typed<T>::dinv(C), child_coarsest ? T(0) : T(1.0 / cth), st);
         vcycle(H, l + 1, as<T>(C.b), as<T>(C.x1));
-        prolong_add<T>(L.n, bs, L.agg, as<T>(C.x1), a, st);
-        // post-smoothing
+        // post-smoothing; the first step applies the prolongated correction
         rho = 1.0 / sigma;
-        cheb_step<T>(bs, M, a, bb, d, b, dinv, T(0), T(1.0 / theta), st);
+        cheb(a, bb, T(0), T(1.0 / theta), L.agg, as<T>(C.x1));
         std::swap(a, bb);
         for (int i = 1; i < deg; ++i) {
             const double rn = 1.0 / (2.0 * sigma - rho);
-            cheb_step<T>(bs, M, a, bb, d, b, dinv, T(rn * rho), T(2.0 * rn / delta), st);
+            cheb(a, bb, T(rn * rho), T(2.0 * rn / delta), nullptr, nullptr);
             std::swap(a, bb);
             rho = rn;
         }
@@ -541,8 +594,11 @@ ns_status fgmres(Ctl& K, const double* b, double* x) {
     auto applyFull = [&](const double* in, double* out, double alpha, const double* z, double beta) {
         if (r1.slot_of)
             outlet_dot<double>(c->sym.n_out, c->d_optr, c->d_onode, c->d_a_msk, c->d_ck, in, c->d_s, st);
-        spmv_full<double>(N, c->d_rp, c->d_col, K.sy->V64, c->sym.g.nnz(), in, out, alpha, z, beta,
-                          r1.slot_of ? &r1 : nullptr, st);
+        const double bytes = (double)c->sym.g.nnz() * (16 * 8 + 4) + 4.0 * (N + 1) + 8.0 * 8 * N + (z ? 32.0 * N : 0);
+        timed(c, NS_KT_SPMV_FULL, bytes, st, [&] {
+            spmv_full<double>(N, c->d_rp, c->d_col, K.sy->V64, c->sym.g.nnz(), in, out, alpha, z, beta,
+                              r1.slot_of ? &r1 : nullptr, st);
+        });
     };
     int forced;
     const int idx = K.sc.begin(forced);
@@ -613,11 +669,11 @@ double power_lambda(ns_ctx* c, const BlockOp<double>& M, int bs, const double* d
     const int64_t n = (int64_t)M.n * bs;
     power_start(n, x, st);
     double* nrm = c->kw_out.status + 6;
-    norm2<double>(n, x, nrm, c->d_red, c->d_counter, st);
+    norm2<double>(n, x, nrm, c->d_red, st);
     scale_by<double>(n, x, nrm, true, x, st);
     for (int it = 0; it < 10; ++it) {
         spmv<double>(bs, bs, M, x, y, 1.0, nullptr, 0.0, dinv, nullptr, st);
-        norm2<double>(n, y, nrm, c->d_red, c->d_counter, st);
+        norm2<double>(n, y, nrm, c->d_red, st);
         scale_by<double>(n, y, nrm, true, x, st);
     }
     check_launch();
@@ -728,6 +784,7 @@ ns_status run_solve(ns_ctx* c, int which, const ns_solve_opts* opts, const doubl
     ns_status rs = K.o.precision == NS_FP32_INNER ? fgmres<float>(K, b, x) : fgmres<double>(K, b, x);
     HIPCHK(hipStreamSynchronize(st));
     auto t2 = std::chrono::steady_clock::now();
+    timing_collect(c);
     K.stats.setup_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
     K.stats.solve_ms = std::chrono::duration<double, std::milli>(t2 - t1).count();
     K.stats.n_calls = (int)K.sc.log.size();
@@ -839,7 +896,6 @@ ns_status ns_ctx_bind(ns_ctx* c, void* ws, size_t bytes, hipStream_t st) {
             h2d(a.aptr, ls.aptr, st);
             h2d(a.anodes, ls.anodes, st);
         }
-        fill<uint32_t>(64, 0u, c->d_counter, st);
         // outlet vectors a^k (geometry only)
         const int nslot = (int)S.onode.size();
         fill<double>(std::max(1, 3 * nslot), 0.0, c->d_a_raw, st);
@@ -858,6 +914,7 @@ ns_status ns_ctx_bind(ns_ctx* c, void* ws, size_t bytes, hipStream_t st) {
 void ns_ctx_destroy(ns_ctx* c) {
     if (!c) return;
     if (c->h_pinned) (void)hipHostFree(c->h_pinned);
+    for (hipEvent_t e : c->kt_ev) (void)hipEventDestroy(e);
     delete c;
 }
 
@@ -993,6 +1050,21 @@ ns_status ns_newton_update(ns_ctx* c, double gamma_dt, const double* d_dx, doubl
         check_launch();
         return NS_OK;
     });
+}
+
+ns_status ns_kernel_timing(ns_ctx* c, int32_t mask) {
+    if (!c || mask < 0 || mask >= (1 << NS_KT_COUNT)) return NS_ERR_ARG;
+    c->kt_mask = mask;
+    return NS_OK;
+}
+
+ns_status ns_kernel_timing_read(ns_ctx* c, int32_t cls, double* out) {
+    if (!c || !out || cls < 0 || cls >= NS_KT_COUNT) return NS_ERR_ARG;
+    for (int i = 0; i < 3; ++i) {
+        out[i] = c->kt_acc[cls][i];
+        c->kt_acc[cls][i] = 0.0;
+    }
+    return NS_OK;
 }
 
 ns_status ns_query(const ns_ctx* c, int64_t* h) {

@@ -165,7 +165,6 @@ struct ns_ctx {
     float* d_ck32 = nullptr;
     double* d_s = nullptr;       // [n_out] rank-one dot results
     double* d_red = nullptr;     // reduction partials
-    uint32_t* d_counter = nullptr;
     ns::SystemDev sys[2];        // 0: forward, 1: transposed
     ns::KrylovWs kw_out, kw_A, kw_S;
     // P_SCR / Algorithm 2 temporaries (FP64-sized)
@@ -177,5 +176,10 @@ struct ns_ctx {
     uint64_t version = 0;        // incremented by every assembly
     bool assembled = false;
     double c_f = 0.0;            // alpha_f gamma dt of the last assembly
+    // kernel timing (HIP event pairs around launches of selected classes)
+    int32_t kt_mask = 0;
+    std::vector<hipEvent_t> kt_ev;           // pool: 2 events per timed launch
+    std::vector<std::pair<int, double>> kt_pending;  // (class, bytes) per used pair
+    double kt_acc[3][3] = {{0}};             // per class: launches, ms, bytes
     std::vector<double> ck_host;
 };

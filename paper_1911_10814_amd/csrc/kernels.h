@@ -53,23 +53,21 @@ void fill(int64_t n, T val, T* y, hipStream_t st);
 template <typename T>
 void mul(int64_t n, const T* a, const T* x, T* y, hipStream_t st);  // y = a .* x
 
-// Arnoldi step support.  Dot results go to `h` (FP64), reductions use the
-// partial buffer `red` and `counter` (last block finalises).
-template <typename T>
-void multidot(int64_t n, int k, const T* V, int64_t ldv, const T* w, bool with_self, double* h, double* red,
-              uint32_t* counter, hipStream_t st);
+// One CGS2 Arnoldi step: w (= V_{j+1}, holding P^{-1} M v_j) is orthogonalised
+// against V_0..V_j by two classical Gram-Schmidt passes, the Hessenberg
+// column j and Givens rotation are updated on the device (status[0] =
+// |g_{j+1}|, [1] = breakdown flag, [2] = 1/h_{j+1,j}, [3] = ||w_pre||), and
+// w is normalised.  h1 [j+2] / h2 [j+1] receive the dot products of the two
+// passes (h1[j+1] = ||w_pre||^2); `red` holds the per-block partial sums.
 struct GivensArgs {
     int j = 0, ldh = 0;
-    const double* h1 = nullptr;  // [j+2] pass-1 dots (h1[j+1] = ||w_pre||^2)
-    const double* h2 = nullptr;  // [j+1] pass-2 dots
+    const double* h1 = nullptr;
+    const double* h2 = nullptr;
     double *H = nullptr, *cs = nullptr, *sn = nullptr, *g = nullptr, *status = nullptr;
 };
-// w -= V h; if givens != nullptr also ||w||^2 and the Givens update (last block)
 template <typename T>
-void orth_update(int64_t n, int k, const T* V, int64_t ldv, const double* h, T* w, const GivensArgs* givens,
-                 double* red, uint32_t* counter, hipStream_t st);
-template <typename T>
-void scale_by_status(int64_t n, T* w, const double* status, hipStream_t st);  // w *= status[2]
+void arnoldi_cgs2(int64_t n, int j, const T* V, int64_t ldv, T* w, double* h1, double* h2, const GivensArgs& ga,
+                  double* red, hipStream_t st);
 void backsolve(int k, int ldh, const double* H, const double* g, double* y, hipStream_t st);
 void init_g(double* g, int len, double beta, hipStream_t st);  // g = [beta, 0, ...]
 // x = (accumulate ? x : 0) + sum_i V_i y_i
@@ -77,7 +75,7 @@ template <typename T, typename TX>
 void combine(int64_t n, int k, const T* V, int64_t ldv, const double* y, TX* x, bool accumulate,
              hipStream_t st);
 template <typename T>
-void norm2(int64_t n, const T* x, double* out, double* red, uint32_t* counter, hipStream_t st);
+void norm2(int64_t n, const T* x, double* out, double* red, hipStream_t st);  // out[0] = ||x|| (device)
 template <typename T>
 void scale_by(int64_t n, const T* x, const double* s, bool inverse, T* y, hipStream_t st);
 
@@ -86,7 +84,10 @@ template <typename T>
 void cheb_first(int64_t n, const T* b, const T* dinv, T c2, T* x, T* d, hipStream_t st);
 template <typename T>
 void cheb_step(int bs, const BlockOp<T>& M, const T* xin, T* xout, T* d, const T* b, const T* dinv, T c1, T c2,
-               hipStream_t st);
+               const int32_t* agg, const T* ec, hipStream_t st);
+template <typename T>
+void restrict_first(int nc, int bs, const int32_t* aptr, const int32_t* anodes, const T* r, T* bc, T* xc, T* dc,
+                    const T* dinvc, T c2c, hipStream_t st);
 template <typename T>
 void restrict_agg(int nc, int bs, const int32_t* aptr, const int32_t* anodes, const T* r, T* bc, hipStream_t st);
 template <typename T>

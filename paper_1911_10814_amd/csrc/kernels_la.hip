@@ -4,6 +4,7 @@
 // pieces, and the per-step set-up numerics.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 
 #include "kernels.h"
@@ -38,20 +39,6 @@ __device__ inline T block_sum(T v, T* lds) {
     if (threadIdx.x == 0) r = lds[0] + lds[1] + lds[2] + lds[3];
     __syncthreads();
     return r;
-}
-
-// Returns true in the block that finishes last (after all partials are visible).
-__device__ inline bool last_block(uint32_t* counter, unsigned total) {
-    __shared__ bool is_last;
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned prev = atomicAdd(counter, 1u);
-        is_last = (prev == total - 1);
-    }
-    __syncthreads();
-    if (is_last) __threadfence();
-    return is_last;
 }
 
 __device__ inline int lower_bound_dev(const int32_t* a, int lo, int hi, int key) {
@@ -259,17 +246,41 @@ void mul(int64_t n, const T* a, const T* x, T* y, hipStream_t st) {
 }
 
 // ---------------------------------------------------------------------------
-// CGS2 pieces.  multidot: h_i = V_i . w for i < k (+ w . w), 8 vectors per
-// blockIdx.y, grid-stride over blockIdx.x; partials [k+1][gx] reduced in a
-// fixed order by the last block (deterministic).
+// CGS2 pieces, without device-scope fences: a kernel writes per-block partial
+// sums and the NEXT kernel (after the kernel boundary made them visible)
+// reduces them in every block in a fixed order (deterministic).
+//   multidot:    partials of V_i . w (i < k) and w . w -> red1[i][G]
+//   orth_update: h = reduce(red1); block 0 stores h; w -= V h;
+//                optionally partials of ||w||^2 -> red2[G2]
+//   finish:      ||w||^2 = reduce(red2); block 0 updates the Hessenberg
+//                column and Givens rotation; every block scales w by 1/||w||
 // ---------------------------------------------------------------------------
 
 constexpr int kDotGroup = 8;
 
+inline unsigned dot_grid(int64_t n, int nv) {
+    int64_t g = (n + 2047) / 2048;
+    int64_t cap = std::max<int64_t>(8, 8192 / std::max(1, nv));
+    g = std::min<int64_t>(std::min<int64_t>(g, 256), cap);
+    return (unsigned)std::max<int64_t>(g, 1);
+}
+
+// every block: out_lds[i] = sum_b red[i*G + b] for i < nv (one wave per value)
+template <typename T>
+__device__ inline void block_reduce_partials(const T* __restrict__ red, int nv, unsigned G, T* out_lds) {
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int i = wv; i < nv; i += kBlock / 64) {
+        T s = 0;
+        for (unsigned b = lane; b < G; b += 64) s += red[(int64_t)i * G + b];
+        s = wave_sum(s);
+        if (lane == 0) out_lds[i] = s;
+    }
+    __syncthreads();
+}
+
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_multidot(int64_t n, int k, const T* __restrict__ V, int64_t ldv,
-                                                     const T* __restrict__ w, int with_self, double* h, T* red,
-                                                     uint32_t* counter) {
+                                                     const T* __restrict__ w, int with_self, T* __restrict__ red) {
     __shared__ T lds[4];
     const int nv = k + with_self;
     const int i0 = blockIdx.y * kDotGroup;
@@ -291,24 +302,14 @@ __global__ __launch_bounds__(kBlock) void k_multidot(int64_t n, int k, const T* 
         T s = block_sum(acc[q], lds);
         if (threadIdx.x == 0) red[(int64_t)i * gridDim.x + blockIdx.x] = s;
     }
-    if (last_block(counter, gridDim.x * gridDim.y)) {
-        const volatile T* vr = red;
-        for (int i = threadIdx.x; i < nv; i += kBlock) {
-            T s = 0;
-            for (unsigned b = 0; b < gridDim.x; ++b) s += vr[(int64_t)i * gridDim.x + b];
-            h[i] = (double)s;
-        }
-        if (threadIdx.x == 0) *counter = 0;
-    }
 }
 
 template <typename T>
-void multidot(int64_t n, int k, const T* V, int64_t ldv, const T* w, bool with_self, double* h, double* red,
-              uint32_t* counter, hipStream_t st) {
+void multidot(int64_t n, int k, const T* V, int64_t ldv, const T* w, bool with_self, T* red, unsigned G,
+              hipStream_t st) {
     const int nv = k + (with_self ? 1 : 0);
-    dim3 grid(red_grid(n), (nv + kDotGroup - 1) / kDotGroup);
-    hipLaunchKernelGGL((k_multidot<T>), grid, dim3(kBlock), 0, st, n, k, V, ldv, w, with_self ? 1 : 0, h,
-                       reinterpret_cast<T*>(red), counter);
+    dim3 grid(G, (nv + kDotGroup - 1) / kDotGroup);
+    hipLaunchKernelGGL((k_multidot<T>), grid, dim3(kBlock), 0, st, n, k, V, ldv, w, with_self ? 1 : 0, red);
 }
 
 // Givens update of Hessenberg column j (FP64, one thread).
@@ -343,60 +344,79 @@ __device__ void givens_step(const GivensArgs& a, double hn2) {
     a.status[3] = wpre;
 }
 
-// w -= sum_i V_i h_i; optional ||w||^2 + Givens (last block)
+// h = reduce(red1) (every block); block 0 stores h (FP64); w -= sum_i V_i h_i;
+// optional partials of ||w||^2 into red2[blockIdx.x].
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_orth_update(int64_t n, int k, const T* __restrict__ V, int64_t ldv,
-                                                        const double* __restrict__ h, T* __restrict__ w,
-                                                        int do_givens, GivensArgs ga, T* red, uint32_t* counter) {
-    __shared__ T hs[256];
+__global__ __launch_bounds__(kBlock) void k_orth_update(int64_t n, int k, int nv, const T* __restrict__ V,
+                                                        int64_t ldv, const T* __restrict__ red1, unsigned G,
+                                                        double* __restrict__ hout, T* __restrict__ w,
+                                                        T* __restrict__ red2) {
+    extern __shared__ char smem[];
+    T* hs = reinterpret_cast<T*>(smem);
     __shared__ T lds[4];
+    block_reduce_partials<T>(red1, nv, G, hs);
+    if (blockIdx.x == 0)
+        for (int i = threadIdx.x; i < nv; i += kBlock) hout[i] = (double)hs[i];
     T acc = 0;
-    for (int c0 = 0; c0 < k; c0 += 256) {
-        // process vectors in chunks of 256 staged in LDS
-        const int cnt = min(256, k - c0);
-        __syncthreads();
-        if ((int)threadIdx.x < cnt) hs[threadIdx.x] = (T)h[c0 + threadIdx.x];
-        __syncthreads();
-        for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < n; t += (int64_t)gridDim.x * kBlock) {
-            T s = 0;
-            for (int i = 0; i < cnt; ++i) s += V[(c0 + i) * ldv + t] * hs[i];
-            w[t] -= s;
-        }
+    for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < n; t += (int64_t)gridDim.x * kBlock) {
+        T s = 0;
+        for (int i = 0; i < k; ++i) s += V[i * ldv + t] * hs[i];
+        const T wn = w[t] - s;
+        w[t] = wn;
+        acc += wn * wn;
     }
-    if (!do_givens) return;
-    for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < n; t += (int64_t)gridDim.x * kBlock)
-        acc += w[t] * w[t];
-    T s = block_sum(acc, lds);
-    if (threadIdx.x == 0) red[blockIdx.x] = s;
-    if (last_block(counter, gridDim.x)) {
-        if (threadIdx.x == 0) {
-            const volatile T* vr = red;
-            T tot = 0;
-            for (unsigned b = 0; b < gridDim.x; ++b) tot += vr[b];
-            givens_step(ga, (double)tot);
-            *counter = 0;
-        }
+    if (red2) {
+        T s = block_sum(acc, lds);
+        if (threadIdx.x == 0) red2[blockIdx.x] = s;
     }
 }
 
-template <typename T>
-void orth_update(int64_t n, int k, const T* V, int64_t ldv, const double* h, T* w, const GivensArgs* givens,
-                 double* red, uint32_t* counter, hipStream_t st) {
-    GivensArgs ga = givens ? *givens : GivensArgs{};
-    hipLaunchKernelGGL((k_orth_update<T>), dim3(red_grid(n)), dim3(kBlock), 0, st, n, k, V, ldv, h, w,
-                       givens ? 1 : 0, ga, reinterpret_cast<T*>(red), counter);
+inline unsigned orth_grid(int64_t n) {
+    int64_t g = (n + kBlock * 4 - 1) / (kBlock * 4);
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(g, 1024));
 }
 
 template <typename T>
-__global__ void k_scale_status(int64_t n, T* w, const double* status) {
-    if (status[1] != 0.0) return;
-    const T s = (T)status[2];
-    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) w[i] *= s;
+void orth_update(int64_t n, int k, int nv, const T* V, int64_t ldv, const T* red1, unsigned G, double* hout, T* w,
+                 T* red2, hipStream_t st) {
+    hipLaunchKernelGGL((k_orth_update<T>), dim3(orth_grid(n)), dim3(kBlock), nv * sizeof(T), st, n, k, nv, V, ldv,
+                       red1, G, hout, w, red2);
 }
+
+// ||w||^2 = reduce(red2); Givens update (block 0); w *= 1/||w|| unless breakdown
 template <typename T>
-void scale_by_status(int64_t n, T* w, const double* status, hipStream_t st) {
-    hipLaunchKernelGGL((k_scale_status<T>), dim3(std::min<int64_t>(grid_for(n), 4096)), dim3(kBlock), 0, st, n, w,
-                       status);
+__global__ __launch_bounds__(kBlock) void k_finish(int64_t n, T* __restrict__ w, const T* __restrict__ red2,
+                                                   unsigned G2, GivensArgs ga) {
+    __shared__ T tot[1];
+    block_reduce_partials<T>(red2, 1, G2, tot);
+    const double hn2 = (double)tot[0];
+    if (blockIdx.x == 0 && threadIdx.x == 0) givens_step(ga, hn2);
+    const double hn = sqrt(hn2);
+    const double wpre = sqrt(ga.h1[ga.j + 1]);
+    if (!(hn > 1e-14 * wpre)) return;
+    const T s = (T)(1.0 / hn);
+    for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < n; t += (int64_t)gridDim.x * kBlock) w[t] *= s;
+}
+
+template <typename T>
+void finish_step(int64_t n, T* w, const T* red2, unsigned G2, const GivensArgs& ga, hipStream_t st) {
+    hipLaunchKernelGGL((k_finish<T>), dim3(orth_grid(n)), dim3(kBlock), 0, st, n, w, red2, G2, ga);
+}
+
+template <typename T>
+void arnoldi_cgs2(int64_t n, int j, const T* V, int64_t ldv, T* w, double* h1, double* h2, const GivensArgs& ga,
+                  double* red, hipStream_t st) {
+    const int k = j + 1;
+    T* r1 = reinterpret_cast<T*>(red);
+    const unsigned G1 = dot_grid(n, k + 1);
+    T* r2 = r1 + (int64_t)(k + 1) * G1;
+    const unsigned G2 = dot_grid(n, k);
+    T* r3 = r2 + (int64_t)k * G2;
+    multidot<T>(n, k, V, ldv, w, true, r1, G1, st);
+    orth_update<T>(n, k, k + 1, V, ldv, r1, G1, h1, w, nullptr, st);
+    multidot<T>(n, k, V, ldv, w, false, r2, G2, st);
+    orth_update<T>(n, k, k, V, ldv, r2, G2, h2, w, r3, st);
+    finish_step<T>(n, w, r3, orth_grid(n), ga, st);
 }
 
 __global__ void k_init_g(double* g, int len, double beta) {
@@ -438,32 +458,31 @@ __global__ __launch_bounds__(kBlock) void k_combine(int64_t n, int k, const T* _
 }
 template <typename T, typename TX>
 void combine(int64_t n, int k, const T* V, int64_t ldv, const double* y, TX* x, bool accumulate, hipStream_t st) {
-    hipLaunchKernelGGL((k_combine<T, TX>), dim3(red_grid(n)), dim3(kBlock), 0, st, n, k, V, ldv, y, x,
+    hipLaunchKernelGGL((k_combine<T, TX>), dim3(orth_grid(n)), dim3(kBlock), 0, st, n, k, V, ldv, y, x,
                        accumulate ? 1 : 0);
 }
 
+// ||x||: partials, then a one-block finalisation
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_norm2(int64_t n, const T* x, double* out, T* red, uint32_t* counter) {
+__global__ __launch_bounds__(kBlock) void k_norm2_part(int64_t n, const T* x, T* red) {
     __shared__ T lds[4];
     T acc = 0;
     for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < n; t += (int64_t)gridDim.x * kBlock)
         acc += x[t] * x[t];
     T s = block_sum(acc, lds);
     if (threadIdx.x == 0) red[blockIdx.x] = s;
-    if (last_block(counter, gridDim.x)) {
-        if (threadIdx.x == 0) {
-            const volatile T* vr = red;
-            T tot = 0;
-            for (unsigned b = 0; b < gridDim.x; ++b) tot += vr[b];
-            out[0] = sqrt((double)tot);
-            *counter = 0;
-        }
-    }
 }
 template <typename T>
-void norm2(int64_t n, const T* x, double* out, double* red, uint32_t* counter, hipStream_t st) {
-    hipLaunchKernelGGL((k_norm2<T>), dim3(red_grid(n)), dim3(kBlock), 0, st, n, x, out, reinterpret_cast<T*>(red),
-                       counter);
+__global__ __launch_bounds__(kBlock) void k_norm2_fin(const T* red, unsigned G, double* out) {
+    __shared__ T tot[1];
+    block_reduce_partials<T>(red, 1, G, tot);
+    if (threadIdx.x == 0) out[0] = sqrt((double)tot[0]);
+}
+template <typename T>
+void norm2(int64_t n, const T* x, double* out, double* red, hipStream_t st) {
+    const unsigned G = orth_grid(n);
+    hipLaunchKernelGGL((k_norm2_part<T>), dim3(G), dim3(kBlock), 0, st, n, x, reinterpret_cast<T*>(red));
+    hipLaunchKernelGGL((k_norm2_fin<T>), dim3(1), dim3(kBlock), 0, st, reinterpret_cast<const T*>(red), G, out);
 }
 
 template <typename T>
@@ -497,11 +516,14 @@ void cheb_first(int64_t n, const T* b, const T* dinv, T c2, T* x, T* d, hipStrea
                        dinv, c2, x, d);
 }
 
-// Fused residual + Chebyshev update: r = b - M xin; d = c1 d + c2 dinv r; xout = xin + d
+// Fused residual + Chebyshev update: r = b - M x; d = c1 d + c2 dinv r; xout = x + d,
+// where x = xin, or x = xin + P ec (prolongation of the coarse correction ec
+// through the aggregate map) when agg != nullptr.
 template <typename T, int BS, int W>
 __global__ __launch_bounds__(kBlock) void k_cheb_step(BlockOp<T> M, const T* __restrict__ xin, T* __restrict__ xout,
                                                       T* __restrict__ d, const T* __restrict__ b,
-                                                      const T* __restrict__ dinv, T c1, T c2) {
+                                                      const T* __restrict__ dinv, T c1, T c2,
+                                                      const int32_t* __restrict__ agg, const T* __restrict__ ec) {
     const int64_t tid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const int row = (int)(tid / W);
     const int lane = threadIdx.x % W;
@@ -514,8 +536,14 @@ __global__ __launch_bounds__(kBlock) void k_cheb_step(BlockOp<T> M, const T* __r
         for (int k = M.rp[row] + lane; k < k1; k += W) {
             const int j = M.col[k];
             T xj[BS];
+            if (agg) {
+                const int64_t J = agg[j];
 #pragma unroll
-            for (int c = 0; c < BS; ++c) xj[c] = xin[(int64_t)BS * j + c];
+                for (int c = 0; c < BS; ++c) xj[c] = xin[(int64_t)BS * j + c] + ec[BS * J + c];
+            } else {
+#pragma unroll
+                for (int c = 0; c < BS; ++c) xj[c] = xin[(int64_t)BS * j + c];
+            }
 #pragma unroll
             for (int r = 0; r < BS; ++r)
 #pragma unroll
@@ -532,23 +560,52 @@ __global__ __launch_bounds__(kBlock) void k_cheb_step(BlockOp<T> M, const T* __r
     for (int r = 1; r < BS; ++r)
         if (lane == r) s = acc[r];
     const int64_t i = (int64_t)BS * row + lane;
-    if (M.dextra) s += M.dextra[i] * xin[i];
+    T xi = xin[i];
+    if (agg) xi += ec[(int64_t)BS * agg[row] + lane];
+    if (M.dextra) s += M.dextra[i] * xi;
     const T ri = b[i] - s;
     T di = c2 * dinv[i] * ri;
     if (c1 != T(0)) di += c1 * d[i];
     d[i] = di;
-    xout[i] = xin[i] + di;
+    xout[i] = xi + di;
 }
 
 template <typename T>
 void cheb_step(int bs, const BlockOp<T>& M, const T* xin, T* xout, T* d, const T* b, const T* dinv, T c1, T c2,
-               hipStream_t st) {
+               const int32_t* agg, const T* ec, hipStream_t st) {
     if (bs == 3)
         hipLaunchKernelGGL((k_cheb_step<T, 3, 8>), dim3(grid_for((int64_t)M.n * 8)), dim3(kBlock), 0, st, M, xin,
-                           xout, d, b, dinv, c1, c2);
+                           xout, d, b, dinv, c1, c2, agg, ec);
     else
         hipLaunchKernelGGL((k_cheb_step<T, 1, 16>), dim3(grid_for((int64_t)M.n * 16)), dim3(kBlock), 0, st, M, xin,
-                           xout, d, b, dinv, c1, c2);
+                           xout, d, b, dinv, c1, c2, agg, ec);
+}
+
+// Restriction bc = P^T r of a precomputed residual; when xc != nullptr also
+// the first Chebyshev step of the coarse level from a zero guess:
+// xc = dc = c2c dinvc bc.
+template <typename T>
+__global__ void k_restrict_first(int nc, int bs, const int32_t* __restrict__ aptr,
+                                 const int32_t* __restrict__ anodes, const T* __restrict__ r, T* __restrict__ bc,
+                                 T* __restrict__ xc, T* __restrict__ dc, const T* __restrict__ dinvc, T c2c) {
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= (int64_t)nc * bs) return;
+    const int I = (int)(t / bs), c = (int)(t % bs);
+    T s = 0;
+    for (int q = aptr[I]; q < aptr[I + 1]; ++q) s += r[(int64_t)bs * anodes[q] + c];
+    bc[t] = s;
+    if (xc) {
+        const T di = c2c * dinvc[t] * s;
+        xc[t] = di;
+        dc[t] = di;
+    }
+}
+
+template <typename T>
+void restrict_first(int nc, int bs, const int32_t* aptr, const int32_t* anodes, const T* r, T* bc, T* xc, T* dc,
+                    const T* dinvc, T c2c, hipStream_t st) {
+    hipLaunchKernelGGL((k_restrict_first<T>), dim3(grid_for((int64_t)nc * bs)), dim3(kBlock), 0, st, nc, bs, aptr,
+                       anodes, r, bc, xc, dc, dinvc, c2c);
 }
 
 template <typename T>
@@ -847,22 +904,21 @@ void newton_update(int64_t n, double gdt, const double* dx, double* y, double* y
     template void axpby<T>(int64_t, T, const T*, T, const T*, T*, hipStream_t);                                      \
     template void fill<T>(int64_t, T, T*, hipStream_t);                                                              \
     template void mul<T>(int64_t, const T*, const T*, T*, hipStream_t);                                              \
-    template void multidot<T>(int64_t, int, const T*, int64_t, const T*, bool, double*, double*, uint32_t*,          \
-                              hipStream_t);                                                                          \
-    template void orth_update<T>(int64_t, int, const T*, int64_t, const double*, T*, const GivensArgs*, double*,     \
-                                 uint32_t*, hipStream_t);                                                            \
-    template void scale_by_status<T>(int64_t, T*, const double*, hipStream_t);                                       \
-    template void norm2<T>(int64_t, const T*, double*, double*, uint32_t*, hipStream_t);                            \
+    template void arnoldi_cgs2<T>(int64_t, int, const T*, int64_t, T*, double*, double*, const GivensArgs&, double*,  \
+                                  hipStream_t);                                                                      \
+    template void norm2<T>(int64_t, const T*, double*, double*, hipStream_t);                                        \
     template void scale_by<T>(int64_t, const T*, const double*, bool, T*, hipStream_t);                             \
     template void cheb_first<T>(int64_t, const T*, const T*, T, T*, T*, hipStream_t);                                \
-    template void cheb_step<T>(int, const BlockOp<T>&, const T*, T*, T*, const T*, const T*, T, T, hipStream_t);     \
+    template void cheb_step<T>(int, const BlockOp<T>&, const T*, T*, T*, const T*, const T*, T, T, const int32_t*,   \
+                               const T*, hipStream_t);                                                               \
+    template void restrict_first<T>(int, int, const int32_t*, const int32_t*, const T*, T*, T*, T*, const T*, T,      \
+                                    hipStream_t);                                                                     \
     template void restrict_agg<T>(int, int, const int32_t*, const int32_t*, const T*, T*, hipStream_t);              \
     template void prolong_add<T>(int, int, const int32_t*, const T*, T*, hipStream_t);                               \
     template void dense_gemv<T>(int, const double*, const T*, T*, hipStream_t);
 
 NS_INST(double)
 NS_INST(float)
-template void fill<uint32_t>(int64_t, uint32_t, uint32_t*, hipStream_t);
 template void convert<double, float>(int64_t, const double*, float*, hipStream_t);
 template void convert<float, double>(int64_t, const float*, double*, hipStream_t);
 template void convert<double, double>(int64_t, const double*, double*, hipStream_t);

@@ -221,6 +221,19 @@ class NsContext:
         self._check(self.lib.ns_newton_update(self.h, float(gamma_dt), _ptr(dx), _ptr(y), _ptr(ydot),
                                               _stream_handle(self.device)))
 
+    def kernel_timing(self, classes=()):
+        """Time launches of the given kernel classes (see ``ns_kernel_class``) in later solves."""
+        mask = 0
+        for k in classes:
+            mask |= 1 << _lib.KERNEL_CLASSES[k]
+        self._check(self.lib.ns_kernel_timing(self.h, mask))
+
+    def kernel_timing_read(self, cls):
+        """(launches, total ms, algorithmic bytes) of a kernel class since the last read."""
+        out = (C.c_double * 3)()
+        self._check(self.lib.ns_kernel_timing_read(self.h, _lib.KERNEL_CLASSES[cls], out))
+        return int(out[0]), float(out[1]), float(out[2])
+
     def export_bsr(self, transposed=False):
         out = torch.empty((self.nnzb, 4, 4), dtype=torch.float64, device=self.device)
         self._check(self.lib.ns_export_bsr(self.h, int(transposed), _ptr(out), _stream_handle(self.device)))
