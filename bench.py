@@ -131,7 +131,6 @@ def main():
     for _ in range(args.warmup):
         step()
         print("[bench] warm-up step done", file=sys.stderr, flush=True)
-    ctx.kernel_timing(("spmv_A", "cheb_A0", "spmv_full"))
     torch.cuda.synchronize()
     times = []
     t_start = time.perf_counter()
@@ -143,6 +142,11 @@ def main():
               file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t_total = time.perf_counter() - t_start
+    # per-launch kernel durations with HIP events on the solver's stream: one
+    # more step with the timed kernel classes bracketed by event pairs (such a
+    # step runs its launches one by one instead of from captured graphs)
+    ctx.kernel_timing(("spmv_A", "cheb_A0", "spmv_full"))
+    step()
     ctx.kernel_timing(())
     kt = {k: ctx.kernel_timing_read(k) for k in ("spmv_A", "cheb_A0", "spmv_full")}
 
@@ -170,7 +174,9 @@ def main():
     # the paper's lighter P_A option (point Jacobi) in both precisions
     variants = {}
     for name, o in (("fp32_inner_jacobi", SolveOptions(precision="fp32_inner", pc_A="jacobi")),
-                    ("fp64_jacobi", SolveOptions(precision="fp64", pc_A="jacobi"))):
+                    ("fp64_jacobi", SolveOptions(precision="fp64", pc_A="jacobi")),
+                    ("fp32_inner_cheb1", SolveOptions(precision="fp32_inner", cheb_degree=1)),
+                    ("fp32_inner_cheb3", SolveOptions(precision="fp32_inner", cheb_degree=3))):
         runs = [solve_fresh(o)[1] for _ in range(args.steps)]
         variants[name] = {"solve_ms": round(statistics.median(r["wall_ms"] for r in runs), 3),
                           "outer_iters": runs[-1]["outer_iters"], "a_iters": runs[-1]["a_iters"],

@@ -118,7 +118,7 @@ typedef struct {
     int32_t m_S, nmax_S;    /* GMRES on S                             [200]   */
     int32_t pc_A;           /* ns_pc: P_A                             [AMG]   */
     int32_t precision;      /* ns_precision                           [FP64]  */
-    int32_t cheb_degree;    /* AMG Chebyshev smoother degree          [2]     */
+    int32_t cheb_degree;    /* AMG Chebyshev smoother degree, 1..8    [1]     */
     int32_t reserved;
     /* Iteration schedule.  If h_sched != NULL, the i-th Krylov call (calls
      * numbered in the order they start: FGMRES, then each GMRES on A or S)

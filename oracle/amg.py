@@ -18,11 +18,12 @@ written definition, which the GPU library implements independently:
 * unsmoothed (piecewise-constant) prolongation, nodal for A (3x3 blocks, the
   three velocity components kept apart) and scalar for S_hat, with the same
   node aggregates; coarse operators are Galerkin products P^T M P;
-* smoother: Chebyshev polynomial of degree ``cheb_degree`` in D^{-1} M (D the
-  point diagonal) on [lambda/30, 1.1 lambda], lambda from 10 power iterations
-  on D^{-1} M from the start vector x_i = 0.5 + ((i * 2654435761) mod 2^32)/2^32;
-  one pre- and one post-smoothing application (zero initial guess before
-  pre-smoothing);
+* smoother: Chebyshev polynomial of degree ``cheb_degree`` (default 1, i.e.
+  damped point Jacobi with weight 1/theta) in D^{-1} M (D the point diagonal)
+  on [lambda/30, lambda] with lambda = 1.1 x the estimate from 10 power
+  iterations on D^{-1} M from the start vector
+  x_i = 0.5 + ((i * 2654435761) mod 2^32)/2^32; one pre- and one
+  post-smoothing application (zero initial guess before pre-smoothing);
 * coarsest level: dense LU solve in FP64.
 """
 from __future__ import annotations
@@ -127,7 +128,7 @@ def chebyshev(M, dinv, b, x, degree, lmin, lmax):
 class AMG:
     """V-cycle for M (scipy CSR) with block size ``bs`` on the node aggregates."""
 
-    def __init__(self, M, bs: int, aggs, cheb_degree: int = 2, extra_diag=None):
+    def __init__(self, M, bs: int, aggs, cheb_degree: int = 1, extra_diag=None):
         self.bs = bs
         self.deg = cheb_degree
         M = sp.csr_matrix(M, dtype=np.float64)

@@ -208,7 +208,7 @@ class SolveOpts:
     nmax_A: int = 200
     nmax_S: int = 200
     pc_A: str = "amg"        # "amg" or "jacobi"
-    cheb_degree: int = 2
+    cheb_degree: int = 1
     coarse_nodes: int = 128
     max_levels: int = 16
     atol: float = 1e-50

@@ -11,6 +11,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <functional>
 #include <stdexcept>
@@ -187,6 +188,9 @@ void layout(ns_ctx* c, Arena& A) {
                 if (l == L - 1) {
                     d.inv = A.take<double>((size_t)nv * nv);
                     d.work = A.take<double>((size_t)nv * 2 * nv);
+                } else {
+                    d.coef64 = A.take<double>(kCoefLen);
+                    d.coef32 = A.take<float>(kCoefLen);
                 }
             }
         }
@@ -297,6 +301,7 @@ struct Typed<double> {
     static const double* lv(const AmgLevelDev& d) { return d.v64; }
     static const double* dinv(const AmgLevelDev& d) { return d.dinv64; }
     static const double* dextra(const AmgLevelDev& d) { return d.dextra64; }
+    static const double* coef(const AmgLevelDev& d) { return d.coef64; }
     static const double* amsk(const ns_ctx* c) { return c->d_a_msk; }
     static const double* ck(const ns_ctx* c) { return c->d_ck; }
 };
@@ -306,6 +311,7 @@ struct Typed<float> {
     static const float* lv(const AmgLevelDev& d) { return d.v32; }
     static const float* dinv(const AmgLevelDev& d) { return d.dinv32; }
     static const float* dextra(const AmgLevelDev& d) { return d.dextra32; }
+    static const float* coef(const AmgLevelDev& d) { return d.coef32; }
     static const float* amsk(const ns_ctx* c) { return c->d_a_msk32; }
     static const float* ck(const ns_ctx* c) { return c->d_ck32; }
 };
@@ -324,21 +330,54 @@ void read_status(ns_ctx* c, const double* d_status, int n, hipStream_t st) {
     HIPCHK(hipStreamSynchronize(st));
 }
 
+// host-mapped scalar slots written by kernels: [0..1] Arnoldi status, [8] norms
+constexpr int kMapStatus = 0, kMapNorm = 8;
+
 template <typename T>
 double dev_norm(ns_ctx* c, int64_t n, const T* x, double* slot, hipStream_t st) {
-    norm2<T>(n, x, slot, c->d_red, st);
+    norm2<T>(n, x, slot, c->d_red, st, c->d_mapped + kMapNorm);
     check_launch();
-    read_status(c, slot, 1, st);
-    return c->h_pinned[0];
+    HIPCHK(hipStreamSynchronize(st));
+    return static_cast<volatile double*>(c->h_mapped)[kMapNorm];
 }
 
-// One Arnoldi step on column j: w (already in V_{j+1}) is orthogonalised
-// against V_0..V_j by two classical Gram-Schmidt passes; the Hessenberg column
-// and Givens rotation are updated on the device; returns |g_{j+1}| and the
-// breakdown flag.
+// Run one Arnoldi-step body, captured once into a HIP graph per
+// (kind, system, precision, P_A, Chebyshev degree, j) and replayed afterwards.
+// Every pointer and size the body uses is fixed for the context, and the
+// numeric set-up reaches the kernels through device memory, so a graph stays
+// valid across tangents.  Kernel timing runs the body eagerly.
+template <typename F>
+void run_step(ns_ctx* c, const Ctl& K, int kind, int j, F&& body) {
+    if (!c->use_graphs || c->kt_mask) {
+        body();
+        return;
+    }
+    const int sys = K.sy == &c->sys[0] ? 0 : 1;
+    const auto key = std::make_tuple(kind, sys, K.o.precision, K.o.pc_A, dflt(K.o.cheb_degree, 1), j);
+    auto it = c->graphs.find(key);
+    if (it == c->graphs.end()) {
+        HIPCHK(hipStreamBeginCapture(K.st, hipStreamCaptureModeThreadLocal));
+        try {
+            body();
+        } catch (...) {
+            hipGraph_t g = nullptr;
+            (void)hipStreamEndCapture(K.st, &g);
+            if (g) (void)hipGraphDestroy(g);
+            throw;
+        }
+        hipGraph_t g = nullptr;
+        HIPCHK(hipStreamEndCapture(K.st, &g));
+        hipGraphExec_t ex = nullptr;
+        hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        HIPCHK(e);
+        it = c->graphs.emplace(key, ex).first;
+    }
+    HIPCHK(hipGraphLaunch(it->second, K.st));
+}
+
 template <typename T>
-void arnoldi_orth(ns_ctx* c, KrylovWs& kw, int64_t n, int j, T* V, hipStream_t st, double& resid, bool& bd) {
-    T* w = V + (int64_t)(j + 1) * n;
+void cgs2_launch(ns_ctx* c, KrylovWs& kw, int64_t n, int j, T* V, hipStream_t st, int slot = 0) {
     GivensArgs ga;
     ga.j = j;
     ga.ldh = kw.m + 1;
@@ -349,19 +388,31 @@ void arnoldi_orth(ns_ctx* c, KrylovWs& kw, int64_t n, int j, T* V, hipStream_t s
     ga.sn = kw.sn;
     ga.g = kw.g;
     ga.status = kw.status;
-    arnoldi_cgs2<T>(n, j, V, n, w, kw.h, kw.h + (kw.m + 2), ga, c->d_red, st);
+    ga.hstatus = c->d_mapped + kMapStatus + 2 * slot;
+    arnoldi_cgs2<T>(n, j, V, n, V + (int64_t)(j + 1) * n, kw.h, kw.h + (kw.m + 2), ga, c->d_red, st);
     check_launch();
-    read_status(c, kw.status, 4, st);
-    resid = c->h_pinned[0];
-    bd = c->h_pinned[1] != 0.0;
+}
+
+void read_step_status(ns_ctx* c, KrylovWs& kw, hipStream_t st, double& resid, bool& bd, hipEvent_t ev = nullptr,
+                      int slot = 0) {
+    if (ev)
+        HIPCHK(hipEventSynchronize(ev));
+    else
+        HIPCHK(hipStreamSynchronize(st));
+    const volatile double* h = c->h_mapped + kMapStatus + 2 * slot;
+    resid = h[0];
+    bd = h[1] != 0.0;
     if (!std::isfinite(resid)) throw Fail{NS_ERR_NAN, "residual estimate is not finite"};
 }
 
 // Left-preconditioned GMRES(m) for M x = b from x = 0 (Sec. 3.1; stopping on
 // the preconditioned residual relative to ||P^{-1} b||).
+// kind: graph kind of the Arnoldi step; m_capturable: applyM launches kernels
+// only (no host synchronisation), so the whole step is one graph.
 template <typename T>
 int gmres_left(Ctl& K, KrylovWs& kw, int64_t n, const std::function<void(const T*, T*)>& applyM,
-               const std::function<void(const T*, T*)>& applyP, const T* b, T* x, double rtol, int m, int nmax) {
+               const std::function<void(const T*, T*)>& applyP, const T* b, T* x, double rtol, int m, int nmax,
+               int kind, bool m_capturable) {
     ns_ctx* c = K.c;
     hipStream_t st = K.st;
     int forced;
@@ -384,12 +435,44 @@ int gmres_left(Ctl& K, KrylovWs& kw, int64_t n, const std::function<void(const T
         init_g(kw.g, m + 1, beta, st);
         int k = 0;
         bool finished = false;
+        // Steps of a capturable operator are queued one ahead of the status
+        // read (status slot and event alternate with j), unless the residual
+        // history predicts convergence at the current step.
+        int launched = 0;
+        double r_prev = beta, r_prev2 = -1.0;
+        auto enqueue = [&](int jj) {
+            T* vj = V + (int64_t)jj * n;
+            T* vn = V + (int64_t)(jj + 1) * n;
+            run_step(c, K, kind, jj, [&] {
+                applyM(vj, tmp);
+                applyP(tmp, vn);
+                cgs2_launch<T>(c, kw, n, jj, V, st, jj & 1);
+            });
+            HIPCHK(hipEventRecord(c->step_ev[jj & 1], st));
+            launched = jj + 1;
+        };
         for (int j = 0; j < m; ++j) {
-            applyM(V + (int64_t)j * n, tmp);
-            applyP(tmp, V + (int64_t)(j + 1) * n);
             double resid;
             bool bd;
-            arnoldi_orth<T>(c, kw, n, j, V, st, resid, bd);
+            if (m_capturable) {
+                if (launched == j) enqueue(j);
+                bool ahead = (j + 1 < m) && (total + 2 <= nmax) && (forced < 0 || total + 2 <= forced);
+                if (ahead && forced < 0) {
+                    const double ratio = r_prev2 > 0.0 ? r_prev / r_prev2 : 0.5;
+                    ahead = r_prev * ratio > 2.0 * tol;
+                }
+                if (ahead) enqueue(j + 1);
+                read_step_status(c, kw, st, resid, bd, c->step_ev[j & 1], j & 1);
+                r_prev2 = r_prev;
+                r_prev = resid;
+            } else {
+                applyM(V + (int64_t)j * n, tmp);
+                run_step(c, K, kind, j, [&] {
+                    applyP(tmp, V + (int64_t)(j + 1) * n);
+                    cgs2_launch<T>(c, kw, n, j, V, st);
+                });
+                read_step_status(c, kw, st, resid, bd);
+            }
             ++total;
             k = j + 1;
             const bool done = forced >= 0 ? total >= forced : resid <= tol;
@@ -432,6 +515,7 @@ struct Nested {
         M.v = V() + (4 * r0 + c0) * nnzb;
         M.rs = 4 * nnzb;
         M.cs = nnzb;
+        M.lanes = lanes_for(nnzb, N);
         return M;
     }
     BlockOp<T> level_op(const AmgLevelDev& d) const {
@@ -443,6 +527,7 @@ struct Nested {
         M.rs = d.rstride;
         M.cs = d.cstride;
         M.dextra = Typed<T>::dextra(d);
+        M.lanes = lanes_for(d.nnz, d.n);
         return M;
     }
     RankOne<T> rank_one() const {
@@ -468,8 +553,7 @@ struct Nested {
     }
     // One V-cycle on level l for right-hand side b, result in xout.  On levels
     // l > 0 the caller has already done the first pre-smoothing step
-    // (x = d = dinv b / theta into L.x0, L.d) inside the fused
-    // residual/restriction kernel of the finer level.
+    // (x = d = dinv b / theta into L.x0, L.d) inside the restriction kernel.
     void vcycle(std::vector<AmgLevelDev>& H, int l, const T* b, T* xout) {
         AmgLevelDev& L = H[l];
         const int bs = L.bs;
@@ -479,53 +563,44 @@ struct Nested {
             dense_gemv<T>((int)nv, L.inv, b, xout, st);
             return;
         }
-        const int deg = dflt(K.o.cheb_degree, 2);
+        const int deg = dflt(K.o.cheb_degree, 1);
         const BlockOp<T> M = level_op(L);
         const T* dinv = Typed<T>::dinv(L);
-        const double lmax = L.lmax, lmin = lmax / 30.0;
-        const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin), sigma = theta / delta;
+        const T* coef = Typed<T>::coef(L);
         T* a = as<T>(L.x0);  // 2*deg-1 ping-pong flips: start in the scratch buffer, end in xout
         T* bb = xout;
         T* d = as<T>(L.d);
         const bool tme = (l == 0 && bs == 3);
         const double sz = sizeof(T);
         // algorithmic bytes: matrix values, columns and row pointers once; reads
-        // x, b, dinv, the extra diagonal and d (when c1 != 0); writes d and x
-        auto cheb = [&](const T* xi, T* xo, T c1, T c2, const int32_t* agg, const T* ec) {
-            const double bytes = (double)L.nnz * (9 * sz + 4) + 4.0 * (L.n + 1) +
-                                 sz * nv * (c1 != T(0) ? 7 : 6);
+        // x, b, dinv, the extra diagonal and d (steps after the first); writes d and x
+        auto cheb = [&](const T* xi, T* xo, int step, const int32_t* agg, const T* ec) {
+            const double bytes = (double)L.nnz * (9 * sz + 4) + 4.0 * (L.n + 1) + sz * nv * (step != 0 ? 7 : 6);
             if (tme)
                 timed(c, NS_KT_CHEB_A0, bytes, st,
-                      [&] { cheb_step<T>(bs, M, xi, xo, d, b, dinv, c1, c2, agg, ec, st); });
+                      [&] { cheb_step<T>(bs, M, xi, xo, d, b, dinv, coef, step, agg, ec, st); });
             else
-                cheb_step<T>(bs, M, xi, xo, d, b, dinv, c1, c2, agg, ec, st);
+                cheb_step<T>(bs, M, xi, xo, d, b, dinv, coef, step, agg, ec, st);
         };
         // pre-smoothing from x = 0
-        double rho = 1.0 / sigma;
-        if (l == 0) cheb_first<T>(nv, b, dinv, T(1.0 / theta), a, d, st);
-        for (int i = 1; i < deg; ++i) {
-            const double rn = 1.0 / (2.0 * sigma - rho);
-            cheb(a, bb, T(rn * rho), T(2.0 * rn / delta), nullptr, nullptr);
+        if (l == 0) cheb_first<T>(nv, b, dinv, coef, a, d, st);
+        for (int s = 1; s < deg; ++s) {
+            cheb(a, bb, s, nullptr, nullptr);
             std::swap(a, bb);
-            rho = rn;
         }
         // coarse-grid correction: residual, restriction (+ first coarse step)
         AmgLevelDev& C = H[l + 1];
         const bool child_coarsest = (l + 2 == (int)H.size());
-        const double cth = 0.5 * (C.lmax + C.lmax / 30.0);
         spmv<T>(bs, bs, M, a, as<T>(L.r), T(-1), b, T(1), nullptr, nullptr, st);
         restrict_first<T>(C.n, bs, L.aptr, L.anodes, as<T>(L.r), as<T>(C.b), child_coarsest ? nullptr : as<T>(C.x0),
-                          as<T>(C.d), Typed<T>::dinv(C), child_coarsest ? T(0) : T(1.0 / cth), st);
+                          as<T>(C.d), Typed<T>::dinv(C), child_coarsest ? nullptr : Typed<T>::coef(C), st);
         vcycle(H, l + 1, as<T>(C.b), as<T>(C.x1));
         // post-smoothing; the first step applies the prolongated correction
-        rho = 1.0 / sigma;
-        cheb(a, bb, T(0), T(1.0 / theta), L.agg, as<T>(C.x1));
+        cheb(a, bb, 0, L.agg, as<T>(C.x1));
         std::swap(a, bb);
-        for (int i = 1; i < deg; ++i) {
-            const double rn = 1.0 / (2.0 * sigma - rho);
-            cheb(a, bb, T(rn * rho), T(2.0 * rn / delta), nullptr, nullptr);
+        for (int s = 1; s < deg; ++s) {
+            cheb(a, bb, s, nullptr, nullptr);
             std::swap(a, bb);
-            rho = rn;
         }
     }
     void applyPA(const T* r, T* z) {
@@ -540,7 +615,7 @@ struct Nested {
         return gmres_left<T>(
             K, c->kw_A, 3 * (int64_t)N, [this](const T* in, T* out) { applyA(in, out); },
             [this](const T* in, T* out) { applyPA(in, out); }, b, x, rtol, dflt(K.o.m_A, 200),
-            dflt(K.o.nmax_A, 200));
+            dflt(K.o.nmax_A, 200), 0, true);
     }
     // Algorithm 2: y = D x - C A^{-1} (B x)
     void schur(const T* xp, T* y) {
@@ -556,7 +631,7 @@ struct Nested {
         return gmres_left<T>(
             K, c->kw_S, N, [this](const T* in, T* out) { schur(in, out); },
             [this](const T* in, T* out) { applyPS(in, out); }, b, x, dfltd(K.o.rtol_S, 1e-3), dflt(K.o.m_S, 200),
-            dflt(K.o.nmax_S, 200));
+            dflt(K.o.nmax_S, 200), 1, false);
     }
     // Algorithm 3: y = P_SCR^{-1} s   (s, y: [4N], field-split)
     void scr(const T* s, T* y) {
@@ -631,10 +706,13 @@ ns_status fgmres(Ctl& K, const double* b, double* x) {
                 P.scr(as<T>(c->t_s), as<T>(c->t_yp));
                 convert<T, double>(n, as<T>(c->t_yp), zj, st);
             }
-            applyFull(zj, V + (int64_t)(j + 1) * n, 1.0, nullptr, 0.0);
+            run_step(c, K, 2, j, [&] {
+                applyFull(zj, V + (int64_t)(j + 1) * n, 1.0, nullptr, 0.0);
+                cgs2_launch<double>(c, kw, n, j, V, st);
+            });
             double resid;
             bool bd;
-            arnoldi_orth<double>(c, kw, n, j, V, st, resid, bd);
+            read_step_status(c, kw, st, resid, bd);
             ++total;
             k = j + 1;
             const bool done = forced >= 0 ? total >= forced : resid <= tol;
@@ -717,6 +795,7 @@ void setup_system(ns_ctx* c, SystemDev& y, bool need32, hipStream_t st) {
                 M.rs = d.rstride;
                 M.cs = d.cstride;
                 M.dextra = d.dextra64;
+                M.lanes = lanes_for(d.nnz, d.n);
                 if (l + 1 < L) {
                     d.lmax = 1.1 * power_lambda(c, M, d.bs, d.dinv64, d.x0, d.r, st);
                 } else {
@@ -728,6 +807,7 @@ void setup_system(ns_ctx* c, SystemDev& y, bool need32, hipStream_t st) {
         }
         y.ready = true;
         y.have32 = false;
+        y.coef_deg = 0;
         y.version = c->version;
     }
     if (need32 && !y.have32) {
@@ -749,6 +829,41 @@ void setup_system(ns_ctx* c, SystemDev& y, bool need32, hipStream_t st) {
         check_launch();
         y.have32 = true;
     }
+}
+
+// Chebyshev coefficients of every smoothed level for the requested degree:
+// interval [lmax/30, lmax] of D^{-1} M, theta/delta its centre/half-width.
+void upload_coef(ns_ctx* c, SystemDev& y, int deg, hipStream_t st) {
+    if (deg < 1 || deg > kMaxChebDegree) throw Fail{NS_ERR_ARG, "Chebyshev degree out of range [1, 8]"};
+    if (y.coef_deg == deg) return;
+    std::vector<double> host;
+    std::vector<AmgLevelDev*> lv;
+    for (int h = 0; h < 2; ++h) {
+        std::vector<AmgLevelDev>& H = h == 0 ? y.A : y.S;
+        for (int l = 0; l + 1 < (int)H.size(); ++l) {
+            const double lmax = H[l].lmax, lmin = lmax / 30.0;
+            const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin), sigma = theta / delta;
+            std::vector<double> cf(kCoefLen, 0.0);
+            cf[0] = 1.0 / theta;
+            double rho = 1.0 / sigma;
+            for (int s = 1; s < deg; ++s) {
+                const double rn = 1.0 / (2.0 * sigma - rho);
+                cf[2 * s - 1] = rn * rho;
+                cf[2 * s] = 2.0 * rn / delta;
+                rho = rn;
+            }
+            host.insert(host.end(), cf.begin(), cf.end());
+            lv.push_back(&H[l]);
+        }
+    }
+    for (size_t i = 0; i < lv.size(); ++i) {
+        HIPCHK(hipMemcpyAsync(lv[i]->coef64, host.data() + i * kCoefLen, kCoefLen * sizeof(double),
+                              hipMemcpyHostToDevice, st));
+        convert<double, float>(kCoefLen, lv[i]->coef64, lv[i]->coef32, st);
+    }
+    check_launch();
+    HIPCHK(hipStreamSynchronize(st));  // the host buffer goes out of scope
+    y.coef_deg = deg;
 }
 
 void ensure_transposed(ns_ctx* c, hipStream_t st) {
@@ -775,10 +890,14 @@ ns_status run_solve(ns_ctx* c, int which, const ns_solve_opts* opts, const doubl
     K.sc.replay = K.o.h_sched;
     K.sc.replay_len = K.o.sched_len;
     HIPCHK(hipSetDevice(c->device));
+    HIPCHK(hipStreamSynchronize(st));  // inputs produced on the caller's stream
+    st = c->own;
+    K.st = st;
     auto t0 = std::chrono::steady_clock::now();
     if (which == 1) ensure_transposed(c, st);
     K.sy = &c->sys[which];
     setup_system(c, *K.sy, K.o.precision == NS_FP32_INNER, st);
+    upload_coef(c, *K.sy, dflt(K.o.cheb_degree, 1), st);
     HIPCHK(hipStreamSynchronize(st));
     auto t1 = std::chrono::steady_clock::now();
     ns_status rs = K.o.precision == NS_FP32_INNER ? fgmres<float>(K, b, x) : fgmres<double>(K, b, x);
@@ -905,6 +1024,16 @@ ns_status ns_ctx_bind(ns_ctx* c, void* ws, size_t bytes, hipStream_t st) {
         mask_outlet(nslot, c->d_onode, c->d_mask, c->d_a_raw, c->d_a_msk, st);
         check_launch();
         if (!c->h_pinned) HIPCHK(hipHostMalloc((void**)&c->h_pinned, 64 * sizeof(double), hipHostMallocDefault));
+        if (!c->h_mapped) {
+            HIPCHK(hipHostMalloc((void**)&c->h_mapped, 64 * sizeof(double),
+                                 hipHostMallocMapped | hipHostMallocCoherent));
+            HIPCHK(hipHostGetDevicePointer((void**)&c->d_mapped, c->h_mapped, 0));
+        }
+        if (!c->own) HIPCHK(hipStreamCreateWithFlags(&c->own, hipStreamNonBlocking));
+        for (int e = 0; e < 2; ++e)
+            if (!c->step_ev[e]) HIPCHK(hipEventCreateWithFlags(&c->step_ev[e], hipEventDisableTiming));
+        const char* ng = getenv("NS_NO_GRAPHS");
+        c->use_graphs = !(ng && ng[0] == '1');
         HIPCHK(hipStreamSynchronize(st));
         c->bound = true;
         return NS_OK;
@@ -914,7 +1043,12 @@ ns_status ns_ctx_bind(ns_ctx* c, void* ws, size_t bytes, hipStream_t st) {
 void ns_ctx_destroy(ns_ctx* c) {
     if (!c) return;
     if (c->h_pinned) (void)hipHostFree(c->h_pinned);
+    if (c->h_mapped) (void)hipHostFree(c->h_mapped);
     for (hipEvent_t e : c->kt_ev) (void)hipEventDestroy(e);
+    for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+    for (int e = 0; e < 2; ++e)
+        if (c->step_ev[e]) (void)hipEventDestroy(c->step_ev[e]);
+    if (c->own) (void)hipStreamDestroy(c->own);
     delete c;
 }
 
@@ -1156,6 +1290,8 @@ ns_status ns_apply(ns_ctx* c, int32_t op, const ns_solve_opts* opts, const doubl
         if (!c->assembled) throw Fail{NS_ERR_STATE, "no tangent assembled"};
         if (!d_x || !d_y) throw Fail{NS_ERR_ARG, "null argument"};
         HIPCHK(hipSetDevice(c->device));
+        HIPCHK(hipStreamSynchronize(st));
+        st = c->own;
         Ctl K{};
         K.c = c;
         K.st = st;
@@ -1166,6 +1302,7 @@ ns_status ns_apply(ns_ctx* c, int32_t op, const ns_solve_opts* opts, const doubl
         K.sy = &c->sys[0];
         const bool f32 = K.o.precision == NS_FP32_INNER;
         setup_system(c, c->sys[0], f32, st);
+        upload_coef(c, c->sys[0], dflt(K.o.cheb_degree, 1), st);
         const int N = c->sym.N;
         const int64_t nin[] = {4L * N, 3L * N, N, 3L * N, N, N, 3L * N, N, N, 4L * N, 3L * N};
         const int64_t nout[] = {4L * N, 3L * N, 3L * N, N, N, N, 3L * N, N, N, 4L * N, 3L * N};

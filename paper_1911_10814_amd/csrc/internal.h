@@ -4,7 +4,9 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <map>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "ns_api.h"
@@ -98,6 +100,8 @@ struct AmgLevelDev {
     const double* dextra64 = nullptr;   // extra diagonal (level 0 of A: lumped diag K)
     const float* dextra32 = nullptr;
     double lmax = 0.0;
+    double* coef64 = nullptr;           // Chebyshev step coefficients (device)
+    float* coef32 = nullptr;
     // Galerkin gather lists from the finer level (levels >= 1)
     int32_t *gptr = nullptr, *gidx = nullptr, *qrow = nullptr;
     // restriction/prolongation to the next level
@@ -118,6 +122,7 @@ struct SystemDev {
     double* shat64 = nullptr;  // [nnz S_hat]
     float* shat32 = nullptr;
     std::vector<AmgLevelDev> A, S;   // hierarchies
+    int coef_deg = 0;                // Chebyshev degree the device coefficients belong to
     bool ready = false;              // per-step set-up done for the current tangent
     bool have32 = false;
     uint64_t version = 0;            // tangent version the set-up belongs to
@@ -171,6 +176,8 @@ struct ns_ctx {
     double *t_s = nullptr, *t_yhat = nullptr, *t_tp = nullptr, *t_yp = nullptr, *t_tv = nullptr,
            *t_yv = nullptr, *t_xhat = nullptr, *t_xbar = nullptr, *t_xt = nullptr, *t_r4 = nullptr;
     double* h_pinned = nullptr;  // pinned host scalars
+    double* h_mapped = nullptr;  // pinned, device-mapped host scalars written by kernels
+    double* d_mapped = nullptr;  // device address of h_mapped
     std::vector<double> h_xyz;   // host copies uploaded by ns_ctx_bind
     std::vector<uint8_t> h_mask;
     uint64_t version = 0;        // incremented by every assembly
@@ -181,5 +188,11 @@ struct ns_ctx {
     std::vector<hipEvent_t> kt_ev;           // pool: 2 events per timed launch
     std::vector<std::pair<int, double>> kt_pending;  // (class, bytes) per used pair
     double kt_acc[3][3] = {{0}};             // per class: launches, ms, bytes
+    // library-owned stream (solves run here; graph capture needs a non-default stream)
+    hipStream_t own = nullptr;
+    hipEvent_t step_ev[2] = {nullptr, nullptr};  // completion of queued Arnoldi steps
+    bool use_graphs = true;
+    // captured Arnoldi steps: (kind, system, precision, pc_A, degree, j) -> executable graph
+    std::map<std::tuple<int, int, int, int, int, int>, hipGraphExec_t> graphs;
     std::vector<double> ck_host;
 };

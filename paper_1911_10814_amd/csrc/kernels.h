@@ -27,7 +27,15 @@ struct BlockOp {
     const T* v = nullptr;
     int64_t rs = 0, cs = 0;
     const T* dextra = nullptr;  // optional extra diagonal [BR*n]
+    int lanes = 16;             // lanes per block row (16, 32 or 64), from the mean row length
 };
+
+// lanes per row for a pattern with nnz blocks over n rows: one pass over a
+// typical row, so consecutive rows give contiguous loads across the wavefront
+inline int lanes_for(int64_t nnz, int n) {
+    const double avg = n > 0 ? (double)nnz / n : 0.0;
+    return avg <= 16.0 ? 16 : (avg <= 32.0 ? 32 : 64);
+}
 
 // y = alpha * (M x [+ dextra x] [+ rank one]) + beta * z, then y *= rscale
 template <typename T>
@@ -64,6 +72,7 @@ struct GivensArgs {
     const double* h1 = nullptr;
     const double* h2 = nullptr;
     double *H = nullptr, *cs = nullptr, *sn = nullptr, *g = nullptr, *status = nullptr;
+    double* hstatus = nullptr;  // optional host-mapped copy of status[0..1]
 };
 template <typename T>
 void arnoldi_cgs2(int64_t n, int j, const T* V, int64_t ldv, T* w, double* h1, double* h2, const GivensArgs& ga,
@@ -74,20 +83,25 @@ void init_g(double* g, int len, double beta, hipStream_t st);  // g = [beta, 0, 
 template <typename T, typename TX>
 void combine(int64_t n, int k, const T* V, int64_t ldv, const double* y, TX* x, bool accumulate,
              hipStream_t st);
+// out[0] = ||x|| (device); also hout[0] (host-mapped) when not null
 template <typename T>
-void norm2(int64_t n, const T* x, double* out, double* red, hipStream_t st);  // out[0] = ||x|| (device)
+void norm2(int64_t n, const T* x, double* out, double* red, hipStream_t st, double* hout = nullptr);
 template <typename T>
 void scale_by(int64_t n, const T* x, const double* s, bool inverse, T* y, hipStream_t st);
 
 // AMG kernels
+// Chebyshev coefficients in device memory: coef[0] = 1/theta; step s >= 1
+// uses (c1, c2) = (coef[2s-1], coef[2s]).
+constexpr int kMaxChebDegree = 8;
+constexpr int kCoefLen = 2 * kMaxChebDegree;
 template <typename T>
-void cheb_first(int64_t n, const T* b, const T* dinv, T c2, T* x, T* d, hipStream_t st);
+void cheb_first(int64_t n, const T* b, const T* dinv, const T* coef, T* x, T* d, hipStream_t st);
 template <typename T>
-void cheb_step(int bs, const BlockOp<T>& M, const T* xin, T* xout, T* d, const T* b, const T* dinv, T c1, T c2,
-               const int32_t* agg, const T* ec, hipStream_t st);
+void cheb_step(int bs, const BlockOp<T>& M, const T* xin, T* xout, T* d, const T* b, const T* dinv, const T* coef,
+               int step, const int32_t* agg, const T* ec, hipStream_t st);
 template <typename T>
 void restrict_first(int nc, int bs, const int32_t* aptr, const int32_t* anodes, const T* r, T* bc, T* xc, T* dc,
-                    const T* dinvc, T c2c, hipStream_t st);
+                    const T* dinvc, const T* coefc, hipStream_t st);
 template <typename T>
 void restrict_agg(int nc, int bs, const int32_t* aptr, const int32_t* anodes, const T* r, T* bc, hipStream_t st);
 template <typename T>

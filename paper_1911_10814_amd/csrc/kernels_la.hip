@@ -103,24 +103,37 @@ __global__ __launch_bounds__(kBlock) void k_spmv(BlockOp<T> M, const T* __restri
     y[i] = out;
 }
 
+template <typename T, int BR, int BC>
+void spmv_w(const BlockOp<T>& M, const T* x, T* y, T alpha, const T* z, T beta, const T* rscale,
+            const RankOne<T>& r1, hipStream_t st) {
+    switch (M.lanes) {
+        case 64:
+            hipLaunchKernelGGL((k_spmv<T, BR, BC, 64>), dim3(grid_for((int64_t)M.n * 64)), dim3(kBlock), 0, st, M,
+                               x, y, alpha, z, beta, rscale, r1);
+            break;
+        case 32:
+            hipLaunchKernelGGL((k_spmv<T, BR, BC, 32>), dim3(grid_for((int64_t)M.n * 32)), dim3(kBlock), 0, st, M,
+                               x, y, alpha, z, beta, rscale, r1);
+            break;
+        default:
+            hipLaunchKernelGGL((k_spmv<T, BR, BC, 16>), dim3(grid_for((int64_t)M.n * 16)), dim3(kBlock), 0, st, M,
+                               x, y, alpha, z, beta, rscale, r1);
+    }
+}
+
 template <typename T>
 void spmv(int br, int bc, const BlockOp<T>& M, const T* x, T* y, T alpha, const T* z, T beta, const T* rscale,
           const RankOne<T>* ro, hipStream_t st) {
     RankOne<T> r1 = ro ? *ro : RankOne<T>{};
     if (M.n <= 0) return;
-    if (br == 3 && bc == 3) {
-        hipLaunchKernelGGL((k_spmv<T, 3, 3, 8>), dim3(grid_for((int64_t)M.n * 8)), dim3(kBlock), 0, st, M, x, y,
-                           alpha, z, beta, rscale, r1);
-    } else if (br == 3 && bc == 1) {
-        hipLaunchKernelGGL((k_spmv<T, 3, 1, 8>), dim3(grid_for((int64_t)M.n * 8)), dim3(kBlock), 0, st, M, x, y,
-                           alpha, z, beta, rscale, r1);
-    } else if (br == 1 && bc == 3) {
-        hipLaunchKernelGGL((k_spmv<T, 1, 3, 8>), dim3(grid_for((int64_t)M.n * 8)), dim3(kBlock), 0, st, M, x, y,
-                           alpha, z, beta, rscale, r1);
-    } else {
-        hipLaunchKernelGGL((k_spmv<T, 1, 1, 16>), dim3(grid_for((int64_t)M.n * 16)), dim3(kBlock), 0, st, M, x, y,
-                           alpha, z, beta, rscale, r1);
-    }
+    if (br == 3 && bc == 3)
+        spmv_w<T, 3, 3>(M, x, y, alpha, z, beta, rscale, r1, st);
+    else if (br == 3 && bc == 1)
+        spmv_w<T, 3, 1>(M, x, y, alpha, z, beta, rscale, r1, st);
+    else if (br == 1 && bc == 3)
+        spmv_w<T, 1, 3>(M, x, y, alpha, z, beta, rscale, r1, st);
+    else
+        spmv_w<T, 1, 1>(M, x, y, alpha, z, beta, rscale, r1, st);
 }
 
 // Full field-split 4x4 operator (outer Arnoldi and true residual).
@@ -169,7 +182,7 @@ template <typename T>
 void spmv_full(int n, const int32_t* rp, const int32_t* col, const T* V, int64_t nnzb, const T* x, T* y, T alpha,
                const T* z, T beta, const RankOne<T>* ro, hipStream_t st) {
     RankOne<T> r1 = ro ? *ro : RankOne<T>{};
-    hipLaunchKernelGGL((k_spmv_full<T, 8>), dim3(grid_for((int64_t)n * 8)), dim3(kBlock), 0, st, n, rp, col, V,
+    hipLaunchKernelGGL((k_spmv_full<T, 16>), dim3(grid_for((int64_t)n * 16)), dim3(kBlock), 0, st, n, rp, col, V,
                        nnzb, x, y, alpha, z, beta, r1);
 }
 
@@ -259,7 +272,7 @@ void mul(int64_t n, const T* a, const T* x, T* y, hipStream_t st) {
 constexpr int kDotGroup = 8;
 
 inline unsigned dot_grid(int64_t n, int nv) {
-    int64_t g = (n + 2047) / 2048;
+    int64_t g = (n + 1023) / 1024;
     int64_t cap = std::max<int64_t>(8, 8192 / std::max(1, nv));
     g = std::min<int64_t>(std::min<int64_t>(g, 256), cap);
     return (unsigned)std::max<int64_t>(g, 1);
@@ -342,6 +355,10 @@ __device__ void givens_step(const GivensArgs& a, double hn2) {
     a.status[1] = bd ? 1.0 : 0.0;
     a.status[2] = bd ? 0.0 : 1.0 / hn;
     a.status[3] = wpre;
+    if (a.hstatus) {
+        a.hstatus[0] = a.status[0];
+        a.hstatus[1] = a.status[1];
+    }
 }
 
 // h = reduce(red1) (every block); block 0 stores h (FP64); w -= sum_i V_i h_i;
@@ -368,6 +385,42 @@ __global__ __launch_bounds__(kBlock) void k_orth_update(int64_t n, int k, int nv
     if (red2) {
         T s = block_sum(acc, lds);
         if (threadIdx.x == 0) red2[blockIdx.x] = s;
+    }
+}
+
+// Pass-1 update fused with the pass-2 dot products: h1 = reduce(red1);
+// w -= V h1 over this block's grid-stride slice, then partials of V_i . w over
+// the same slice (written by this block, so no grid synchronisation is
+// needed) into red2[i][blockIdx.x].
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_orth_dot(int64_t n, int k, const T* __restrict__ V, int64_t ldv,
+                                                     const T* __restrict__ red1, unsigned G1, double* __restrict__ h1,
+                                                     T* __restrict__ w, T* __restrict__ red2) {
+    extern __shared__ char smem[];
+    T* hs = reinterpret_cast<T*>(smem);
+    __shared__ T lds[4];
+    block_reduce_partials<T>(red1, k + 1, G1, hs);
+    if (blockIdx.x == 0)
+        for (int i = threadIdx.x; i <= k; i += kBlock) h1[i] = (double)hs[i];
+    for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < n; t += (int64_t)gridDim.x * kBlock) {
+        T s = 0;
+        for (int i = 0; i < k; ++i) s += V[i * ldv + t] * hs[i];
+        w[t] -= s;
+    }
+    for (int i0 = 0; i0 < k; i0 += kDotGroup) {
+        T acc[kDotGroup];
+#pragma unroll
+        for (int q = 0; q < kDotGroup; ++q) acc[q] = 0;
+        for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < n; t += (int64_t)gridDim.x * kBlock) {
+            const T wt = w[t];
+#pragma unroll
+            for (int q = 0; q < kDotGroup; ++q)
+                if (i0 + q < k) acc[q] += V[(i0 + q) * ldv + t] * wt;
+        }
+        for (int q = 0; q < kDotGroup && i0 + q < k; ++q) {
+            T sq = block_sum(acc[q], lds);
+            if (threadIdx.x == 0) red2[(int64_t)(i0 + q) * gridDim.x + blockIdx.x] = sq;
+        }
     }
 }
 
@@ -413,8 +466,8 @@ void arnoldi_cgs2(int64_t n, int j, const T* V, int64_t ldv, T* w, double* h1, d
     const unsigned G2 = dot_grid(n, k);
     T* r3 = r2 + (int64_t)k * G2;
     multidot<T>(n, k, V, ldv, w, true, r1, G1, st);
-    orth_update<T>(n, k, k + 1, V, ldv, r1, G1, h1, w, nullptr, st);
-    multidot<T>(n, k, V, ldv, w, false, r2, G2, st);
+    hipLaunchKernelGGL((k_orth_dot<T>), dim3(G2), dim3(kBlock), (k + 1) * sizeof(T), st, n, k, V, ldv, r1, G1, h1, w,
+                       r2);
     orth_update<T>(n, k, k, V, ldv, r2, G2, h2, w, r3, st);
     finish_step<T>(n, w, r3, orth_grid(n), ga, st);
 }
@@ -473,16 +526,20 @@ __global__ __launch_bounds__(kBlock) void k_norm2_part(int64_t n, const T* x, T*
     if (threadIdx.x == 0) red[blockIdx.x] = s;
 }
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_norm2_fin(const T* red, unsigned G, double* out) {
+__global__ __launch_bounds__(kBlock) void k_norm2_fin(const T* red, unsigned G, double* out, double* hout) {
     __shared__ T tot[1];
     block_reduce_partials<T>(red, 1, G, tot);
-    if (threadIdx.x == 0) out[0] = sqrt((double)tot[0]);
+    if (threadIdx.x == 0) {
+        out[0] = sqrt((double)tot[0]);
+        if (hout) hout[0] = out[0];
+    }
 }
 template <typename T>
-void norm2(int64_t n, const T* x, double* out, double* red, hipStream_t st) {
+void norm2(int64_t n, const T* x, double* out, double* red, hipStream_t st, double* hout) {
     const unsigned G = orth_grid(n);
     hipLaunchKernelGGL((k_norm2_part<T>), dim3(G), dim3(kBlock), 0, st, n, x, reinterpret_cast<T*>(red));
-    hipLaunchKernelGGL((k_norm2_fin<T>), dim3(1), dim3(kBlock), 0, st, reinterpret_cast<const T*>(red), G, out);
+    hipLaunchKernelGGL((k_norm2_fin<T>), dim3(1), dim3(kBlock), 0, st, reinterpret_cast<const T*>(red), G, out,
+                       hout);
 }
 
 template <typename T>
@@ -502,8 +559,17 @@ void scale_by(int64_t n, const T* x, const double* s, bool inverse, T* y, hipStr
 // V-cycle pieces
 // ---------------------------------------------------------------------------
 
+// Chebyshev step coefficients live in device memory: coef[0] = 1/theta (first
+// step: c1 = 0, c2 = 1/theta); step s >= 1: c1 = coef[2s-1], c2 = coef[2s].
 template <typename T>
-__global__ void k_cheb_first(int64_t n, const T* b, const T* dinv, T c2, T* x, T* d) {
+__device__ inline void cheb_coef(const T* coef, int s, T& c1, T& c2) {
+    c1 = s == 0 ? T(0) : coef[2 * s - 1];
+    c2 = s == 0 ? coef[0] : coef[2 * s];
+}
+
+template <typename T>
+__global__ void k_cheb_first(int64_t n, const T* b, const T* dinv, const T* coef, T* x, T* d) {
+    const T c2 = coef[0];
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
         const T di = c2 * dinv[i] * b[i];
         d[i] = di;
@@ -511,9 +577,9 @@ __global__ void k_cheb_first(int64_t n, const T* b, const T* dinv, T c2, T* x, T
     }
 }
 template <typename T>
-void cheb_first(int64_t n, const T* b, const T* dinv, T c2, T* x, T* d, hipStream_t st) {
+void cheb_first(int64_t n, const T* b, const T* dinv, const T* coef, T* x, T* d, hipStream_t st) {
     hipLaunchKernelGGL((k_cheb_first<T>), dim3(std::min<int64_t>(grid_for(n), 65535)), dim3(kBlock), 0, st, n, b,
-                       dinv, c2, x, d);
+                       dinv, coef, x, d);
 }
 
 // Fused residual + Chebyshev update: r = b - M x; d = c1 d + c2 dinv r; xout = x + d,
@@ -522,8 +588,9 @@ void cheb_first(int64_t n, const T* b, const T* dinv, T c2, T* x, T* d, hipStrea
 template <typename T, int BS, int W>
 __global__ __launch_bounds__(kBlock) void k_cheb_step(BlockOp<T> M, const T* __restrict__ xin, T* __restrict__ xout,
                                                       T* __restrict__ d, const T* __restrict__ b,
-                                                      const T* __restrict__ dinv, T c1, T c2,
-                                                      const int32_t* __restrict__ agg, const T* __restrict__ ec) {
+                                                      const T* __restrict__ dinv, const T* __restrict__ coef,
+                                                      int step, const int32_t* __restrict__ agg,
+                                                      const T* __restrict__ ec) {
     const int64_t tid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const int row = (int)(tid / W);
     const int lane = threadIdx.x % W;
@@ -563,22 +630,40 @@ __global__ __launch_bounds__(kBlock) void k_cheb_step(BlockOp<T> M, const T* __r
     T xi = xin[i];
     if (agg) xi += ec[(int64_t)BS * agg[row] + lane];
     if (M.dextra) s += M.dextra[i] * xi;
+    T c1, c2;
+    cheb_coef(coef, step, c1, c2);
     const T ri = b[i] - s;
     T di = c2 * dinv[i] * ri;
-    if (c1 != T(0)) di += c1 * d[i];
+    if (step != 0) di += c1 * d[i];
     d[i] = di;
     xout[i] = xi + di;
 }
 
+template <typename T, int BS>
+void cheb_step_w(const BlockOp<T>& M, const T* xin, T* xout, T* d, const T* b, const T* dinv, const T* coef, int step,
+                 const int32_t* agg, const T* ec, hipStream_t st) {
+    switch (M.lanes) {
+        case 64:
+            hipLaunchKernelGGL((k_cheb_step<T, BS, 64>), dim3(grid_for((int64_t)M.n * 64)), dim3(kBlock), 0, st, M,
+                               xin, xout, d, b, dinv, coef, step, agg, ec);
+            break;
+        case 32:
+            hipLaunchKernelGGL((k_cheb_step<T, BS, 32>), dim3(grid_for((int64_t)M.n * 32)), dim3(kBlock), 0, st, M,
+                               xin, xout, d, b, dinv, coef, step, agg, ec);
+            break;
+        default:
+            hipLaunchKernelGGL((k_cheb_step<T, BS, 16>), dim3(grid_for((int64_t)M.n * 16)), dim3(kBlock), 0, st, M,
+                               xin, xout, d, b, dinv, coef, step, agg, ec);
+    }
+}
+
 template <typename T>
-void cheb_step(int bs, const BlockOp<T>& M, const T* xin, T* xout, T* d, const T* b, const T* dinv, T c1, T c2,
-               const int32_t* agg, const T* ec, hipStream_t st) {
+void cheb_step(int bs, const BlockOp<T>& M, const T* xin, T* xout, T* d, const T* b, const T* dinv, const T* coef,
+               int step, const int32_t* agg, const T* ec, hipStream_t st) {
     if (bs == 3)
-        hipLaunchKernelGGL((k_cheb_step<T, 3, 8>), dim3(grid_for((int64_t)M.n * 8)), dim3(kBlock), 0, st, M, xin,
-                           xout, d, b, dinv, c1, c2, agg, ec);
+        cheb_step_w<T, 3>(M, xin, xout, d, b, dinv, coef, step, agg, ec, st);
     else
-        hipLaunchKernelGGL((k_cheb_step<T, 1, 16>), dim3(grid_for((int64_t)M.n * 16)), dim3(kBlock), 0, st, M, xin,
-                           xout, d, b, dinv, c1, c2, agg, ec);
+        cheb_step_w<T, 1>(M, xin, xout, d, b, dinv, coef, step, agg, ec, st);
 }
 
 // Restriction bc = P^T r of a precomputed residual; when xc != nullptr also
@@ -587,7 +672,8 @@ void cheb_step(int bs, const BlockOp<T>& M, const T* xin, T* xout, T* d, const T
 template <typename T>
 __global__ void k_restrict_first(int nc, int bs, const int32_t* __restrict__ aptr,
                                  const int32_t* __restrict__ anodes, const T* __restrict__ r, T* __restrict__ bc,
-                                 T* __restrict__ xc, T* __restrict__ dc, const T* __restrict__ dinvc, T c2c) {
+                                 T* __restrict__ xc, T* __restrict__ dc, const T* __restrict__ dinvc,
+                                 const T* __restrict__ coefc) {
     const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (t >= (int64_t)nc * bs) return;
     const int I = (int)(t / bs), c = (int)(t % bs);
@@ -595,7 +681,7 @@ __global__ void k_restrict_first(int nc, int bs, const int32_t* __restrict__ apt
     for (int q = aptr[I]; q < aptr[I + 1]; ++q) s += r[(int64_t)bs * anodes[q] + c];
     bc[t] = s;
     if (xc) {
-        const T di = c2c * dinvc[t] * s;
+        const T di = coefc[0] * dinvc[t] * s;
         xc[t] = di;
         dc[t] = di;
     }
@@ -603,9 +689,9 @@ __global__ void k_restrict_first(int nc, int bs, const int32_t* __restrict__ apt
 
 template <typename T>
 void restrict_first(int nc, int bs, const int32_t* aptr, const int32_t* anodes, const T* r, T* bc, T* xc, T* dc,
-                    const T* dinvc, T c2c, hipStream_t st) {
+                    const T* dinvc, const T* coefc, hipStream_t st) {
     hipLaunchKernelGGL((k_restrict_first<T>), dim3(grid_for((int64_t)nc * bs)), dim3(kBlock), 0, st, nc, bs, aptr,
-                       anodes, r, bc, xc, dc, dinvc, c2c);
+                       anodes, r, bc, xc, dc, dinvc, coefc);
 }
 
 template <typename T>
@@ -906,13 +992,13 @@ void newton_update(int64_t n, double gdt, const double* dx, double* y, double* y
     template void mul<T>(int64_t, const T*, const T*, T*, hipStream_t);                                              \
     template void arnoldi_cgs2<T>(int64_t, int, const T*, int64_t, T*, double*, double*, const GivensArgs&, double*,  \
                                   hipStream_t);                                                                      \
-    template void norm2<T>(int64_t, const T*, double*, double*, hipStream_t);                                        \
+    template void norm2<T>(int64_t, const T*, double*, double*, hipStream_t, double*);                               \
     template void scale_by<T>(int64_t, const T*, const double*, bool, T*, hipStream_t);                             \
-    template void cheb_first<T>(int64_t, const T*, const T*, T, T*, T*, hipStream_t);                                \
-    template void cheb_step<T>(int, const BlockOp<T>&, const T*, T*, T*, const T*, const T*, T, T, const int32_t*,   \
-                               const T*, hipStream_t);                                                               \
-    template void restrict_first<T>(int, int, const int32_t*, const int32_t*, const T*, T*, T*, T*, const T*, T,      \
-                                    hipStream_t);                                                                     \
+    template void cheb_first<T>(int64_t, const T*, const T*, const T*, T*, T*, hipStream_t);                         \
+    template void cheb_step<T>(int, const BlockOp<T>&, const T*, T*, T*, const T*, const T*, const T*, int,           \
+                               const int32_t*, const T*, hipStream_t);                                               \
+    template void restrict_first<T>(int, int, const int32_t*, const int32_t*, const T*, T*, T*, T*, const T*,         \
+                                    const T*, hipStream_t);                                                           \
     template void restrict_agg<T>(int, int, const int32_t*, const int32_t*, const T*, T*, hipStream_t);              \
     template void prolong_add<T>(int, int, const int32_t*, const T*, T*, hipStream_t);                               \
     template void dense_gemv<T>(int, const double*, const T*, T*, hipStream_t);

@@ -33,7 +33,7 @@ class SolveOptions:
     nmax_S: int = 200
     pc_A: str = "amg"            # "amg" | "jacobi"
     precision: str = "fp64"      # "fp64" | "fp32_inner"
-    cheb_degree: int = 2
+    cheb_degree: int = 1
     schedule: list | None = None  # fixed iteration counts per Krylov call (replay)
     record: bool = True           # record the iteration count of every Krylov call
 

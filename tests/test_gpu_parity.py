@@ -233,3 +233,29 @@ def test_newton_update():
     ctx.newton_update(0.25, dx, y, yd)
     torch.cuda.synchronize()
     assert torch.equal(y, y0 + 0.25 * dx) and torch.equal(yd, yd0 + dx)
+
+
+def test_graph_replays_match_eager_launches(monkeypatch):
+    """The captured Arnoldi-step graphs give bitwise the same solve as launching
+    the same kernels one by one, on every replay, with eager work between."""
+    from paper_1911_10814_amd import NsContext, SolveOptions
+    name = "channel2"
+    c = get_case(name)
+    S = get_assembled(name)
+    monkeypatch.setenv("NS_NO_GRAPHS", "1")
+    eager = NsContext(c).bind()
+    monkeypatch.delenv("NS_NO_GRAPHS")
+    graph = ctx_for(name)
+    kw = dict(rho=c.rho, mu=c.mu, dt=c.dt, rho_inf=c.rho_inf, m=c.R, P_af=c.R * S.Q)
+    r_e = eager.assemble(c.v, c.p, c.vdot, **kw)
+    for prec in ("fp64", "fp32_inner"):
+        xe, ie = eager.solve(r_e, SolveOptions(precision=prec))
+        for rep in range(3):
+            graph._rhs = graph.assemble(c.v, c.p, c.vdot, **kw)
+            xg, ig = graph.solve(graph._rhs, SolveOptions(precision=prec))
+            torch.cuda.synchronize()
+            assert ig["schedule"] == ie["schedule"]
+            assert torch.equal(xg, xe), (prec, rep)
+    le, _ = eager.adjoint(r_e, SolveOptions())
+    lg, _ = graph.adjoint(graph._rhs, SolveOptions())
+    assert torch.equal(le, lg)
