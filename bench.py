@@ -66,6 +66,21 @@ def cpu_baseline(sample: str, scale_to_nnzb: int):
     }
 
 
+def measured_traffic(kernel_class: str, config: str):
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary (profiles/), or None when the kernel source changed since."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", f"{kernel_class}_{config}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    src = open(os.path.join(ROOT, "paper_1911_10814_amd", "csrc", "kernels_la.hip"), "rb").read()
+    if hashlib.sha256(src).hexdigest()[:16] != rec.get("kernels_la_sha256_16"):
+        return None
+    return rec["traffic_bytes_per_launch"]
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -190,6 +205,7 @@ def main():
     dom = max(kt, key=lambda k: kt[k][1])
     n_l, ms_l, by_l = kt[dom]
     achieved = (by_l / (ms_l * 1e-3)) / 1e9 if ms_l > 0 else None
+    traffic = measured_traffic(dom, args.config)
     kernels = {k: {"launches": n, "avg_us": 1e3 * ms / n if n else None,
                    "GBps": (b / (ms * 1e-3)) / 1e9 if ms > 0 else None, "total_ms": ms}
                for k, (n, ms, b) in kt.items()}
@@ -222,7 +238,7 @@ def main():
         "true_rel_res": {"fp32_inner": info["true_rel_res"], "fp64": f64[-1]["true_rel_res"]},
         "kernels": kernels,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": None,
+                     "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": traffic,
                      "bytes_per_launch": by_l / n_l if n_l else None},
     }
     if not args.no_cpu_baseline:

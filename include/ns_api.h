@@ -217,7 +217,8 @@ ns_status ns_newton_update(ns_ctx* ctx, double gamma_dt, const double* d_dx, dou
 
 /* ---- kernel timing ----------------------------------------------------------
  * Kernel classes that can be timed with HIP events on the solve's stream:
- *   NS_KT_SPMV_A    the A-operator SpMV (F x + rank-one epilogue), 3x3 blocks
+ *   NS_KT_SPMV_A    the finest-level 3x3 block SpMV of A: the A operator
+ *                   (F x + rank-one epilogue) and the V-cycle residual
  *   NS_KT_CHEB_A0   the fused residual + Chebyshev step on the finest level of
  *                   the A hierarchy
  *   NS_KT_SPMV_FULL the 4x4 field-split SpMV of the outer FGMRES

@@ -591,7 +591,14 @@ struct Nested {
         // coarse-grid correction: residual, restriction (+ first coarse step)
         AmgLevelDev& C = H[l + 1];
         const bool child_coarsest = (l + 2 == (int)H.size());
-        spmv<T>(bs, bs, M, a, as<T>(L.r), T(-1), b, T(1), nullptr, nullptr, st);
+        if (tme) {
+            // finest A-level residual: same SpMV class as the A operator, plus reads of b and the extra diagonal
+            const double bytes = (double)L.nnz * (9 * sz + 4) + 4.0 * (L.n + 1) + sz * nv * 4;
+            timed(c, NS_KT_SPMV_A, bytes, st,
+                  [&] { spmv<T>(bs, bs, M, a, as<T>(L.r), T(-1), b, T(1), nullptr, nullptr, st); });
+        } else {
+            spmv<T>(bs, bs, M, a, as<T>(L.r), T(-1), b, T(1), nullptr, nullptr, st);
+        }
         restrict_first<T>(C.n, bs, L.aptr, L.anodes, as<T>(L.r), as<T>(C.b), child_coarsest ? nullptr : as<T>(C.x0),
                           as<T>(C.d), Typed<T>::dinv(C), child_coarsest ? nullptr : Typed<T>::coef(C), st);
         vcycle(H, l + 1, as<T>(C.b), as<T>(C.x1));
