@@ -199,8 +199,9 @@ void layout(ns_ctx* c, Arena& A) {
     auto kry = [&](KrylovWs& k, int m, int64_t n, bool outer) {
         k.m = m;
         k.n = n;
-        k.V = A.take<double>((size_t)(m + 1) * n);
-        k.Z = outer ? A.take<double>((size_t)m * n) : nullptr;
+        k.ld = (n + 63) / 64 * 64;
+        k.V = A.take<double>((size_t)(m + 1) * k.ld);
+        k.Z = outer ? A.take<double>((size_t)m * k.ld) : nullptr;
         k.tmp = A.take<double>(n);
         k.H = A.take<double>((size_t)(m + 1) * m);
         k.cs = A.take<double>(m);
@@ -222,6 +223,7 @@ void layout(ns_ctx* c, Arena& A) {
     c->t_xhat = A.take<double>(N);
     c->t_xbar = A.take<double>(3 * (size_t)N);
     c->t_xt = A.take<double>(3 * (size_t)N);
+    c->t_sf = A.take<double>(3 * (size_t)N);
     c->t_r4 = A.take<double>(4 * (size_t)N);
     A.take<char>(256);
 }
@@ -302,6 +304,7 @@ struct Typed<double> {
     static const double* dinv(const AmgLevelDev& d) { return d.dinv64; }
     static const double* dextra(const AmgLevelDev& d) { return d.dextra64; }
     static const double* coef(const AmgLevelDev& d) { return d.coef64; }
+    static const double* dinvA(const SystemDev& y) { return y.dinvA64; }
     static const double* amsk(const ns_ctx* c) { return c->d_a_msk; }
     static const double* ck(const ns_ctx* c) { return c->d_ck; }
 };
@@ -312,6 +315,7 @@ struct Typed<float> {
     static const float* dinv(const AmgLevelDev& d) { return d.dinv32; }
     static const float* dextra(const AmgLevelDev& d) { return d.dextra32; }
     static const float* coef(const AmgLevelDev& d) { return d.coef32; }
+    static const float* dinvA(const SystemDev& y) { return y.dinvA32; }
     static const float* amsk(const ns_ctx* c) { return c->d_a_msk32; }
     static const float* ck(const ns_ctx* c) { return c->d_ck32; }
 };
@@ -389,7 +393,7 @@ void cgs2_launch(ns_ctx* c, KrylovWs& kw, int64_t n, int j, T* V, hipStream_t st
     ga.g = kw.g;
     ga.status = kw.status;
     ga.hstatus = c->d_mapped + kMapStatus + 2 * slot;
-    arnoldi_cgs2<T>(n, j, V, n, V + (int64_t)(j + 1) * n, kw.h, kw.h + (kw.m + 2), ga, c->d_red, st);
+    arnoldi_cgs2<T>(n, j, V, kw.ld, V + (int64_t)(j + 1) * kw.ld, kw.h, kw.h + (kw.m + 2), ga, c->d_red, st);
     check_launch();
 }
 
@@ -409,10 +413,17 @@ void read_step_status(ns_ctx* c, KrylovWs& kw, hipStream_t st, double& resid, bo
 // the preconditioned residual relative to ||P^{-1} b||).
 // kind: graph kind of the Arnoldi step; m_capturable: applyM launches kernels
 // only (no host synchronisation), so the whole step is one graph.
+// stepM / stepP (optional): the operator and preconditioner as used inside an
+// Arnoldi step, where stepM may already perform the preconditioner's first
+// smoothing step on its output (the start and restart residuals use applyM
+// and applyP).
 template <typename T>
 int gmres_left(Ctl& K, KrylovWs& kw, int64_t n, const std::function<void(const T*, T*)>& applyM,
                const std::function<void(const T*, T*)>& applyP, const T* b, T* x, double rtol, int m, int nmax,
-               int kind, bool m_capturable) {
+               int kind, bool m_capturable, const std::function<void(const T*, T*)>& stepM = {},
+               const std::function<void(const T*, T*)>& stepP = {}) {
+    const auto& sM = stepM ? stepM : applyM;
+    const auto& sP = stepP ? stepP : applyP;
     ns_ctx* c = K.c;
     hipStream_t st = K.st;
     int forced;
@@ -441,11 +452,11 @@ int gmres_left(Ctl& K, KrylovWs& kw, int64_t n, const std::function<void(const T
         int launched = 0;
         double r_prev = beta, r_prev2 = -1.0;
         auto enqueue = [&](int jj) {
-            T* vj = V + (int64_t)jj * n;
-            T* vn = V + (int64_t)(jj + 1) * n;
+            T* vj = V + (int64_t)jj * kw.ld;
+            T* vn = V + (int64_t)(jj + 1) * kw.ld;
             run_step(c, K, kind, jj, [&] {
-                applyM(vj, tmp);
-                applyP(tmp, vn);
+                sM(vj, tmp);
+                sP(tmp, vn);
                 cgs2_launch<T>(c, kw, n, jj, V, st, jj & 1);
             });
             HIPCHK(hipEventRecord(c->step_ev[jj & 1], st));
@@ -466,9 +477,9 @@ int gmres_left(Ctl& K, KrylovWs& kw, int64_t n, const std::function<void(const T
                 r_prev2 = r_prev;
                 r_prev = resid;
             } else {
-                applyM(V + (int64_t)j * n, tmp);
+                sM(V + (int64_t)j * kw.ld, tmp);
                 run_step(c, K, kind, j, [&] {
-                    applyP(tmp, V + (int64_t)(j + 1) * n);
+                    sP(tmp, V + (int64_t)(j + 1) * kw.ld);
                     cgs2_launch<T>(c, kw, n, j, V, st);
                 });
                 read_step_status(c, kw, st, resid, bd);
@@ -482,7 +493,7 @@ int gmres_left(Ctl& K, KrylovWs& kw, int64_t n, const std::function<void(const T
             }
         }
         backsolve(k, m + 1, kw.H, kw.g, kw.y, st);
-        combine<T, T>(n, k, V, n, kw.y, x, !first, st);
+        combine<T, T>(n, k, V, kw.ld, kw.y, x, !first, st);
         check_launch();
         first = false;
         if (finished) break;
@@ -539,8 +550,20 @@ struct Nested {
         r.s = as<T>(c->d_s);
         return r;
     }
+    // first Chebyshev step of the V-cycle on level 0 of H, for fusing into the
+    // operator that produces the V-cycle's right-hand side
+    FirstStep<T> first_step(std::vector<AmgLevelDev>& H) {
+        FirstStep<T> f;
+        AmgLevelDev& L = H[0];
+        f.dinv = Typed<T>::dinv(L);
+        f.coef = Typed<T>::coef(L);
+        f.x = as<T>(L.x0);
+        f.d = as<T>(L.d);
+        return f;
+    }
+    bool fuse_first(const std::vector<AmgLevelDev>& H) const { return H.size() > 1; }
     // y = (F + K) x
-    void applyA(const T* x, T* y) {
+    void applyA(const T* x, T* y, const FirstStep<T>* fs = nullptr) {
         RankOne<T> r = rank_one();
         if (r.slot_of)
             outlet_dot<T>(c->sym.n_out, c->d_optr, c->d_onode, Typed<T>::amsk(c), Typed<T>::ck(c), x, as<T>(c->d_s),
@@ -548,13 +571,13 @@ struct Nested {
         const double s = sizeof(T);
         const double bytes = (double)nnzb * (9 * s + 4) + 4.0 * (N + 1) + 6 * s * N;
         timed(c, NS_KT_SPMV_A, bytes, K.st, [&] {
-            spmv<T>(3, 3, op(0, 0), x, y, T(1), nullptr, T(0), nullptr, r.slot_of ? &r : nullptr, K.st);
+            spmv<T>(3, 3, op(0, 0), x, y, T(1), nullptr, T(0), nullptr, r.slot_of ? &r : nullptr, K.st, fs);
         });
     }
     // One V-cycle on level l for right-hand side b, result in xout.  On levels
     // l > 0 the caller has already done the first pre-smoothing step
     // (x = d = dinv b / theta into L.x0, L.d) inside the restriction kernel.
-    void vcycle(std::vector<AmgLevelDev>& H, int l, const T* b, T* xout) {
+    void vcycle(std::vector<AmgLevelDev>& H, int l, const T* b, T* xout, bool first_done = false) {
         AmgLevelDev& L = H[l];
         const int bs = L.bs;
         const int64_t nv = (int64_t)L.n * bs;
@@ -571,6 +594,9 @@ struct Nested {
         T* bb = xout;
         T* d = as<T>(L.d);
         const bool tme = (l == 0 && bs == 3);
+        // finest S_hat level: applied in factored form D - C diag(A)^{-1} B
+        const bool sfact = (l == 0 && &H == &sy.S);
+        T* tsf = as<T>(c->t_sf);
         const double sz = sizeof(T);
         // algorithmic bytes: matrix values, columns and row pointers once; reads
         // x, b, dinv, the extra diagonal and d (steps after the first); writes d and x
@@ -579,11 +605,14 @@ struct Nested {
             if (tme)
                 timed(c, NS_KT_CHEB_A0, bytes, st,
                       [&] { cheb_step<T>(bs, M, xi, xo, d, b, dinv, coef, step, agg, ec, st); });
+            else if (sfact)
+                shat_factored<T>(N, c->d_rp, c->d_col, V(), nnzb, Typed<T>::dinvA(sy), xi, agg, ec, tsf, xo, T(1),
+                                 nullptr, T(0), b, dinv, coef, step, d, st);
             else
                 cheb_step<T>(bs, M, xi, xo, d, b, dinv, coef, step, agg, ec, st);
         };
         // pre-smoothing from x = 0
-        if (l == 0) cheb_first<T>(nv, b, dinv, coef, a, d, st);
+        if (l == 0 && !first_done) cheb_first<T>(nv, b, dinv, coef, a, d, st);
         for (int s = 1; s < deg; ++s) {
             cheb(a, bb, s, nullptr, nullptr);
             std::swap(a, bb);
@@ -591,16 +620,28 @@ struct Nested {
         // coarse-grid correction: residual, restriction (+ first coarse step)
         AmgLevelDev& C = H[l + 1];
         const bool child_coarsest = (l + 2 == (int)H.size());
-        if (tme) {
-            // finest A-level residual: same SpMV class as the A operator, plus reads of b and the extra diagonal
-            const double bytes = (double)L.nnz * (9 * sz + 4) + 4.0 * (L.n + 1) + sz * nv * 4;
-            timed(c, NS_KT_SPMV_A, bytes, st,
-                  [&] { spmv<T>(bs, bs, M, a, as<T>(L.r), T(-1), b, T(1), nullptr, nullptr, st); });
+        T* xc = child_coarsest ? nullptr : as<T>(C.x0);
+        const T* coefc = child_coarsest ? nullptr : Typed<T>::coef(C);
+        if (l == 0) {
+            // finest level: a row-ordered residual SpMV (coalesced value
+            // streams), then the restriction
+            if (tme) {
+                // same SpMV class as the A operator, plus reads of b and the extra diagonal
+                const double bytes = (double)L.nnz * (9 * sz + 4) + 4.0 * (L.n + 1) + sz * nv * 4;
+                timed(c, NS_KT_SPMV_A, bytes, st,
+                      [&] { spmv<T>(bs, bs, M, a, as<T>(L.r), T(-1), b, T(1), nullptr, nullptr, st); });
+            } else if (sfact) {
+                shat_factored<T>(N, c->d_rp, c->d_col, V(), nnzb, Typed<T>::dinvA(sy), a, nullptr, nullptr, tsf,
+                                 as<T>(L.r), T(-1), b, T(1), nullptr, nullptr, nullptr, 0, nullptr, st);
+            } else {
+                spmv<T>(bs, bs, M, a, as<T>(L.r), T(-1), b, T(1), nullptr, nullptr, st);
+            }
+            restrict_first<T>(C.n, bs, L.aptr, L.anodes, as<T>(L.r), as<T>(C.b), xc, as<T>(C.d), Typed<T>::dinv(C),
+                              coefc, st);
         } else {
-            spmv<T>(bs, bs, M, a, as<T>(L.r), T(-1), b, T(1), nullptr, nullptr, st);
+            resid_restrict<T>(bs, M, a, b, C.n, L.aptr, L.anodes, as<T>(C.b), xc, as<T>(C.d), Typed<T>::dinv(C),
+                              coefc, st);
         }
-        restrict_first<T>(C.n, bs, L.aptr, L.anodes, as<T>(L.r), as<T>(C.b), child_coarsest ? nullptr : as<T>(C.x0),
-                          as<T>(C.d), Typed<T>::dinv(C), child_coarsest ? nullptr : Typed<T>::coef(C), st);
         vcycle(H, l + 1, as<T>(C.b), as<T>(C.x1));
         // post-smoothing; the first step applies the prolongated correction
         cheb(a, bb, 0, L.agg, as<T>(C.x1));
@@ -619,26 +660,42 @@ struct Nested {
     void applyPS(const T* r, T* z) { vcycle(sy.S, 0, r, z); }
 
     int solveA(const T* b, T* x, double rtol) {
+        std::function<void(const T*, T*)> sM, sP;
+        if (K.o.pc_A != NS_PC_JACOBI && fuse_first(sy.A)) {
+            sM = [this](const T* in, T* out) {
+                const FirstStep<T> f = first_step(sy.A);
+                applyA(in, out, &f);
+            };
+            sP = [this](const T* in, T* out) { vcycle(sy.A, 0, in, out, true); };
+        }
         return gmres_left<T>(
             K, c->kw_A, 3 * (int64_t)N, [this](const T* in, T* out) { applyA(in, out); },
             [this](const T* in, T* out) { applyPA(in, out); }, b, x, rtol, dflt(K.o.m_A, 200),
-            dflt(K.o.nmax_A, 200), 0, true);
+            dflt(K.o.nmax_A, 200), 0, true, sM, sP);
     }
     // Algorithm 2: y = D x - C A^{-1} (B x)
-    void schur(const T* xp, T* y) {
+    void schur(const T* xp, T* y, const FirstStep<T>* fs = nullptr) {
         hipStream_t st = K.st;
         spmv<T>(1, 1, op(3, 3), xp, as<T>(c->t_xhat), T(1), nullptr, T(0), nullptr, nullptr, st);
         spmv<T>(3, 1, op(0, 3), xp, as<T>(c->t_xbar), T(1), nullptr, T(0), nullptr, nullptr, st);
         const int it = solveA(as<T>(c->t_xbar), as<T>(c->t_xt), dfltd(K.o.rtol_I, 1e-3));
         K.stats.inner_solves++;
         K.stats.inner_iters += it;
-        spmv<T>(1, 3, op(3, 0), as<T>(c->t_xt), y, T(-1), as<T>(c->t_xhat), T(1), nullptr, nullptr, st);
+        spmv<T>(1, 3, op(3, 0), as<T>(c->t_xt), y, T(-1), as<T>(c->t_xhat), T(1), nullptr, nullptr, st, fs);
     }
     int solveS(const T* b, T* x) {
+        std::function<void(const T*, T*)> sM, sP;
+        if (fuse_first(sy.S)) {
+            sM = [this](const T* in, T* out) {
+                const FirstStep<T> f = first_step(sy.S);
+                schur(in, out, &f);
+            };
+            sP = [this](const T* in, T* out) { vcycle(sy.S, 0, in, out, true); };
+        }
         return gmres_left<T>(
             K, c->kw_S, N, [this](const T* in, T* out) { schur(in, out); },
             [this](const T* in, T* out) { applyPS(in, out); }, b, x, dfltd(K.o.rtol_S, 1e-3), dflt(K.o.m_S, 200),
-            dflt(K.o.nmax_S, 200), 1, false);
+            dflt(K.o.nmax_S, 200), 1, false, sM, sP);
     }
     // Algorithm 3: y = P_SCR^{-1} s   (s, y: [4N], field-split)
     void scr(const T* s, T* y) {
@@ -704,8 +761,8 @@ ns_status fgmres(Ctl& K, const double* b, double* x) {
         init_g(kw.g, m + 1, beta, st);
         int k = 0;
         for (int j = 0; j < m; ++j) {
-            double* vj = V + (int64_t)j * n;
-            double* zj = Z + (int64_t)j * n;
+            double* vj = V + (int64_t)j * kw.ld;
+            double* zj = Z + (int64_t)j * kw.ld;
             if (std::is_same<T, double>::value) {
                 P.scr(reinterpret_cast<const T*>(vj), reinterpret_cast<T*>(zj));
             } else {
@@ -714,7 +771,7 @@ ns_status fgmres(Ctl& K, const double* b, double* x) {
                 convert<T, double>(n, as<T>(c->t_yp), zj, st);
             }
             run_step(c, K, 2, j, [&] {
-                applyFull(zj, V + (int64_t)(j + 1) * n, 1.0, nullptr, 0.0);
+                applyFull(zj, V + (int64_t)(j + 1) * kw.ld, 1.0, nullptr, 0.0);
                 cgs2_launch<double>(c, kw, n, j, V, st);
             });
             double resid;
@@ -726,7 +783,7 @@ ns_status fgmres(Ctl& K, const double* b, double* x) {
             if (done || bd || total >= nmax) break;
         }
         backsolve(k, m + 1, kw.H, kw.g, kw.y, st);
-        combine<double, double>(n, k, Z, n, kw.y, x, true, st);
+        combine<double, double>(n, k, Z, kw.ld, kw.y, x, true, st);
         // true residual in FP64
         applyFull(x, V, -1.0, b, 1.0);
         check_launch();

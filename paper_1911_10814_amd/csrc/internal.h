@@ -131,8 +131,9 @@ struct SystemDev {
 struct KrylovWs {
     int m = 0;
     int64_t n = 0;
-    double* V = nullptr;    // [(m+1)][n] (FP64 size; reused as FP32)
-    double* Z = nullptr;    // [m][n] (outer level only)
+    int64_t ld = 0;         // row stride of V and Z: n rounded up to 64 elements
+    double* V = nullptr;    // [(m+1)][ld] (FP64 size; reused as FP32 with the same ld)
+    double* Z = nullptr;    // [m][ld] (outer level only)
     double* tmp = nullptr;  // [n]
     double* H = nullptr;    // [(m+1)*m] column-major, leading dim m+1
     double* cs = nullptr;
@@ -175,6 +176,7 @@ struct ns_ctx {
     // P_SCR / Algorithm 2 temporaries (FP64-sized)
     double *t_s = nullptr, *t_yhat = nullptr, *t_tp = nullptr, *t_yp = nullptr, *t_tv = nullptr,
            *t_yv = nullptr, *t_xhat = nullptr, *t_xbar = nullptr, *t_xt = nullptr, *t_r4 = nullptr;
+    double* t_sf = nullptr;  // [3N] scratch of the factored S_hat application
     double* h_pinned = nullptr;  // pinned host scalars
     double* h_mapped = nullptr;  // pinned, device-mapped host scalars written by kernels
     double* d_mapped = nullptr;  // device address of h_mapped

@@ -17,6 +17,17 @@ struct RankOne {
     const T* s = nullptr;              // [n_out] c_k (a^k . x)
 };
 
+// Optional epilogue of an operator application y = M x that also performs the
+// first Chebyshev step of the V-cycle which follows on y, from a zero guess:
+// x0 = d0 = coef[0] * dinv .* y.
+template <typename T>
+struct FirstStep {
+    const T* dinv = nullptr;
+    const T* coef = nullptr;
+    T* x = nullptr;
+    T* d = nullptr;
+};
+
 // Block-sparse operator: rows of BR, columns of BC unknowns; value of block k
 // at (r, c) is v[r*rs + c*cs + k].
 template <typename T>
@@ -40,7 +51,7 @@ inline int lanes_for(int64_t nnz, int n) {
 // y = alpha * (M x [+ dextra x] [+ rank one]) + beta * z, then y *= rscale
 template <typename T>
 void spmv(int br, int bc, const BlockOp<T>& M, const T* x, T* y, T alpha, const T* z, T beta,
-          const T* rscale, const RankOne<T>* ro, hipStream_t st);
+          const T* rscale, const RankOne<T>* ro, hipStream_t st, const FirstStep<T>* fs = nullptr);
 
 // Full 4x4 field-split operator: y = alpha [A B; C D] x + beta z.
 template <typename T>
@@ -102,6 +113,19 @@ void cheb_step(int bs, const BlockOp<T>& M, const T* xin, T* xout, T* d, const T
 template <typename T>
 void restrict_first(int nc, int bs, const int32_t* aptr, const int32_t* anodes, const T* r, T* bc, T* xc, T* dc,
                     const T* dinvc, const T* coefc, hipStream_t st);
+// Factored S_hat = D - C diag(A)^{-1} B on the node pattern (V: the 16 value
+// planes; t: [3n] scratch).  With coef == nullptr: y = alpha S_hat xx + beta z;
+// else one Chebyshev step y = xx + d, d = c1 d + c2 dinv (b - S_hat xx), where
+// xx = x, or x + P ec when agg != nullptr.
+template <typename T>
+void shat_factored(int n, const int32_t* rp, const int32_t* col, const T* V, int64_t nnzb, const T* dinvA, const T* x,
+                   const int32_t* agg, const T* ec, T* t, T* y, T alpha, const T* z, T beta, const T* b,
+                   const T* dinv, const T* coef, int step, T* d, hipStream_t st);
+// bc = P^T (b - M x) in one launch (residual rows summed per aggregate), plus
+// the coarse first Chebyshev step when xc != nullptr (as restrict_first)
+template <typename T>
+void resid_restrict(int bs, const BlockOp<T>& M, const T* x, const T* b, int nc, const int32_t* aptr,
+                    const int32_t* anodes, T* bc, T* xc, T* dc, const T* dinvc, const T* coefc, hipStream_t st);
 template <typename T>
 void restrict_agg(int nc, int bs, const int32_t* aptr, const int32_t* anodes, const T* r, T* bc, hipStream_t st);
 template <typename T>

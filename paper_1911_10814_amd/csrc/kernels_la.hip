@@ -61,7 +61,7 @@ __device__ inline int lower_bound_dev(const int32_t* a, int lo, int hi, int key)
 template <typename T, int BR, int BC, int W>
 __global__ __launch_bounds__(kBlock) void k_spmv(BlockOp<T> M, const T* __restrict__ x, T* __restrict__ y, T alpha,
                                                  const T* __restrict__ z, T beta, const T* __restrict__ rscale,
-                                                 RankOne<T> ro) {
+                                                 RankOne<T> ro, FirstStep<T> fs) {
     const int64_t tid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const int row = (int)(tid / W);
     const int lane = threadIdx.x % W;
@@ -101,39 +101,45 @@ __global__ __launch_bounds__(kBlock) void k_spmv(BlockOp<T> M, const T* __restri
     if (z) out += beta * z[i];
     if (rscale) out *= rscale[i];
     y[i] = out;
+    if (fs.x) {
+        const T di = fs.coef[0] * fs.dinv[i] * out;
+        fs.x[i] = di;
+        fs.d[i] = di;
+    }
 }
 
 template <typename T, int BR, int BC>
 void spmv_w(const BlockOp<T>& M, const T* x, T* y, T alpha, const T* z, T beta, const T* rscale,
-            const RankOne<T>& r1, hipStream_t st) {
+            const RankOne<T>& r1, const FirstStep<T>& fs, hipStream_t st) {
     switch (M.lanes) {
         case 64:
             hipLaunchKernelGGL((k_spmv<T, BR, BC, 64>), dim3(grid_for((int64_t)M.n * 64)), dim3(kBlock), 0, st, M,
-                               x, y, alpha, z, beta, rscale, r1);
+                               x, y, alpha, z, beta, rscale, r1, fs);
             break;
         case 32:
             hipLaunchKernelGGL((k_spmv<T, BR, BC, 32>), dim3(grid_for((int64_t)M.n * 32)), dim3(kBlock), 0, st, M,
-                               x, y, alpha, z, beta, rscale, r1);
+                               x, y, alpha, z, beta, rscale, r1, fs);
             break;
         default:
             hipLaunchKernelGGL((k_spmv<T, BR, BC, 16>), dim3(grid_for((int64_t)M.n * 16)), dim3(kBlock), 0, st, M,
-                               x, y, alpha, z, beta, rscale, r1);
+                               x, y, alpha, z, beta, rscale, r1, fs);
     }
 }
 
 template <typename T>
 void spmv(int br, int bc, const BlockOp<T>& M, const T* x, T* y, T alpha, const T* z, T beta, const T* rscale,
-          const RankOne<T>* ro, hipStream_t st) {
+          const RankOne<T>* ro, hipStream_t st, const FirstStep<T>* fsp) {
     RankOne<T> r1 = ro ? *ro : RankOne<T>{};
+    FirstStep<T> fs = fsp ? *fsp : FirstStep<T>{};
     if (M.n <= 0) return;
     if (br == 3 && bc == 3)
-        spmv_w<T, 3, 3>(M, x, y, alpha, z, beta, rscale, r1, st);
+        spmv_w<T, 3, 3>(M, x, y, alpha, z, beta, rscale, r1, fs, st);
     else if (br == 3 && bc == 1)
-        spmv_w<T, 3, 1>(M, x, y, alpha, z, beta, rscale, r1, st);
+        spmv_w<T, 3, 1>(M, x, y, alpha, z, beta, rscale, r1, fs, st);
     else if (br == 1 && bc == 3)
-        spmv_w<T, 1, 3>(M, x, y, alpha, z, beta, rscale, r1, st);
+        spmv_w<T, 1, 3>(M, x, y, alpha, z, beta, rscale, r1, fs, st);
     else
-        spmv_w<T, 1, 1>(M, x, y, alpha, z, beta, rscale, r1, st);
+        spmv_w<T, 1, 1>(M, x, y, alpha, z, beta, rscale, r1, fs, st);
 }
 
 // Full field-split 4x4 operator (outer Arnoldi and true residual).
@@ -263,26 +269,65 @@ void mul(int64_t n, const T* a, const T* x, T* y, hipStream_t st) {
 // sums and the NEXT kernel (after the kernel boundary made them visible)
 // reduces them in every block in a fixed order (deterministic).
 //   multidot:    partials of V_i . w (i < k) and w . w -> red1[i][G]
-//   orth_update: h = reduce(red1); block 0 stores h; w -= V h;
-//                optionally partials of ||w||^2 -> red2[G2]
-//   finish:      ||w||^2 = reduce(red2); block 0 updates the Hessenberg
+//   orth_dot:    h1 = reduce(red1); w -= V h1; partials of V_i . w -> red2
+//   orth_update: h2 = reduce(red2); w -= V h2; partials of ||w||^2 -> red3
+//   finish:      ||w||^2 = reduce(red3); block 0 updates the Hessenberg
 //                column and Givens rotation; every block scales w by 1/||w||
+// All four use the same G blocks of kCgsBlock threads, each thread owning
+// the same 16-byte packs of w in every kernel.
 // ---------------------------------------------------------------------------
 
 constexpr int kDotGroup = 8;
+constexpr int kCgsBlock = 512;
+constexpr int kCgsWaves = kCgsBlock / 64;
 
-inline unsigned dot_grid(int64_t n, int nv) {
-    int64_t g = (n + 1023) / 1024;
-    int64_t cap = std::max<int64_t>(8, 8192 / std::max(1, nv));
-    g = std::min<int64_t>(std::min<int64_t>(g, 256), cap);
-    return (unsigned)std::max<int64_t>(g, 1);
+// 16-byte packs (4 floats or 2 doubles): the Krylov basis rows are padded to
+// a multiple of 64 elements and 256-byte aligned, so every pack load is one
+// aligned 128-bit access; elements at or beyond n read as zero.
+template <typename T>
+struct alignas(16) Pk {
+    static constexpr int W = 16 / sizeof(T);
+    T e[W];
+};
+
+template <typename T>
+__device__ inline Pk<T> ld_pk(const T* __restrict__ p, int64_t q, int64_t n) {
+    constexpr int W = Pk<T>::W;
+    Pk<T> v = reinterpret_cast<const Pk<T>*>(p)[q];
+    if ((q + 1) * W > n) {
+#pragma unroll
+        for (int e = 0; e < W; ++e)
+            if (q * W + e >= n) v.e[e] = T(0);
+    }
+    return v;
+}
+template <typename T>
+__device__ inline T pk_dot(const Pk<T>& a, const Pk<T>& b) {
+    T s = 0;
+#pragma unroll
+    for (int e = 0; e < Pk<T>::W; ++e) s += a.e[e] * b.e[e];
+    return s;
+}
+
+template <typename T>
+__host__ __device__ inline int64_t n_packs(int64_t n) {
+    return (n + Pk<T>::W - 1) / Pk<T>::W;
+}
+
+// Blocks of every CGS2 kernel for a vector of length n: about one pack per
+// thread, at most 256 partial sums per reduced value.
+template <typename T>
+inline unsigned cgs_grid(int64_t n) {
+    const int64_t g = (n_packs<T>(n) + kCgsBlock - 1) / kCgsBlock;
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(g, 256));
 }
 
 // every block: out_lds[i] = sum_b red[i*G + b] for i < nv (one wave per value)
 template <typename T>
 __device__ inline void block_reduce_partials(const T* __restrict__ red, int nv, unsigned G, T* out_lds) {
+    const int nw = blockDim.x >> 6;
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    for (int i = wv; i < nv; i += kBlock / 64) {
+    for (int i = wv; i < nv; i += nw) {
         T s = 0;
         for (unsigned b = lane; b < G; b += 64) s += red[(int64_t)i * G + b];
         s = wave_sum(s);
@@ -291,38 +336,25 @@ __device__ inline void block_reduce_partials(const T* __restrict__ red, int nv, 
     __syncthreads();
 }
 
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_multidot(int64_t n, int k, const T* __restrict__ V, int64_t ldv,
-                                                     const T* __restrict__ w, int with_self, T* __restrict__ red) {
-    __shared__ T lds[4];
-    const int nv = k + with_self;
-    const int i0 = blockIdx.y * kDotGroup;
-    T acc[kDotGroup];
+// Block sums of K per-thread accumulators (kCgsBlock threads) written as
+// partials red[g * gridDim.x + blockIdx.x] for g < cnt; one barrier.
+template <typename T, int K>
+__device__ inline void block_partials(const T (&acc)[K], int cnt, T* lds, T* __restrict__ red) {
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
 #pragma unroll
-    for (int q = 0; q < kDotGroup; ++q) acc[q] = 0;
-    for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < n; t += (int64_t)gridDim.x * kBlock) {
-        const T wt = w[t];
+    for (int g = 0; g < K; ++g) {
+        if (g >= cnt) break;
+        const T s = wave_sum(acc[g]);
+        if (lane == 0) lds[wv * K + g] = s;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < cnt) {
+        T s = 0;
 #pragma unroll
-        for (int q = 0; q < kDotGroup; ++q) {
-            const int i = i0 + q;
-            if (i < k) acc[q] += V[i * ldv + t] * wt;
-            else if (i == k && with_self) acc[q] += wt * wt;
-        }
+        for (int w = 0; w < kCgsWaves; ++w) s += lds[w * K + threadIdx.x];
+        red[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = s;
     }
-    for (int q = 0; q < kDotGroup; ++q) {
-        const int i = i0 + q;
-        if (i >= nv) break;
-        T s = block_sum(acc[q], lds);
-        if (threadIdx.x == 0) red[(int64_t)i * gridDim.x + blockIdx.x] = s;
-    }
-}
-
-template <typename T>
-void multidot(int64_t n, int k, const T* V, int64_t ldv, const T* w, bool with_self, T* red, unsigned G,
-              hipStream_t st) {
-    const int nv = k + (with_self ? 1 : 0);
-    dim3 grid(G, (nv + kDotGroup - 1) / kDotGroup);
-    hipLaunchKernelGGL((k_multidot<T>), grid, dim3(kBlock), 0, st, n, k, V, ldv, w, with_self ? 1 : 0, red);
+    __syncthreads();
 }
 
 // Givens update of Hessenberg column j (FP64, one thread).
@@ -361,115 +393,147 @@ __device__ void givens_step(const GivensArgs& a, double hn2) {
     }
 }
 
-// h = reduce(red1) (every block); block 0 stores h (FP64); w -= sum_i V_i h_i;
-// optional partials of ||w||^2 into red2[blockIdx.x].
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_orth_update(int64_t n, int k, int nv, const T* __restrict__ V,
-                                                        int64_t ldv, const T* __restrict__ red1, unsigned G,
-                                                        double* __restrict__ hout, T* __restrict__ w,
-                                                        T* __restrict__ red2) {
-    extern __shared__ char smem[];
-    T* hs = reinterpret_cast<T*>(smem);
-    __shared__ T lds[4];
-    block_reduce_partials<T>(red1, nv, G, hs);
-    if (blockIdx.x == 0)
-        for (int i = threadIdx.x; i < nv; i += kBlock) hout[i] = (double)hs[i];
-    T acc = 0;
-    for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < n; t += (int64_t)gridDim.x * kBlock) {
-        T s = 0;
-        for (int i = 0; i < k; ++i) s += V[i * ldv + t] * hs[i];
-        const T wn = w[t] - s;
-        w[t] = wn;
-        acc += wn * wn;
-    }
-    if (red2) {
-        T s = block_sum(acc, lds);
-        if (threadIdx.x == 0) red2[blockIdx.x] = s;
-    }
-}
-
-// Pass-1 update fused with the pass-2 dot products: h1 = reduce(red1);
-// w -= V h1 over this block's grid-stride slice, then partials of V_i . w over
-// the same slice (written by this block, so no grid synchronisation is
-// needed) into red2[i][blockIdx.x].
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_orth_dot(int64_t n, int k, const T* __restrict__ V, int64_t ldv,
-                                                     const T* __restrict__ red1, unsigned G1, double* __restrict__ h1,
-                                                     T* __restrict__ w, T* __restrict__ red2) {
-    extern __shared__ char smem[];
-    T* hs = reinterpret_cast<T*>(smem);
-    __shared__ T lds[4];
-    block_reduce_partials<T>(red1, k + 1, G1, hs);
-    if (blockIdx.x == 0)
-        for (int i = threadIdx.x; i <= k; i += kBlock) h1[i] = (double)hs[i];
-    for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < n; t += (int64_t)gridDim.x * kBlock) {
-        T s = 0;
-        for (int i = 0; i < k; ++i) s += V[i * ldv + t] * hs[i];
-        w[t] -= s;
-    }
-    for (int i0 = 0; i0 < k; i0 += kDotGroup) {
-        T acc[kDotGroup];
-#pragma unroll
-        for (int q = 0; q < kDotGroup; ++q) acc[q] = 0;
-        for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < n; t += (int64_t)gridDim.x * kBlock) {
-            const T wt = w[t];
-#pragma unroll
-            for (int q = 0; q < kDotGroup; ++q)
-                if (i0 + q < k) acc[q] += V[(i0 + q) * ldv + t] * wt;
-        }
-        for (int q = 0; q < kDotGroup && i0 + q < k; ++q) {
-            T sq = block_sum(acc[q], lds);
-            if (threadIdx.x == 0) red2[(int64_t)(i0 + q) * gridDim.x + blockIdx.x] = sq;
-        }
-    }
-}
-
 inline unsigned orth_grid(int64_t n) {
     int64_t g = (n + kBlock * 4 - 1) / (kBlock * 4);
     return (unsigned)std::max<int64_t>(1, std::min<int64_t>(g, 1024));
 }
 
+// Pass-1 dot products: partials of V_i . w (i < k) and of w . w (i = k),
+// kDotGroup values per blockIdx.y.
 template <typename T>
-void orth_update(int64_t n, int k, int nv, const T* V, int64_t ldv, const T* red1, unsigned G, double* hout, T* w,
-                 T* red2, hipStream_t st) {
-    hipLaunchKernelGGL((k_orth_update<T>), dim3(orth_grid(n)), dim3(kBlock), nv * sizeof(T), st, n, k, nv, V, ldv,
-                       red1, G, hout, w, red2);
+__global__ __launch_bounds__(kCgsBlock) void k_multidot(int64_t n, int k, const T* __restrict__ V, int64_t ldv,
+                                                        const T* __restrict__ w, T* __restrict__ red) {
+    __shared__ T lds[kCgsWaves * kDotGroup];
+    const int i0 = blockIdx.y * kDotGroup;
+    const int64_t np = n_packs<T>(n);
+    T acc[kDotGroup];
+#pragma unroll
+    for (int g = 0; g < kDotGroup; ++g) acc[g] = 0;
+    for (int64_t q = (int64_t)blockIdx.x * kCgsBlock + threadIdx.x; q < np; q += (int64_t)gridDim.x * kCgsBlock) {
+        const Pk<T> wp = ld_pk(w, q, n);
+#pragma unroll
+        for (int g = 0; g < kDotGroup; ++g) {
+            const int i = i0 + g;
+            if (i < k) acc[g] += pk_dot(ld_pk(V + (int64_t)i * ldv, q, n), wp);
+            else if (i == k) acc[g] += pk_dot(wp, wp);
+        }
+    }
+    block_partials<T, kDotGroup>(acc, min(kDotGroup, k + 1 - i0), lds, red + (int64_t)i0 * gridDim.x);
 }
 
-// ||w||^2 = reduce(red2); Givens update (block 0); w *= 1/||w|| unless breakdown
+// w -= sum_{i<k} V_i hs_i over this block's packs; returns the sum of the
+// squares of the updated entries this thread owns.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_finish(int64_t n, T* __restrict__ w, const T* __restrict__ red2,
-                                                   unsigned G2, GivensArgs ga) {
+__device__ inline T orth_subtract(int64_t n, int k, const T* __restrict__ V, int64_t ldv, const T* hs,
+                                  T* __restrict__ w) {
+    const int64_t np = n_packs<T>(n);
+    T sq = 0;
+    for (int64_t q = (int64_t)blockIdx.x * kCgsBlock + threadIdx.x; q < np; q += (int64_t)gridDim.x * kCgsBlock) {
+        Pk<T> s;
+#pragma unroll
+        for (int e = 0; e < Pk<T>::W; ++e) s.e[e] = 0;
+        for (int i = 0; i < k; ++i) {
+            const Pk<T> v = ld_pk(V + (int64_t)i * ldv, q, n);
+            const T h = hs[i];
+#pragma unroll
+            for (int e = 0; e < Pk<T>::W; ++e) s.e[e] += v.e[e] * h;
+        }
+        Pk<T> wp = ld_pk(w, q, n);
+#pragma unroll
+        for (int e = 0; e < Pk<T>::W; ++e) {
+            wp.e[e] -= s.e[e];
+            sq += wp.e[e] * wp.e[e];
+        }
+        reinterpret_cast<Pk<T>*>(w)[q] = wp;
+    }
+    return sq;
+}
+
+// Pass-1 update fused with the pass-2 dot products: h1 = reduce(red1);
+// w -= V h1 over this block's packs, then partials of V_i . w over the same
+// packs (written by this block, so no grid synchronisation is needed) into
+// red2[i][blockIdx.x].
+template <typename T>
+__global__ __launch_bounds__(kCgsBlock) void k_orth_dot(int64_t n, int k, const T* __restrict__ V, int64_t ldv,
+                                                        const T* __restrict__ red1, unsigned G1,
+                                                        double* __restrict__ h1, T* __restrict__ w,
+                                                        T* __restrict__ red2) {
+    extern __shared__ char smem[];
+    T* hs = reinterpret_cast<T*>(smem);
+    __shared__ T lds[kCgsWaves * kDotGroup];
+    block_reduce_partials<T>(red1, k + 1, G1, hs);
+    if (blockIdx.x == 0)
+        for (int i = threadIdx.x; i <= k; i += kCgsBlock) h1[i] = (double)hs[i];
+    (void)orth_subtract<T>(n, k, V, ldv, hs, w);
+    const int64_t np = n_packs<T>(n);
+    for (int i0 = 0; i0 < k; i0 += kDotGroup) {
+        T acc[kDotGroup];
+#pragma unroll
+        for (int g = 0; g < kDotGroup; ++g) acc[g] = 0;
+        for (int64_t q = (int64_t)blockIdx.x * kCgsBlock + threadIdx.x; q < np;
+             q += (int64_t)gridDim.x * kCgsBlock) {
+            const Pk<T> wp = ld_pk(w, q, n);
+#pragma unroll
+            for (int g = 0; g < kDotGroup; ++g)
+                if (i0 + g < k) acc[g] += pk_dot(ld_pk(V + (int64_t)(i0 + g) * ldv, q, n), wp);
+        }
+        block_partials<T, kDotGroup>(acc, min(kDotGroup, k - i0), lds, red2 + (int64_t)i0 * gridDim.x);
+    }
+}
+
+// h2 = reduce(red2) (every block); block 0 stores h2 (FP64); w -= V h2;
+// partials of ||w||^2 into red3[blockIdx.x].
+template <typename T>
+__global__ __launch_bounds__(kCgsBlock) void k_orth_update(int64_t n, int k, const T* __restrict__ V, int64_t ldv,
+                                                           const T* __restrict__ red2, unsigned G2,
+                                                           double* __restrict__ h2, T* __restrict__ w,
+                                                           T* __restrict__ red3) {
+    extern __shared__ char smem[];
+    T* hs = reinterpret_cast<T*>(smem);
+    __shared__ T lds[kCgsWaves];
+    block_reduce_partials<T>(red2, k, G2, hs);
+    if (blockIdx.x == 0)
+        for (int i = threadIdx.x; i < k; i += kCgsBlock) h2[i] = (double)hs[i];
+    const T acc[1] = {orth_subtract<T>(n, k, V, ldv, hs, w)};
+    block_partials<T, 1>(acc, 1, lds, red3);
+}
+
+// ||w||^2 = reduce(red3); Givens update (block 0); w *= 1/||w|| unless breakdown
+template <typename T>
+__global__ __launch_bounds__(kCgsBlock) void k_finish(int64_t n, T* __restrict__ w, const T* __restrict__ red3,
+                                                      unsigned G3, GivensArgs ga) {
     __shared__ T tot[1];
-    block_reduce_partials<T>(red2, 1, G2, tot);
+    block_reduce_partials<T>(red3, 1, G3, tot);
     const double hn2 = (double)tot[0];
     if (blockIdx.x == 0 && threadIdx.x == 0) givens_step(ga, hn2);
     const double hn = sqrt(hn2);
     const double wpre = sqrt(ga.h1[ga.j + 1]);
     if (!(hn > 1e-14 * wpre)) return;
     const T s = (T)(1.0 / hn);
-    for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < n; t += (int64_t)gridDim.x * kBlock) w[t] *= s;
-}
-
-template <typename T>
-void finish_step(int64_t n, T* w, const T* red2, unsigned G2, const GivensArgs& ga, hipStream_t st) {
-    hipLaunchKernelGGL((k_finish<T>), dim3(orth_grid(n)), dim3(kBlock), 0, st, n, w, red2, G2, ga);
+    const int64_t np = n_packs<T>(n);
+    for (int64_t q = (int64_t)blockIdx.x * kCgsBlock + threadIdx.x; q < np; q += (int64_t)gridDim.x * kCgsBlock) {
+        Pk<T> wp = ld_pk(w, q, n);
+#pragma unroll
+        for (int e = 0; e < Pk<T>::W; ++e) wp.e[e] *= s;
+        reinterpret_cast<Pk<T>*>(w)[q] = wp;
+    }
 }
 
 template <typename T>
 void arnoldi_cgs2(int64_t n, int j, const T* V, int64_t ldv, T* w, double* h1, double* h2, const GivensArgs& ga,
                   double* red, hipStream_t st) {
     const int k = j + 1;
+    const unsigned G = cgs_grid<T>(n);
     T* r1 = reinterpret_cast<T*>(red);
-    const unsigned G1 = dot_grid(n, k + 1);
-    T* r2 = r1 + (int64_t)(k + 1) * G1;
-    const unsigned G2 = dot_grid(n, k);
-    T* r3 = r2 + (int64_t)k * G2;
-    multidot<T>(n, k, V, ldv, w, true, r1, G1, st);
-    hipLaunchKernelGGL((k_orth_dot<T>), dim3(G2), dim3(kBlock), (k + 1) * sizeof(T), st, n, k, V, ldv, r1, G1, h1, w,
-                       r2);
-    orth_update<T>(n, k, k, V, ldv, r2, G2, h2, w, r3, st);
-    finish_step<T>(n, w, r3, orth_grid(n), ga, st);
+    T* r2 = r1 + (int64_t)(k + 1) * G;
+    T* r3 = r2 + (int64_t)k * G;
+    hipLaunchKernelGGL((k_multidot<T>), dim3(G, (k + 1 + kDotGroup - 1) / kDotGroup), dim3(kCgsBlock), 0, st, n, k,
+                       V, ldv, w, r1);
+    hipLaunchKernelGGL((k_orth_dot<T>), dim3(G), dim3(kCgsBlock), (k + 1) * sizeof(T), st, n, k, V, ldv, r1, G, h1,
+                       w, r2);
+    hipLaunchKernelGGL((k_orth_update<T>), dim3(G), dim3(kCgsBlock), k * sizeof(T), st, n, k, V, ldv, r2, G, h2, w,
+                       r3);
+    hipLaunchKernelGGL((k_finish<T>), dim3(G), dim3(kCgsBlock), 0, st, n, w, r3, G, ga);
 }
 
 __global__ void k_init_g(double* g, int len, double beta) {
@@ -666,6 +730,99 @@ void cheb_step(int bs, const BlockOp<T>& M, const T* xin, T* xout, T* d, const T
         cheb_step_w<T, 1>(M, xin, xout, d, b, dinv, coef, step, agg, ec, st);
 }
 
+// Factored application of S_hat = D - C diag(A)^{-1} B on the finest pressure
+// level, two passes over the node-block value planes (V: the 16 planes, B in
+// planes 4r+3, C in planes 12+c, D in plane 15), instead of one pass over the
+// explicit distance-2 pattern of S_hat (several times more gathers):
+//   pass 1: t = dinvA .* (B xx)                        (3 values per node)
+//   pass 2: s = D xx - C t, then the Chebyshev update with residual b - s
+//           (coef != nullptr), else y = alpha s + beta z
+// where xx = x, or x + P ec (prolongated coarse correction) when agg != nullptr.
+template <typename T, int W>
+__global__ __launch_bounds__(kBlock) void k_sfact_bt(int n, const int32_t* __restrict__ rp,
+                                                     const int32_t* __restrict__ col, const T* __restrict__ V,
+                                                     int64_t nnzb, const T* __restrict__ dinvA,
+                                                     const T* __restrict__ x, const int32_t* __restrict__ agg,
+                                                     const T* __restrict__ ec, T* __restrict__ t) {
+    const int64_t tid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int row = (int)(tid / W);
+    const int lane = threadIdx.x % W;
+    const bool valid = row < n;
+    T acc[3] = {0, 0, 0};
+    if (valid) {
+        const int k1 = rp[row + 1];
+        for (int k = rp[row] + lane; k < k1; k += W) {
+            const int j = col[k];
+            T xj = x[j];
+            if (agg) xj += ec[agg[j]];
+#pragma unroll
+            for (int r = 0; r < 3; ++r) acc[r] += V[(4 * r + 3) * nnzb + k] * xj;
+        }
+    }
+#pragma unroll
+    for (int off = W / 2; off > 0; off >>= 1)
+#pragma unroll
+        for (int r = 0; r < 3; ++r) acc[r] += __shfl_xor(acc[r], off, W);
+    if (!valid || lane >= 3) return;
+    const T s = lane == 0 ? acc[0] : (lane == 1 ? acc[1] : acc[2]);
+    const int64_t i = 3 * (int64_t)row + lane;
+    t[i] = dinvA[i] * s;
+}
+
+template <typename T, int W>
+__global__ __launch_bounds__(kBlock) void k_sfact_dc(int n, const int32_t* __restrict__ rp,
+                                                     const int32_t* __restrict__ col, const T* __restrict__ V,
+                                                     int64_t nnzb, const T* __restrict__ t, const T* __restrict__ x,
+                                                     const int32_t* __restrict__ agg, const T* __restrict__ ec,
+                                                     T* __restrict__ y, T alpha, const T* __restrict__ z, T beta,
+                                                     const T* __restrict__ b, const T* __restrict__ dinv,
+                                                     const T* __restrict__ coef, int step, T* __restrict__ d) {
+    const int64_t tid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int row = (int)(tid / W);
+    const int lane = threadIdx.x % W;
+    const bool valid = row < n;
+    T acc = 0;
+    if (valid) {
+        const int k1 = rp[row + 1];
+        for (int k = rp[row] + lane; k < k1; k += W) {
+            const int j = col[k];
+            T xj = x[j];
+            if (agg) xj += ec[agg[j]];
+            acc += V[15 * nnzb + k] * xj;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) acc -= V[(12 + c) * nnzb + k] * t[3 * (int64_t)j + c];
+        }
+    }
+#pragma unroll
+    for (int off = W / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, W);
+    if (!valid || lane != 0) return;
+    if (!coef) {
+        T out = alpha * acc;
+        if (z) out += beta * z[row];
+        y[row] = out;
+        return;
+    }
+    T xi = x[row];
+    if (agg) xi += ec[agg[row]];
+    T c1, c2;
+    cheb_coef(coef, step, c1, c2);
+    T di = c2 * dinv[row] * (b[row] - acc);
+    if (step != 0) di += c1 * d[row];
+    d[row] = di;
+    y[row] = xi + di;
+}
+
+template <typename T>
+void shat_factored(int n, const int32_t* rp, const int32_t* col, const T* V, int64_t nnzb, const T* dinvA, const T* x,
+                   const int32_t* agg, const T* ec, T* t, T* y, T alpha, const T* z, T beta, const T* b,
+                   const T* dinv, const T* coef, int step, T* d, hipStream_t st) {
+    if (n <= 0) return;
+    const dim3 grid(grid_for((int64_t)n * 16));
+    hipLaunchKernelGGL((k_sfact_bt<T, 16>), grid, dim3(kBlock), 0, st, n, rp, col, V, nnzb, dinvA, x, agg, ec, t);
+    hipLaunchKernelGGL((k_sfact_dc<T, 16>), grid, dim3(kBlock), 0, st, n, rp, col, V, nnzb, t, x, agg, ec, y, alpha,
+                       z, beta, b, dinv, coef, step, d);
+}
+
 // Restriction bc = P^T r of a precomputed residual; when xc != nullptr also
 // the first Chebyshev step of the coarse level from a zero guess:
 // xc = dc = c2c dinvc bc.
@@ -692,6 +849,88 @@ void restrict_first(int nc, int bs, const int32_t* aptr, const int32_t* anodes, 
                     const T* dinvc, const T* coefc, hipStream_t st) {
     hipLaunchKernelGGL((k_restrict_first<T>), dim3(grid_for((int64_t)nc * bs)), dim3(kBlock), 0, st, nc, bs, aptr,
                        anodes, r, bc, xc, dc, dinvc, coefc);
+}
+
+// Residual fused with the restriction, for the coarser levels: one wavefront
+// per aggregate I, 16 lanes per fine row of I (aggregates of two pairwise
+// matchings hold at most 4 nodes; larger ones loop), so the rows are summed
+// in parallel:
+// bc = P^T (b - M x), then the coarse first Chebyshev step as in
+// k_restrict_first.  Saves the launch of a separate residual kernel where the
+// level is too small to be bandwidth-bound.
+constexpr int kAggMax = 4;
+constexpr int kRowLanes = 64 / kAggMax;
+
+template <typename T, int BS>
+__global__ __launch_bounds__(kBlock) void k_resid_restrict(BlockOp<T> M, const T* __restrict__ x,
+                                                           const T* __restrict__ b, int nc,
+                                                           const int32_t* __restrict__ aptr,
+                                                           const int32_t* __restrict__ anodes, T* __restrict__ bc,
+                                                           T* __restrict__ xc, T* __restrict__ dc,
+                                                           const T* __restrict__ dinvc, const T* __restrict__ coefc) {
+    const int64_t tid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int I = (int)(tid >> 6);
+    const int lane = threadIdx.x & 63;
+    const int sub = lane / kRowLanes, l = lane % kRowLanes;
+    const bool valid = I < nc;
+    // acc = sum over the aggregate of (M x + dextra x - b): the negated residual
+    T acc[BS];
+#pragma unroll
+    for (int r = 0; r < BS; ++r) acc[r] = 0;
+    if (valid) {
+        const int q1 = aptr[I + 1];
+        for (int q = aptr[I] + sub; q < q1; q += kAggMax) {
+            const int row = anodes[q];
+            const int k1 = M.rp[row + 1];
+            for (int k = M.rp[row] + l; k < k1; k += kRowLanes) {
+                const int j = M.col[k];
+                T xj[BS];
+#pragma unroll
+                for (int c = 0; c < BS; ++c) xj[c] = x[(int64_t)BS * j + c];
+#pragma unroll
+                for (int r = 0; r < BS; ++r)
+#pragma unroll
+                    for (int c = 0; c < BS; ++c) acc[r] += M.v[r * M.rs + c * M.cs + k] * xj[c];
+            }
+            if (l < BS) {
+                const int64_t i = (int64_t)BS * row + l;
+                T t = -b[i];
+                if (M.dextra) t += M.dextra[i] * x[i];
+#pragma unroll
+                for (int r = 0; r < BS; ++r)
+                    if (l == r) acc[r] += t;
+            }
+        }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+        for (int r = 0; r < BS; ++r) acc[r] += __shfl_xor(acc[r], off, 64);
+    if (!valid || lane >= BS) return;
+    T s = -acc[0];
+#pragma unroll
+    for (int r = 1; r < BS; ++r)
+        if (lane == r) s = -acc[r];
+    const int64_t t = (int64_t)BS * I + lane;
+    bc[t] = s;
+    if (xc) {
+        const T di = coefc[0] * dinvc[t] * s;
+        xc[t] = di;
+        dc[t] = di;
+    }
+}
+
+template <typename T>
+void resid_restrict(int bs, const BlockOp<T>& M, const T* x, const T* b, int nc, const int32_t* aptr,
+                    const int32_t* anodes, T* bc, T* xc, T* dc, const T* dinvc, const T* coefc, hipStream_t st) {
+    if (nc <= 0) return;
+    const dim3 grid(grid_for((int64_t)nc * 64));
+    if (bs == 3)
+        hipLaunchKernelGGL((k_resid_restrict<T, 3>), grid, dim3(kBlock), 0, st, M, x, b, nc, aptr, anodes, bc, xc, dc,
+                           dinvc, coefc);
+    else
+        hipLaunchKernelGGL((k_resid_restrict<T, 1>), grid, dim3(kBlock), 0, st, M, x, b, nc, aptr, anodes, bc, xc, dc,
+                           dinvc, coefc);
 }
 
 template <typename T>
@@ -983,7 +1222,7 @@ void newton_update(int64_t n, double gdt, const double* dx, double* y, double* y
 // ---------------------------------------------------------------------------
 #define NS_INST(T)                                                                                                   \
     template void spmv<T>(int, int, const BlockOp<T>&, const T*, T*, T, const T*, T, const T*, const RankOne<T>*,   \
-                          hipStream_t);                                                                              \
+                          hipStream_t, const FirstStep<T>*);                                                         \
     template void spmv_full<T>(int, const int32_t*, const int32_t*, const T*, int64_t, const T*, T*, T, const T*, T, \
                                const RankOne<T>*, hipStream_t);                                                      \
     template void outlet_dot<T>(int, const int32_t*, const int32_t*, const T*, const T*, const T*, T*, hipStream_t);  \
@@ -1000,6 +1239,11 @@ void newton_update(int64_t n, double gdt, const double* dx, double* y, double* y
     template void restrict_first<T>(int, int, const int32_t*, const int32_t*, const T*, T*, T*, T*, const T*,         \
                                     const T*, hipStream_t);                                                           \
     template void restrict_agg<T>(int, int, const int32_t*, const int32_t*, const T*, T*, hipStream_t);              \
+    template void shat_factored<T>(int, const int32_t*, const int32_t*, const T*, int64_t, const T*, const T*,       \
+                                   const int32_t*, const T*, T*, T*, T, const T*, T, const T*, const T*, const T*,   \
+                                   int, T*, hipStream_t);                                                            \
+    template void resid_restrict<T>(int, const BlockOp<T>&, const T*, const T*, int, const int32_t*, const int32_t*, \
+                                    T*, T*, T*, const T*, const T*, hipStream_t);                                    \
     template void prolong_add<T>(int, int, const int32_t*, const T*, T*, hipStream_t);                               \
     template void dense_gemv<T>(int, const double*, const T*, T*, hipStream_t);
 
