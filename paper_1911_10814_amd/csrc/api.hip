@@ -335,7 +335,8 @@ void read_status(ns_ctx* c, const double* d_status, int n, hipStream_t st) {
 }
 
 // host-mapped scalar slots written by kernels: [0..1] Arnoldi status, [8] norms
-constexpr int kMapStatus = 0, kMapNorm = 8;
+// [9 + kind] initial residual norm of a left GMRES call of that kind
+constexpr int kMapStatus = 0, kMapNorm = 8, kMapNorm0 = 9;
 
 template <typename T>
 double dev_norm(ns_ctx* c, int64_t n, const T* x, double* slot, hipStream_t st) {
@@ -398,7 +399,7 @@ void cgs2_launch(ns_ctx* c, KrylovWs& kw, int64_t n, int j, T* V, hipStream_t st
 }
 
 void read_step_status(ns_ctx* c, KrylovWs& kw, hipStream_t st, double& resid, bool& bd, hipEvent_t ev = nullptr,
-                      int slot = 0) {
+                      int slot = 0, bool check = true) {
     if (ev)
         HIPCHK(hipEventSynchronize(ev));
     else
@@ -406,7 +407,7 @@ void read_step_status(ns_ctx* c, KrylovWs& kw, hipStream_t st, double& resid, bo
     const volatile double* h = c->h_mapped + kMapStatus + 2 * slot;
     resid = h[0];
     bd = h[1] != 0.0;
-    if (!std::isfinite(resid)) throw Fail{NS_ERR_NAN, "residual estimate is not finite"};
+    if (check && !std::isfinite(resid)) throw Fail{NS_ERR_NAN, "residual estimate is not finite"};
 }
 
 // Left-preconditioned GMRES(m) for M x = b from x = 0 (Sec. 3.1; stopping on
@@ -430,20 +431,25 @@ int gmres_left(Ctl& K, KrylovWs& kw, int64_t n, const std::function<void(const T
     const int idx = K.sc.begin(forced);
     T* V = as<T>(kw.V);
     T* tmp = as<T>(kw.tmp);
-    applyP(b, V);
-    const double beta0 = dev_norm<T>(c, n, V, kw.status + 4, st);
     int total = 0;
-    if (beta0 == 0.0 || forced == 0) {
+    applyP(b, V);
+    if (forced == 0) {
         fill<T>(n, T(0), x, st);
         K.sc.end(idx, 0);
         return 0;
     }
-    const double tol = std::max(rtol * beta0, K.o.atol);
-    double beta = beta0;
+    // ||P^{-1} b|| stays on the device (status[4], used by the first cycle) and
+    // reaches the host through a mapped slot of its own, read together with
+    // the first step's status: no host round trip before the first step.
+    volatile double* hnorm0 = c->h_mapped + kMapNorm0 + kind;
+    norm2<T>(n, V, kw.status + 4, c->d_red, st, c->d_mapped + kMapNorm0 + kind);
+    check_launch();
+    double beta0 = -1.0, tol = 0.0;  // known after the first status read
+    double beta = -1.0;
     bool first = true;
+    bool zero_rhs = false;
     while (true) {
-        scale_by<T>(n, V, kw.status + 4, true, V, st);
-        init_g(kw.g, m + 1, beta, st);
+        start_cycle<T>(n, V, kw.status + 4, kw.g, m + 1, st);
         int k = 0;
         bool finished = false;
         // Steps of a capturable operator are queued one ahead of the status
@@ -469,21 +475,37 @@ int gmres_left(Ctl& K, KrylovWs& kw, int64_t n, const std::function<void(const T
                 if (launched == j) enqueue(j);
                 bool ahead = (j + 1 < m) && (total + 2 <= nmax) && (forced < 0 || total + 2 <= forced);
                 if (ahead && forced < 0) {
-                    const double ratio = r_prev2 > 0.0 ? r_prev / r_prev2 : 0.5;
-                    ahead = r_prev * ratio > 2.0 * tol;
+                    if (beta0 < 0.0) {
+                        ahead = 0.5 > 2.0 * rtol;  // first step: assume a halving
+                    } else {
+                        const double ratio = r_prev2 > 0.0 ? r_prev / r_prev2 : 0.5;
+                        ahead = r_prev * ratio > 2.0 * tol;
+                    }
                 }
                 if (ahead) enqueue(j + 1);
-                read_step_status(c, kw, st, resid, bd, c->step_ev[j & 1], j & 1);
-                r_prev2 = r_prev;
-                r_prev = resid;
+                read_step_status(c, kw, st, resid, bd, c->step_ev[j & 1], j & 1, false);
             } else {
                 sM(V + (int64_t)j * kw.ld, tmp);
                 run_step(c, K, kind, j, [&] {
                     sP(tmp, V + (int64_t)(j + 1) * kw.ld);
                     cgs2_launch<T>(c, kw, n, j, V, st);
                 });
-                read_step_status(c, kw, st, resid, bd);
+                read_step_status(c, kw, st, resid, bd, nullptr, 0, false);
             }
+            if (beta0 < 0.0) {
+                beta0 = *hnorm0;
+                if (!std::isfinite(beta0)) throw Fail{NS_ERR_NAN, "residual norm is not finite"};
+                if (beta0 == 0.0) {
+                    zero_rhs = true;
+                    break;
+                }
+                tol = std::max(rtol * beta0, K.o.atol);
+                beta = beta0;
+                r_prev = beta0;
+            }
+            if (!std::isfinite(resid)) throw Fail{NS_ERR_NAN, "residual estimate is not finite"};
+            r_prev2 = r_prev;
+            r_prev = resid;
             ++total;
             k = j + 1;
             const bool done = forced >= 0 ? total >= forced : resid <= tol;
@@ -491,6 +513,13 @@ int gmres_left(Ctl& K, KrylovWs& kw, int64_t n, const std::function<void(const T
                 finished = true;
                 break;
             }
+        }
+        if (zero_rhs) {
+            // P^{-1} b = 0: the steps already queued ran on a zero basis and
+            // are discarded
+            fill<T>(n, T(0), x, st);
+            check_launch();
+            break;
         }
         backsolve(k, m + 1, kw.H, kw.g, kw.y, st);
         combine<T, T>(n, k, V, kw.ld, kw.y, x, !first, st);

@@ -90,6 +90,9 @@ void arnoldi_cgs2(int64_t n, int j, const T* V, int64_t ldv, T* w, double* h1, d
                   double* red, hipStream_t st);
 void backsolve(int k, int ldh, const double* H, const double* g, double* y, hipStream_t st);
 void init_g(double* g, int len, double beta, hipStream_t st);  // g = [beta, 0, ...]
+// v /= nrm[0]; g = [nrm[0], 0, ...] (len entries)
+template <typename T>
+void start_cycle(int64_t n, T* v, const double* nrm, double* g, int len, hipStream_t st);
 // x = (accumulate ? x : 0) + sum_i V_i y_i
 template <typename T, typename TX>
 void combine(int64_t n, int k, const T* V, int64_t ldv, const double* y, TX* x, bool accumulate,

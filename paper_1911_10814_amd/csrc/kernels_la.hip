@@ -536,6 +536,24 @@ void arnoldi_cgs2(int64_t n, int j, const T* V, int64_t ldv, T* w, double* h1, d
     hipLaunchKernelGGL((k_finish<T>), dim3(G), dim3(kCgsBlock), 0, st, n, w, r3, G, ga);
 }
 
+// Start of a GMRES cycle with the residual norm on the device: v /= nrm,
+// g = [nrm, 0, ...].
+template <typename T>
+__global__ void k_start_cycle(int64_t n, T* __restrict__ v, const double* __restrict__ nrm, double* __restrict__ g,
+                              int len) {
+    const double s = nrm[0];
+    if (blockIdx.x == 0)
+        for (int i = threadIdx.x; i < len; i += kBlock) g[i] = (i == 0) ? s : 0.0;
+    const T f = (T)(1.0 / s);
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
+        v[i] *= f;
+}
+template <typename T>
+void start_cycle(int64_t n, T* v, const double* nrm, double* g, int len, hipStream_t st) {
+    hipLaunchKernelGGL((k_start_cycle<T>), dim3(std::min<int64_t>(grid_for(n), 4096)), dim3(kBlock), 0, st, n, v, nrm,
+                       g, len);
+}
+
 __global__ void k_init_g(double* g, int len, double beta) {
     for (int i = threadIdx.x; i < len; i += blockDim.x) g[i] = (i == 0) ? beta : 0.0;
 }
@@ -1233,6 +1251,7 @@ void newton_update(int64_t n, double gdt, const double* dx, double* y, double* y
                                   hipStream_t);                                                                      \
     template void norm2<T>(int64_t, const T*, double*, double*, hipStream_t, double*);                               \
     template void scale_by<T>(int64_t, const T*, const double*, bool, T*, hipStream_t);                             \
+    template void start_cycle<T>(int64_t, T*, const double*, double*, int, hipStream_t);                             \
     template void cheb_first<T>(int64_t, const T*, const T*, const T*, T*, T*, hipStream_t);                         \
     template void cheb_step<T>(int, const BlockOp<T>&, const T*, T*, T*, const T*, const T*, const T*, int,           \
                                const int32_t*, const T*, hipStream_t);                                               \
