@@ -20,9 +20,12 @@ written definition, which the GPU library implements independently:
   node aggregates; coarse operators are Galerkin products P^T M P;
 * smoother: Chebyshev polynomial of degree ``cheb_degree`` (default 1, i.e.
   damped point Jacobi with weight 1/theta) in D^{-1} M (D the point diagonal)
-  on [lambda/30, lambda] with lambda = 1.1 x the estimate from 10 power
-  iterations on D^{-1} M from the start vector
-  x_i = 0.5 + ((i * 2654435761) mod 2^32)/2^32; one pre- and one
+  on [lambda/30, lambda]; lambda must bound the spectral radius of D^{-1} M
+  from above, else the smoother amplifies the top modes.  It is the smaller of
+  the Gershgorin bound max_i sum_j |M_ij / D_ii| (a guaranteed bound) and
+  1.2 x the estimate from 20 power iterations on D^{-1} M from the start
+  vector x_i = 0.5 + ((i * 2654435761) mod 2^32)/2^32 (power iteration
+  approaches the spectral radius from below); one pre- and one
   post-smoothing application (zero initial guess before pre-smoothing);
 * coarsest level: dense LU solve in FP64.
 """
@@ -105,6 +108,17 @@ def lambda_max(M: sp.csr_matrix, dinv: np.ndarray, iters: int = 10) -> float:
     return lam
 
 
+def gershgorin_bound(M: sp.csr_matrix, dinv: np.ndarray) -> float:
+    """max_i sum_j |dinv_i M_ij|: every eigenvalue of D^{-1} M lies in a
+    Gershgorin disc of a row, so its modulus is at most this."""
+    return float(np.max(np.abs(sp.diags(dinv) @ M).sum(axis=1)))
+
+
+def smoother_bound(M: sp.csr_matrix, dinv: np.ndarray) -> float:
+    """Upper end of the smoother interval (module docstring)."""
+    return min(gershgorin_bound(M, dinv), 1.2 * lambda_max(M, dinv, 20))
+
+
 def chebyshev(M, dinv, b, x, degree, lmin, lmax):
     """Chebyshev iteration of the given degree for M x = b, preconditioned by
     D^{-1}, with eigenvalue interval [lmin, lmax] of D^{-1} M."""
@@ -144,7 +158,7 @@ class AMG:
             self.P.append(P)
             self.M.append((P.T @ self.M[-1] @ P).tocsr())
         self.dinv = [1.0 / Ml.diagonal() for Ml in self.M[:-1]]
-        self.lmax = [1.1 * lambda_max(Ml, di) for Ml, di in zip(self.M[:-1], self.dinv)]
+        self.lmax = [smoother_bound(Ml, di) for Ml, di in zip(self.M[:-1], self.dinv)]
         self.lu = sla.lu_factor(self.M[-1].toarray())
 
     @property

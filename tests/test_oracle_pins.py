@@ -452,6 +452,32 @@ def test_power_start_vector_values():
     assert x[2] == 0.5 + ((2 * 2654435761) % 2 ** 32) / 2 ** 32
 
 
+def test_gershgorin_bound_brute_force():
+    """Row sums of |D^{-1} M| by explicit loops over a small dense matrix."""
+    rng = np.random.default_rng(5)
+    A = rng.standard_normal((7, 7)) + 6 * np.eye(7)
+    A[A < -1.0] = 0.0
+    d = 1.0 / np.diag(A)
+    want = max(sum(abs(d[i] * A[i, j]) for j in range(7)) for i in range(7))
+    assert amg.gershgorin_bound(sp.csr_matrix(A), d) == pytest.approx(want, rel=1e-15)
+
+
+@pytest.mark.parametrize("name", ["cube", "channel2", "pipe_tiny"])
+def test_smoother_bound_covers_spectrum(name):
+    """The smoother interval's upper end bounds the spectral radius of
+    D^{-1} M on every smoothed level (dense eigenvalues), for both
+    hierarchies; a smaller value would make the damped Jacobi step amplify the
+    top modes."""
+    c = get_case(name)
+    S = get_assembled(name)
+    ns = kr.NestedSolver(S, amg.node_adjacency(c.n_nodes, c.tets), kr.SolveOpts(coarse_nodes=16))
+    for h in (ns.amgA, ns.amgS):
+        assert h.n_levels >= 2
+        for Ml, di, lm in zip(h.M[:-1], h.dinv, h.lmax):
+            rho = np.abs(np.linalg.eigvals(np.diag(di) @ Ml.toarray())).max()
+            assert rho <= lm <= amg.gershgorin_bound(Ml, di) * (1 + 1e-15)
+
+
 def test_chebyshev_matches_scalar_polynomial():
     """For M = diag(lam), D = M... use D = I via a unit diagonal: x = (1 - p(lam)) b / lam
     with p(t) = T_k((theta - t)/delta) / T_k(theta/delta)."""
