@@ -170,6 +170,162 @@ def pipe(size: str = "pipe_200k", seed: int = 2, R: float = 1e3, radius: float =
                    {"seed": seed, "m": m, "nr": nr, "layers": layers, "pressure": "p = 0 everywhere"})
 
 
+# ----------------------------------------------------------------------------
+# Y-bifurcation (carved Kuhn lattice)
+# ----------------------------------------------------------------------------
+
+YBIF_SIZES = {
+    # name: lattice spacing -> about 7e3 / 1e6 nodes
+    "ybif_small": 0.1,
+    "ybif_1m": 0.0176,
+}
+
+
+def ybif(size: str = "ybif_1m", seed: int = 4, R=(1.5e3, 3.0e3), umax: float = 30.0, noise: float = 0.01,
+         rho: float = 1.06, mu: float = 0.04, dt: float = 1e-3) -> Case:
+    """Parent tube r = 0.5 along z over [0, 4]; two daughters r = 0.35 from
+    (0, 0, 4) at +-30 degrees from z in the x-z plane, cut by the plane
+    z = 4 + 3 cos 30 deg (planar, disjoint outlet caps: outlet 1 at x < 0,
+    outlet 2 at x > 0).  Mesh: the Kuhn tetrahedra of the lattice cells whose
+    centre is inside (staircase wall).  Inflow: parabolic v_z with peak umax
+    over the parent radius; no-slip on the rest of the boundary (outlet rims
+    included).  State: per-branch axial Poiseuille (each daughter carries half
+    the parent flow) plus N(0, (noise*umax)^2) on free components; p = 0."""
+    h = YBIF_SIZES[size]
+    rp, rd, lp, ld = 0.5, 0.35, 4.0, 3.0
+    th = np.radians(30.0)
+    ztop = lp + ld * np.cos(th)
+    P0 = np.array([0.0, 0.0, lp])
+    dirs = [np.array([-np.sin(th), 0.0, np.cos(th)]), np.array([np.sin(th), 0.0, np.cos(th)])]
+
+    def axial(p):
+        """branch (0 parent, 1/2 daughters), radial distance, unit axis"""
+        q = p - P0
+        br = np.zeros(len(p), np.int64)
+        rad = np.sqrt(p[:, 0] ** 2 + p[:, 1] ** 2)
+        for b, d in enumerate(dirs, start=1):
+            a = q @ d
+            rr = np.linalg.norm(q - a[:, None] * d, axis=1)
+            sel = (p[:, 2] > lp) & ((p[:, 0] < 0) if b == 1 else (p[:, 0] >= 0))
+            br[sel] = b
+            rad[sel] = rr[sel]
+        return br, rad
+
+    def inside(c):
+        inp = (c[:, 0] ** 2 + c[:, 1] ** 2 <= rp ** 2) & (c[:, 2] <= lp)
+        q = c - P0
+        for d in dirs:
+            a = q @ d
+            rr = np.linalg.norm(q - a[:, None] * d, axis=1)
+            inp |= (a >= 0.0) & (rr <= rd)
+        return inp & (c[:, 2] >= 0.0) & (c[:, 2] <= ztop)
+
+    xmax = ld * np.sin(th) + rd / np.cos(th) + h
+    lo, hi = (-xmax, -rp, 0.0), (xmax, rp, ztop)
+    shape = (int(round(2 * xmax / h)), int(round(2 * rp / h)), int(round(ztop / h)))
+    xyz, tets = meshes.carved_kuhn(inside, lo, hi, shape)
+    N = len(xyz)
+    tol = 1e-9
+    bf = meshes.boundary_faces(xyz, tets)
+    fz = xyz[bf][:, :, 2]
+    inl = np.all(np.abs(fz) < tol, axis=1)
+    outl = np.all(np.abs(fz - ztop) < tol, axis=1)
+    fx = xyz[bf][:, :, 0].mean(axis=1)
+    wall = np.zeros(N, bool)
+    wall[bf[~inl & ~outl].ravel()] = True
+    inlet = np.zeros(N, bool)
+    inlet[bf[inl].ravel()] = True
+    dirn = wall | inlet
+    mask = np.zeros((N, 4), np.uint8)
+    mask[dirn, :3] = 1
+    br, rad = axial(xyz)
+    qp = np.pi * rp ** 2 * umax / 2.0          # parent flow (Poiseuille mean = peak/2)
+    ud = 2.0 * (qp / 2.0) / (np.pi * rd ** 2)  # daughter peak carrying half of it
+    v = np.zeros((N, 3))
+    par = br == 0
+    v[par, 2] = umax * np.clip(1.0 - rad[par] ** 2 / rp ** 2, 0.0, None)
+    for b, d in enumerate(dirs, start=1):
+        s = br == b
+        v[s] = (ud * np.clip(1.0 - rad[s] ** 2 / rd ** 2, 0.0, None))[:, None] * d[None, :]
+    v[wall] = 0.0
+    free = ~dirn
+    rng = np.random.Generator(np.random.PCG64(seed))
+    v[free] += rng.normal(0.0, noise * umax, size=(int(free.sum()), 3))
+    outs = [bf[outl & (fx < 0)], bf[outl & (fx >= 0)]]
+    return _finish(size, xyz, tets, mask, outs, v, np.zeros(N), rho, mu, dt, 0.5, np.asarray(R, float),
+                   {"seed": seed, "h": h, "lattice": shape, "pressure": "p = 0 everywhere",
+                    "wall": "staircase (cells with centre inside)"})
+
+
+# ----------------------------------------------------------------------------
+# Contraction-expansion tube (swept O-grid with a sudden expansion)
+# ----------------------------------------------------------------------------
+
+CONEXP_SIZES = {
+    # name: (m, nr, annulus rings, cone layers, throat layers, expansion layers)
+    "conexp_small": (6, 3, 4, 6, 10, 16),
+    "conexp_4m": (24, 10, 20, 100, 200, 1000),
+}
+
+
+def conexp(size: str = "conexp_4m", seed: int = 5, R: float = 1e5, re_t: float = 3500.0,
+           rho: float = 1.0, mu: float = 0.0035, dt: float = 5e-4, n_modes: int = 16,
+           rms: float = 0.05) -> Case:
+    """Inlet r = 0.6, cone of 20 deg included angle to a throat r = 0.2 of
+    length 4, sudden expansion to r = 0.6 for length 12.  Throat Reynolds
+    number re_t fixes the throat mean velocity u_t = re_t mu / (rho 2 r_t);
+    the inflow is parabolic with the same flow rate.  Axial layers: uniform in
+    the cone and throat, geometrically graded after the step (finest at the
+    step plane).  State: the local-radius Poiseuille profile carrying that
+    flow, plus ``n_modes`` divergence-free Fourier modes (wavelengths
+    U[2 r_t, 8 r_t], random directions and phases) scaled to an RMS of
+    rms * u_t over the free components; zero at Dirichlet DOFs; p = 0."""
+    m, nr, nrings, kc, kt, kw = CONEXP_SIZES[size]
+    ri, rt, rw, lt, lw = 0.6, 0.2, 0.6, 4.0, 12.0
+    lc = (ri - rt) / np.tan(np.radians(10.0))
+    zs = lc + lt
+
+    def r_of(z):
+        return ri + (rt - ri) * min(max(z / lc, 0.0), 1.0) if z < lc else rt
+
+    z_narrow = np.concatenate([np.linspace(0.0, lc, kc + 1)[:-1], np.linspace(lc, zs, kt + 1)])
+    beta = 2.5
+    t = np.linspace(0.0, 1.0, kw + 1)
+    z_wide = zs + lw * (np.expm1(beta * t) / np.expm1(beta))
+    xyz, tets, wall, inl_faces, out_faces, layer_of = meshes.swept_step_tube(
+        r_of, z_narrow, z_wide, rt, rw, m, nr, nrings)
+    N = len(xyz)
+    inlet = layer_of == 0
+    mask = np.zeros((N, 4), np.uint8)
+    dirn = wall | inlet
+    mask[dirn, :3] = 1
+    u_t = re_t * mu / (rho * 2.0 * rt)
+    q = np.pi * rt ** 2 * u_t
+    z = xyz[:, 2]
+    rloc = np.where(z < lc, ri + (rt - ri) * np.clip(z / lc, 0.0, 1.0), rt)
+    rloc = np.where(z < zs - 1e-12, rloc, rw)
+    rad2 = (xyz[:, 0] ** 2 + xyz[:, 1] ** 2) / rloc ** 2
+    v = np.zeros((N, 3))
+    v[:, 2] = 2.0 * q / (np.pi * rloc ** 2) * np.clip(1.0 - rad2, 0.0, None)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    pert = np.zeros((N, 3))
+    for _ in range(n_modes):
+        lam = rng.uniform(2 * rt, 8 * rt)
+        kdir = rng.normal(size=3)
+        kdir /= np.linalg.norm(kdir)
+        e = np.cross(kdir, rng.normal(size=3))
+        e /= np.linalg.norm(e)
+        phase = rng.uniform(0.0, 2 * np.pi)
+        pert += np.cos((2 * np.pi / lam) * (xyz @ kdir) + phase)[:, None] * e[None, :]
+    free = ~dirn
+    scale = rms * u_t / np.sqrt(np.mean(pert[free] ** 2))
+    v[free] += scale * pert[free]
+    v[wall] = 0.0
+    return _finish(size, xyz, tets, mask, [out_faces], v, np.zeros(N), rho, mu, dt, 0.5, np.asarray([R], float),
+                   {"seed": seed, "m": m, "nr": nr, "rings": nrings, "layers": (kc, kt, kw), "u_t": u_t,
+                    "pressure": "p = 0 everywhere"})
+
+
 def build(name: str, **kw) -> Case:
     if name.startswith("cube"):
         return cube_lid(**kw)
@@ -177,4 +333,8 @@ def build(name: str, **kw) -> Case:
         return channel2(**kw)
     if name in PIPE_SIZES:
         return pipe(name, **kw)
+    if name in YBIF_SIZES:
+        return ybif(name, **kw)
+    if name in CONEXP_SIZES:
+        return conexp(name, **kw)
     raise KeyError(name)

@@ -209,3 +209,160 @@ def swept_tube(radius_of_z, z_nodes: np.ndarray, m: int, nr: int):
     inlet_faces = tris[:, [0, 2, 1]].astype(np.int32)
     outlet_faces = (tris + layers * nd).astype(np.int32)
     return xyz, tets, rim_all, layer_of, inlet_faces, outlet_faces
+
+
+# ----------------------------------------------------------------------------
+# Carved Kuhn lattice (cells whose centre lies inside a region)
+# ----------------------------------------------------------------------------
+
+
+def carved_kuhn(inside, lo, hi, shape):
+    """Kuhn tetrahedra of the lattice cells of the box [lo, hi] (``shape`` =
+    cells per axis) whose centre satisfies ``inside(centres [n, 3]) -> bool``.
+
+    Unused lattice nodes are dropped; node order follows the lattice index
+    (x fastest, then y, then z).  Returns xyz, tets (positively oriented).
+    """
+    lo = np.asarray(lo, float)
+    hi = np.asarray(hi, float)
+    nx, ny, nz = (int(s) for s in shape)
+    h = (hi - lo) / np.array([nx, ny, nz], float)
+    kk, jj, ii = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    ii, jj, kk = ii.ravel(), jj.ravel(), kk.ravel()
+    cen = lo + (np.stack([ii, jj, kk], 1) + 0.5) * h
+    keep = inside(cen)
+    ii, jj, kk = ii[keep], jj[keep], kk[keep]
+
+    def nid(i, j, k):
+        return i + (nx + 1) * (j + (ny + 1) * k.astype(np.int64))
+
+    tets = []
+    for perm in itertools.permutations(range(3)):
+        c = [np.zeros_like(ii), np.zeros_like(ii), np.zeros_like(ii)]
+        verts = [nid(ii, jj, kk)]
+        for axis in perm:
+            c[axis] = c[axis] + 1
+            verts.append(nid(ii + c[0], jj + c[1], kk + c[2]))
+        tets.append(np.stack(verts, axis=1))
+    tets = np.stack(tets, axis=1).reshape(-1, 4)
+    used, tets = np.unique(tets, return_inverse=True)
+    tets = tets.reshape(-1, 4)
+    i = used % (nx + 1)
+    j = (used // (nx + 1)) % (ny + 1)
+    k = used // ((nx + 1) * (ny + 1))
+    xyz = lo + np.stack([i, j, k], 1).astype(np.float64) * h
+    return xyz, _orient(xyz, tets)
+
+
+# ----------------------------------------------------------------------------
+# Swept tube with a sudden expansion: an O-grid core disk swept through a
+# variable-radius section, then the core plus annulus rings (so the step
+# plane conforms) swept through the wide section.
+# ----------------------------------------------------------------------------
+
+
+def annulus_rings(pts, rim_walk, n_rings: int, r_out: float):
+    """Rings outside the unit disk: points at radii 1 + (r_out - 1) k / n_rings
+    (k = 1..n_rings) along the angles of the rim walk, and the triangles
+    between consecutive rings.  Returns (new points [n, 2], triangles [t, 3]
+    indexed into the concatenation [pts; new points], outer-rim mask of the
+    concatenation)."""
+    nb = len(rim_walk)
+    base = len(pts)
+    ang = np.arctan2(pts[rim_walk, 1], pts[rim_walk, 0])
+    new = []
+    for k in range(1, n_rings + 1):
+        r = 1.0 + (r_out - 1.0) * k / n_rings
+        new.append(np.stack([r * np.cos(ang), r * np.sin(ang)], 1))
+    new = np.concatenate(new, 0)
+
+    def idx(t, k):
+        t = t % nb
+        return rim_walk[t] if k == 0 else base + (k - 1) * nb + t
+
+    tris = []
+    for k in range(n_rings):
+        for t in range(nb):
+            a, b, c, d = idx(t, k), idx(t + 1, k), idx(t + 1, k + 1), idx(t, k + 1)
+            tris += [(a, b, c), (a, c, d)]
+    tris = np.array(tris, dtype=np.int64)
+    allp = np.concatenate([pts, new], 0)
+    e1 = allp[tris[:, 1]] - allp[tris[:, 0]]
+    e2 = allp[tris[:, 2]] - allp[tris[:, 0]]
+    cw = (e1[:, 0] * e2[:, 1] - e1[:, 1] * e2[:, 0]) < 0
+    tris[cw, 1], tris[cw, 2] = tris[cw, 2].copy(), tris[cw, 1].copy()
+    outer = np.zeros(len(allp), dtype=bool)
+    outer[base + (n_rings - 1) * nb:] = True
+    return new, tris.astype(np.int32), outer
+
+
+def _prisms(tris, gid_lo, gid_hi):
+    """Three tetrahedra per prism (as sweep_prisms, cut by the 2-D vertex
+    order so neighbouring prisms agree), with per-layer index maps."""
+    st = np.sort(tris.astype(np.int64), axis=1)
+    a, b, c = st[:, 0], st[:, 1], st[:, 2]
+    L, H = gid_lo, gid_hi
+    return np.concatenate([np.stack([L[a], L[b], L[c], H[c]], 1),
+                           np.stack([L[a], L[b], H[b], H[c]], 1),
+                           np.stack([L[a], H[a], H[b], H[c]], 1)], 0)
+
+
+def swept_step_tube(radius_of_z, z_narrow: np.ndarray, z_wide: np.ndarray, r_step: float, r_wide: float,
+                    m: int, nr: int, n_rings: int):
+    """Tube along z: the core disk scaled to ``radius_of_z`` at the layers
+    ``z_narrow`` (ending at the step plane z_narrow[-1] == z_wide[0] where the
+    radius is r_step), then core + annulus (out to r_wide) at the layers
+    ``z_wide``.  Returns xyz, tets, wall-node mask, inlet faces, outlet faces,
+    layer index per node (narrow layers first)."""
+    pts, tris, rim = ogrid_disk(m, nr)
+    nd = len(pts)
+    # rim walk in angular order (the rim points of the O-grid, counter-clockwise)
+    rim_idx = np.nonzero(rim)[0]
+    ang = np.arctan2(pts[rim_idx, 1], pts[rim_idx, 0])
+    walk = rim_idx[np.argsort(ang)]
+    new, atris, outer = annulus_rings(pts, walk, n_rings, r_wide / r_step)
+    nfull = nd + len(new)
+    full_pts = np.concatenate([pts, new], 0)
+    all_tris = np.concatenate([tris, atris], 0)
+    K1 = len(z_narrow) - 1          # narrow layers below the step plane
+    K2 = len(z_wide) - 1
+    # node ids: narrow layers 0..K1-1 hold nd nodes; wide layers 0..K2 hold nfull
+    n_narrow = K1 * nd
+    N = n_narrow + (K2 + 1) * nfull
+    xyz = np.empty((N, 3))
+    layer_of = np.empty(N, np.int64)
+    for lay in range(K1):
+        z = z_narrow[lay]
+        r = radius_of_z(z)
+        s = slice(lay * nd, (lay + 1) * nd)
+        xyz[s, 0], xyz[s, 1], xyz[s, 2] = r * pts[:, 0], r * pts[:, 1], z
+        layer_of[s] = lay
+    for lay in range(K2 + 1):
+        z = z_wide[lay]
+        s = slice(n_narrow + lay * nfull, n_narrow + (lay + 1) * nfull)
+        xyz[s, 0], xyz[s, 1], xyz[s, 2] = r_step * full_pts[:, 0], r_step * full_pts[:, 1], z
+        layer_of[s] = K1 + lay
+
+    def gid_narrow(lay):  # disk nodes of narrow layer lay (lay == K1: the step layer)
+        if lay < K1:
+            return np.arange(lay * nd, (lay + 1) * nd)
+        return n_narrow + np.arange(nd)
+
+    def gid_wide(lay):
+        return n_narrow + lay * nfull + np.arange(nfull)
+
+    tets = [_prisms(tris, gid_narrow(l), gid_narrow(l + 1)) for l in range(K1)]
+    tets += [_prisms(all_tris, gid_wide(l), gid_wide(l + 1)) for l in range(K2)]
+    tets = _orient(xyz, np.concatenate(tets, 0))
+    wall = np.zeros(N, dtype=bool)
+    for lay in range(K1):
+        wall[lay * nd + np.nonzero(rim)[0]] = True
+    for lay in range(K2 + 1):
+        wall[n_narrow + lay * nfull + np.nonzero(outer)[0]] = True
+    # the step plane: the core rim (the corner of the step) and the annulus
+    # nodes of the first wide layer (r_step <= r <= r_wide) are wall
+    wall[n_narrow + np.nonzero(rim)[0]] = True
+    wall[n_narrow + nd + np.arange(len(new))] = True
+    inlet_faces = tris[:, [0, 2, 1]].astype(np.int32)
+    outlet_faces = (all_tris + n_narrow + K2 * nfull).astype(np.int32)
+    return xyz, tets, wall, inlet_faces, outlet_faces, layer_of

@@ -835,21 +835,28 @@ ns_status fgmres(Ctl& K, const double* b, double* x) {
 // numeric (Galerkin sums, Jacobi diagonals, lambda_max, coarsest inverse)
 // ---------------------------------------------------------------------------
 
-double power_lambda(ns_ctx* c, const BlockOp<double>& M, int bs, const double* dinv, double* x, double* y,
-                    hipStream_t st) {
+// Upper end of the smoother interval of a level: the smaller of the
+// Gershgorin bound of D^{-1} M (guaranteed) and kPowerSafety times the
+// estimate from kPowerIters power iterations (which approach the spectral
+// radius from below) from the fixed start vector.
+constexpr int kPowerIters = 20;
+constexpr double kPowerSafety = 1.2;
+double smoother_bound(ns_ctx* c, const BlockOp<double>& M, int bs, const double* dinv, double* x, double* y,
+                      hipStream_t st) {
     const int64_t n = (int64_t)M.n * bs;
     power_start(n, x, st);
     double* nrm = c->kw_out.status + 6;
     norm2<double>(n, x, nrm, c->d_red, st);
     scale_by<double>(n, x, nrm, true, x, st);
-    for (int it = 0; it < 10; ++it) {
+    for (int it = 0; it < kPowerIters; ++it) {
         spmv<double>(bs, bs, M, x, y, 1.0, nullptr, 0.0, dinv, nullptr, st);
         norm2<double>(n, y, nrm, c->d_red, st);
         scale_by<double>(n, y, nrm, true, x, st);
     }
+    gershgorin_bound(M, bs, dinv, c->d_red, nrm + 1, st);
     check_launch();
-    read_status(c, nrm, 1, st);
-    return c->h_pinned[0];
+    read_status(c, nrm, 2, st);
+    return std::min(c->h_pinned[1], kPowerSafety * c->h_pinned[0]);
 }
 
 void setup_system(ns_ctx* c, SystemDev& y, bool need32, hipStream_t st) {
@@ -890,7 +897,7 @@ void setup_system(ns_ctx* c, SystemDev& y, bool need32, hipStream_t st) {
                 M.dextra = d.dextra64;
                 M.lanes = lanes_for(d.nnz, d.n);
                 if (l + 1 < L) {
-                    d.lmax = 1.1 * power_lambda(c, M, d.bs, d.dinv64, d.x0, d.r, st);
+                    d.lmax = smoother_bound(c, M, d.bs, d.dinv64, d.x0, d.r, st);
                 } else {
                     dense_from_csr(d.n, d.bs, d.rp, d.col, d.v64, d.rstride, d.cstride, d.dextra64, d.work, st);
                     gauss_jordan_inverse(d.n * d.bs, d.work, d.inv, st);

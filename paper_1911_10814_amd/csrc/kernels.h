@@ -148,6 +148,9 @@ void shat_numeric(int n, const int32_t* rp, const int32_t* col, const double* V,
 void gauss_jordan_inverse(int n, double* work, double* inv, hipStream_t st);
 void dense_from_csr(int nb, int bs, const int32_t* rp, const int32_t* col, const double* v, int64_t rs,
                     int64_t cs, const double* dextra, double* work, hipStream_t st);
+// out[0] = max_r |dinv_r| sum_c |M_rc| (Gershgorin bound of D^{-1} M); part: >= kMaxRedBlocks scratch
+void gershgorin_bound(const BlockOp<double>& M, int bs, const double* dinv, double* part, double* out,
+                      hipStream_t st);
 void power_start(int64_t n, double* x, hipStream_t st);
 void rank_one_diag(int n_slots, const int32_t* onode, const int32_t* oid, const double* amsk, const double* ck,
                    double* dK, hipStream_t st);

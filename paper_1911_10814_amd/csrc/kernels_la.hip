@@ -1183,6 +1183,56 @@ void power_start(int64_t n, double* x, hipStream_t st) {
     hipLaunchKernelGGL(k_power_start, dim3(grid_for(n)), dim3(kBlock), 0, st, n, x);
 }
 
+// Gershgorin bound of D^{-1} M: max over point rows of |dinv_r| sum_c |M_rc|
+// (the extra diagonal added to the diagonal entry).  Per-block maxima into
+// part[blockIdx.x], then a one-block maximum into out[0].
+__global__ __launch_bounds__(kBlock) void k_gersh_part(BlockOp<double> M, int bs, const double* __restrict__ dinv,
+                                                       double* __restrict__ part) {
+    __shared__ double lds[kBlock / 64];
+    double mx = 0.0;
+    const int64_t nr = (int64_t)M.n * bs;
+    for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < nr; t += (int64_t)gridDim.x * kBlock) {
+        const int i = (int)(t / bs), r = (int)(t % bs);
+        double s = 0.0;
+        for (int k = M.rp[i]; k < M.rp[i + 1]; ++k) {
+            const bool diag = M.col[k] == i;
+            for (int c = 0; c < bs; ++c) {
+                double v = M.v[r * M.rs + c * M.cs + k];
+                if (diag && c == r && M.dextra) v += M.dextra[t];
+                s += fabs(v);
+            }
+        }
+        mx = fmax(mx, s * fabs(dinv[t]));
+    }
+    for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
+    if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = 0.0;
+        for (int w = 0; w < kBlock / 64; ++w) m = fmax(m, lds[w]);
+        part[blockIdx.x] = m;
+    }
+}
+__global__ void k_max_fin(const double* part, int G, double* out) {
+    __shared__ double lds[kBlock / 64];
+    double mx = 0.0;
+    for (int b = threadIdx.x; b < G; b += kBlock) mx = fmax(mx, part[b]);
+    for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
+    if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = 0.0;
+        for (int w = 0; w < kBlock / 64; ++w) m = fmax(m, lds[w]);
+        out[0] = m;
+    }
+}
+void gershgorin_bound(const BlockOp<double>& M, int bs, const double* dinv, double* part, double* out,
+                      hipStream_t st) {
+    const int G = (int)std::min<int64_t>(grid_for((int64_t)M.n * bs), kMaxRedBlocks);
+    hipLaunchKernelGGL(k_gersh_part, dim3(G), dim3(kBlock), 0, st, M, bs, dinv, part);
+    hipLaunchKernelGGL(k_max_fin, dim3(1), dim3(kBlock), 0, st, part, G, out);
+}
+
 // dK_{3 node + c} = sum_k c_k (a^k_{node,c})^2 over outlet slots (outlets are disjoint)
 __global__ void k_rank_one_diag(int n_slots, const int32_t* onode, const int32_t* oid, const double* amsk,
                                 const double* ck, double* dK) {

@@ -13,20 +13,6 @@
 namespace ns {
 namespace {
 
-// CSR of the union of per-row neighbour lists (sorted, duplicates removed).
-Csr csr_from_pairs(int n, std::vector<std::pair<int32_t, int32_t>>& pairs) {
-    std::sort(pairs.begin(), pairs.end());
-    pairs.erase(std::unique(pairs.begin(), pairs.end()), pairs.end());
-    Csr c;
-    c.n = n;
-    c.rp.assign(n + 1, 0);
-    for (auto& p : pairs) c.rp[p.first + 1]++;
-    for (int i = 0; i < n; ++i) c.rp[i + 1] += c.rp[i];
-    c.col.resize(pairs.size());
-    for (size_t k = 0; k < pairs.size(); ++k) c.col[k] = pairs[k].second;
-    return c;
-}
-
 int64_t find_in_row(const Csr& c, int32_t i, int32_t j) {
     auto b = c.col.begin() + c.rp[i], e = c.col.begin() + c.rp[i + 1];
     auto it = std::lower_bound(b, e, j);
@@ -55,27 +41,68 @@ std::vector<int32_t> greedy_matching(const Csr& c, int& nc) {
     return agg;
 }
 
-// Quotient pattern: (I,J) present when some fine (i,j) maps to it.
+// Members of every group: CSR (ptr [ng+1], items ascending within a group).
+static void group_lists(const std::vector<int32_t>& grp, int ng, std::vector<int32_t>& ptr,
+                        std::vector<int32_t>& items) {
+    ptr.assign(ng + 1, 0);
+    for (int32_t g : grp) ptr[g + 1]++;
+    for (int c = 0; c < ng; ++c) ptr[c + 1] += ptr[c];
+    items.resize(grp.size());
+    std::vector<int32_t> fill(ptr.begin(), ptr.end() - 1);
+    for (size_t i = 0; i < grp.size(); ++i) items[fill[grp[i]]++] = (int32_t)i;
+}
+
+// Quotient pattern: (I,J) present when some fine (i,j) maps to it (rows built
+// one coarse node at a time from its members, columns sorted).
 Csr quotient(const Csr& c, const std::vector<int32_t>& agg, int nc) {
-    std::vector<std::pair<int32_t, int32_t>> pr;
-    pr.reserve(c.col.size());
-    for (int i = 0; i < c.n; ++i)
-        for (int k = c.rp[i]; k < c.rp[i + 1]; ++k) pr.emplace_back(agg[i], agg[c.col[k]]);
-    return csr_from_pairs(nc, pr);
+    std::vector<int32_t> ptr, mem;
+    group_lists(agg, nc, ptr, mem);
+    Csr q;
+    q.n = nc;
+    q.rp.assign(nc + 1, 0);
+    q.col.reserve(c.col.size() / 2);
+    std::vector<int32_t> mark(nc, -1), row;
+    for (int I = 0; I < nc; ++I) {
+        row.clear();
+        for (int t = ptr[I]; t < ptr[I + 1]; ++t) {
+            const int i = mem[t];
+            for (int k = c.rp[i]; k < c.rp[i + 1]; ++k) {
+                const int J = agg[c.col[k]];
+                if (mark[J] != I) {
+                    mark[J] = I;
+                    row.push_back(J);
+                }
+            }
+        }
+        std::sort(row.begin(), row.end());
+        q.col.insert(q.col.end(), row.begin(), row.end());
+        q.rp[I + 1] = (int32_t)q.col.size();
+    }
+    q.col.shrink_to_fit();
+    return q;
 }
 
 // Gather list: every fine nnz k is appended (ascending k) to the list of the
-// coarse nnz it sums into.
+// coarse nnz it sums into.  The target of k is looked up through the
+// positions of coarse row agg[i]'s columns, set once per coarse row.
 void gather_lists(const Csr& fine, const Csr& coarse, const std::vector<int32_t>& agg,
                   std::vector<int32_t>& gptr, std::vector<int32_t>& gidx) {
+    std::vector<int32_t> ptr, mem;
+    group_lists(agg, coarse.n, ptr, mem);
     std::vector<int32_t> tgt(fine.col.size());
+    std::vector<int32_t> pos(coarse.n, -1);
     gptr.assign(coarse.col.size() + 1, 0);
-    for (int i = 0; i < fine.n; ++i)
-        for (int k = fine.rp[i]; k < fine.rp[i + 1]; ++k) {
-            int64_t q = find_in_row(coarse, agg[i], agg[fine.col[k]]);
-            tgt[k] = (int32_t)q;
-            gptr[q + 1]++;
+    for (int I = 0; I < coarse.n; ++I) {
+        for (int q = coarse.rp[I]; q < coarse.rp[I + 1]; ++q) pos[coarse.col[q]] = q;
+        for (int t = ptr[I]; t < ptr[I + 1]; ++t) {
+            const int i = mem[t];
+            for (int k = fine.rp[i]; k < fine.rp[i + 1]; ++k) {
+                const int32_t q = pos[agg[fine.col[k]]];
+                tgt[k] = q;
+                gptr[q + 1]++;
+            }
         }
+    }
     for (size_t q = 0; q < coarse.col.size(); ++q) gptr[q + 1] += gptr[q];
     gidx.resize(fine.col.size());
     std::vector<int32_t> fill(gptr.begin(), gptr.end() - 1);
@@ -116,14 +143,33 @@ std::string build_symbolic(const ns_mesh* m, const ns_ctx_opts& o, Symbolic& S) 
     for (int64_t k = 0; k < (int64_t)E * 4; ++k)
         if (m->h_tets[k] < 0 || m->h_tets[k] >= N) return "tetrahedron vertex index out of range";
 
+    // node -> element incidence (elements ascending per node)
+    std::vector<int32_t> nptr, nelem;
+    {
+        std::vector<int32_t> vert(m->h_tets, m->h_tets + (size_t)E * 4);
+        group_lists(vert, N, nptr, nelem);  // items: element slots 4e+a
+    }
     // node graph (P1: nodes sharing an element), with the diagonal
     {
-        std::vector<std::pair<int32_t, int32_t>> pr;
-        pr.reserve((size_t)E * 16);
-        for (int e = 0; e < E; ++e)
-            for (int a = 0; a < 4; ++a)
-                for (int b = 0; b < 4; ++b) pr.emplace_back(m->h_tets[4 * e + a], m->h_tets[4 * e + b]);
-        S.g = csr_from_pairs(N, pr);
+        Csr& g = S.g;
+        g.n = N;
+        g.rp.assign(N + 1, 0);
+        g.col.reserve((size_t)N * 16);
+        std::vector<int32_t> mark(N, -1), row;
+        for (int i = 0; i < N; ++i) {
+            row.clear();
+            for (int t = nptr[i]; t < nptr[i + 1]; ++t) {
+                const int32_t* tet = m->h_tets + 4 * (size_t)(nelem[t] / 4);
+                for (int b = 0; b < 4; ++b)
+                    if (mark[tet[b]] != i) {
+                        mark[tet[b]] = i;
+                        row.push_back(tet[b]);
+                    }
+            }
+            std::sort(row.begin(), row.end());
+            g.col.insert(g.col.end(), row.begin(), row.end());
+            g.rp[i + 1] = (int32_t)g.col.size();
+        }
     }
     const Csr& g = S.g;
     const int64_t nnzb = g.nnz();
@@ -154,11 +200,21 @@ std::string build_symbolic(const ns_mesh* m, const ns_ctx_opts& o, Symbolic& S) 
         for (int e = 0; e < E; ++e) S.elem_perm[fill[col[e]]++] = e;
         S.tets.resize((size_t)E * 4);
         S.emap.resize((size_t)E * 16);
+        std::vector<int32_t> sorted_pos(E);
         for (int s = 0; s < E; ++s) {
+            sorted_pos[S.elem_perm[s]] = s;
             const int32_t* t = m->h_tets + 4 * (size_t)S.elem_perm[s];
-            for (int a = 0; a < 4; ++a) {
-                S.tets[4 * (size_t)s + a] = t[a];
-                for (int b = 0; b < 4; ++b) S.emap[16 * (size_t)s + 4 * a + b] = (int32_t)find_in_row(g, t[a], t[b]);
+            for (int a = 0; a < 4; ++a) S.tets[4 * (size_t)s + a] = t[a];
+        }
+        // block index of (t[a], t[b]): positions of row t[a]'s columns, set
+        // once per node, read by every element slot at that node
+        std::vector<int32_t> pos(N, -1);
+        for (int i = 0; i < N; ++i) {
+            for (int k = g.rp[i]; k < g.rp[i + 1]; ++k) pos[g.col[k]] = k;
+            for (int t = nptr[i]; t < nptr[i + 1]; ++t) {
+                const int e = nelem[t] / 4, a = nelem[t] % 4;
+                const int32_t* tet = m->h_tets + 4 * (size_t)e;
+                for (int b = 0; b < 4; ++b) S.emap[16 * (size_t)sorted_pos[e] + 4 * a + b] = pos[tet[b]];
             }
         }
     }
