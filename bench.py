@@ -191,6 +191,7 @@ def main():
     for name, o in (("fp32_inner_jacobi", SolveOptions(precision="fp32_inner", pc_A="jacobi")),
                     ("fp64_jacobi", SolveOptions(precision="fp64", pc_A="jacobi")),
                     ("fp32_inner_cheb1", SolveOptions(precision="fp32_inner", cheb_degree=1)),
+                    ("fp32_inner_cheb2_ratio30", SolveOptions(precision="fp32_inner", cheb_ratio=30.0)),
                     ("fp32_inner_cheb3", SolveOptions(precision="fp32_inner", cheb_degree=3))):
         runs = [solve_fresh(o)[1] for _ in range(args.steps)]
         variants[name] = {"solve_ms": round(statistics.median(r["wall_ms"] for r in runs), 3),

@@ -113,12 +113,14 @@ typedef struct {
     double rtol_A;          /* delta^r_A, intermediate A-solves       [1e-3]  */
     double rtol_S;          /* delta^r_S, Schur solve                 [1e-3]  */
     double rtol_I;          /* delta^r_I, inner A-solve of Alg. 2     [1e-3]  */
+    double cheb_ratio;      /* AMG smoother interval [lambda/cheb_ratio, lambda],
+                             * lambda >= spectral radius of D^-1 M     [10]    */
     int32_t m, nmax;        /* FGMRES restart length / max iterations [200]   */
     int32_t m_A, nmax_A;    /* GMRES on A                             [200]   */
     int32_t m_S, nmax_S;    /* GMRES on S                             [200]   */
     int32_t pc_A;           /* ns_pc: P_A                             [AMG]   */
     int32_t precision;      /* ns_precision                           [FP64]  */
-    int32_t cheb_degree;    /* AMG Chebyshev smoother degree, 1..8    [1]     */
+    int32_t cheb_degree;    /* AMG Chebyshev smoother degree, 1..8    [2]     */
     int32_t reserved;
     /* Iteration schedule.  If h_sched != NULL, the i-th Krylov call (calls
      * numbered in the order they start: FGMRES, then each GMRES on A or S)

@@ -18,9 +18,9 @@ written definition, which the GPU library implements independently:
 * unsmoothed (piecewise-constant) prolongation, nodal for A (3x3 blocks, the
   three velocity components kept apart) and scalar for S_hat, with the same
   node aggregates; coarse operators are Galerkin products P^T M P;
-* smoother: Chebyshev polynomial of degree ``cheb_degree`` (default 1, i.e.
-  damped point Jacobi with weight 1/theta) in D^{-1} M (D the point diagonal)
-  on [lambda/30, lambda]; lambda must bound the spectral radius of D^{-1} M
+* smoother: Chebyshev polynomial of degree ``cheb_degree`` (default 2; degree
+  1 is damped point Jacobi with weight 1/theta) in D^{-1} M (D the point diagonal)
+  on [lambda/cheb_ratio, lambda] (cheb_ratio default 10); lambda must bound the spectral radius of D^{-1} M
   from above, else the smoother amplifies the top modes.  It is the smaller of
   the Gershgorin bound max_i sum_j |M_ij / D_ii| (a guaranteed bound) and
   1.2 x the estimate from 20 power iterations on D^{-1} M from the start
@@ -142,9 +142,10 @@ def chebyshev(M, dinv, b, x, degree, lmin, lmax):
 class AMG:
     """V-cycle for M (scipy CSR) with block size ``bs`` on the node aggregates."""
 
-    def __init__(self, M, bs: int, aggs, cheb_degree: int = 1, extra_diag=None):
+    def __init__(self, M, bs: int, aggs, cheb_degree: int = 2, extra_diag=None, cheb_ratio: float = 10.0):
         self.bs = bs
         self.deg = cheb_degree
+        self.ratio = cheb_ratio
         M = sp.csr_matrix(M, dtype=np.float64)
         if extra_diag is not None:
             M = (M + sp.diags(extra_diag)).tocsr()
@@ -169,8 +170,8 @@ class AMG:
         if level == len(self.M) - 1:
             return sla.lu_solve(self.lu, b)
         M, dinv, lmax = self.M[level], self.dinv[level], self.lmax[level]
-        x = chebyshev(M, dinv, b, None, self.deg, lmax / 30.0, lmax)
+        x = chebyshev(M, dinv, b, None, self.deg, lmax / self.ratio, lmax)
         r = b - M @ x
         P = self.P[level]
         x = x + P @ self.vcycle(P.T @ r, level + 1)
-        return chebyshev(M, dinv, b, x, self.deg, lmax / 30.0, lmax)
+        return chebyshev(M, dinv, b, x, self.deg, lmax / self.ratio, lmax)

@@ -208,7 +208,8 @@ class SolveOpts:
     nmax_A: int = 200
     nmax_S: int = 200
     pc_A: str = "amg"        # "amg" or "jacobi"
-    cheb_degree: int = 1
+    cheb_degree: int = 2
+    cheb_ratio: float = 10.0
     coarse_nodes: int = 128
     max_levels: int = 16
     atol: float = 1e-50
@@ -228,11 +229,11 @@ class NestedSolver:
         dK = np.zeros(3 * self.N)
         for ak, ck in zip(S.a, S.c):
             dK += ck * ak * ak
-        self.amgA = amg_mod.AMG(S.A_F, 3, self.aggs, opts.cheb_degree, extra_diag=dK)
+        self.amgA = amg_mod.AMG(S.A_F, 3, self.aggs, opts.cheb_degree, extra_diag=dK, cheb_ratio=opts.cheb_ratio)
         # S_hat = D - C diag(A)^{-1} B  (Sec. 3.1)
         import scipy.sparse as sp
         self.Shat = (S.D - S.C @ sp.diags(1.0 / dA) @ S.B).tocsr()
-        self.amgS = amg_mod.AMG(self.Shat, 1, self.aggs, opts.cheb_degree)
+        self.amgS = amg_mod.AMG(self.Shat, 1, self.aggs, opts.cheb_degree, cheb_ratio=opts.cheb_ratio)
 
     def pA(self, r):
         if self.o.pc_A == "jacobi":

@@ -48,6 +48,9 @@ inline T* as(double* p) {
 
 int dflt(int v, int d) { return v > 0 ? v : d; }
 double dfltd(double v, double d) { return v > 0 ? v : d; }
+// AMG smoother defaults: Chebyshev degree 2 on [lambda/10, lambda]
+constexpr int kDefaultChebDegree = 2;
+constexpr double kDefaultChebRatio = 10.0;
 
 // ---------------------------------------------------------------------------
 // workspace layout (measured with a null base, then applied to the real one)
@@ -224,6 +227,7 @@ void layout(ns_ctx* c, Arena& A) {
     c->t_xbar = A.take<double>(3 * (size_t)N);
     c->t_xt = A.take<double>(3 * (size_t)N);
     c->t_sf = A.take<double>(3 * (size_t)N);
+    c->d_bnd = A.take<double>(3 * 2 * std::max<size_t>(S.lv.size(), 1));
     c->t_r4 = A.take<double>(4 * (size_t)N);
     A.take<char>(256);
 }
@@ -358,7 +362,7 @@ void run_step(ns_ctx* c, const Ctl& K, int kind, int j, F&& body) {
         return;
     }
     const int sys = K.sy == &c->sys[0] ? 0 : 1;
-    const auto key = std::make_tuple(kind, sys, K.o.precision, K.o.pc_A, dflt(K.o.cheb_degree, 1), j);
+    const auto key = std::make_tuple(kind, sys, K.o.precision, K.o.pc_A, dflt(K.o.cheb_degree, kDefaultChebDegree), j);
     auto it = c->graphs.find(key);
     if (it == c->graphs.end()) {
         HIPCHK(hipStreamBeginCapture(K.st, hipStreamCaptureModeThreadLocal));
@@ -615,7 +619,7 @@ struct Nested {
             dense_gemv<T>((int)nv, L.inv, b, xout, st);
             return;
         }
-        const int deg = dflt(K.o.cheb_degree, 1);
+        const int deg = dflt(K.o.cheb_degree, kDefaultChebDegree);
         const BlockOp<T> M = level_op(L);
         const T* dinv = Typed<T>::dinv(L);
         const T* coef = Typed<T>::coef(L);
@@ -838,26 +842,28 @@ ns_status fgmres(Ctl& K, const double* b, double* x) {
 // Upper end of the smoother interval of a level: the smaller of the
 // Gershgorin bound of D^{-1} M (guaranteed) and kPowerSafety times the
 // estimate from kPowerIters power iterations (which approach the spectral
-// radius from below) from the fixed start vector.
+// radius from below) from the fixed start vector.  The iterates are not
+// normalised (the estimate ||y_k|| / ||y_{k-1}|| equals the normalised
+// iteration's last norm; the growth lambda^k stays far inside FP64 range).
+// Writes ||y_k||, ||y_{k-1}|| and the Gershgorin bound to out[0..2].
 constexpr int kPowerIters = 20;
 constexpr double kPowerSafety = 1.2;
-double smoother_bound(ns_ctx* c, const BlockOp<double>& M, int bs, const double* dinv, double* x, double* y,
-                      hipStream_t st) {
+void smoother_bound_dev(ns_ctx* c, const BlockOp<double>& M, int bs, const double* dinv, double* x, double* y,
+                        double* out, hipStream_t st) {
     const int64_t n = (int64_t)M.n * bs;
     power_start(n, x, st);
-    double* nrm = c->kw_out.status + 6;
-    norm2<double>(n, x, nrm, c->d_red, st);
-    scale_by<double>(n, x, nrm, true, x, st);
     for (int it = 0; it < kPowerIters; ++it) {
         spmv<double>(bs, bs, M, x, y, 1.0, nullptr, 0.0, dinv, nullptr, st);
-        norm2<double>(n, y, nrm, c->d_red, st);
-        scale_by<double>(n, y, nrm, true, x, st);
+        std::swap(x, y);
     }
-    gershgorin_bound(M, bs, dinv, c->d_red, nrm + 1, st);
+    norm2<double>(n, x, out, c->d_red, st);
+    norm2<double>(n, y, out + 1, c->d_red, st);
+    // the iterates are no longer needed: x holds the per-block partials
+    // (at most n/4 + 1 <= n*bs of them)
+    gershgorin_bound(M, bs, dinv, x, out + 2, st);
     check_launch();
-    read_status(c, nrm, 2, st);
-    return std::min(c->h_pinned[1], kPowerSafety * c->h_pinned[0]);
 }
+double smoother_bound_host(const double* v) { return std::min(v[2], kPowerSafety * (v[0] / v[1])); }
 
 void setup_system(ns_ctx* c, SystemDev& y, bool need32, hipStream_t st) {
     const Symbolic& S = c->sym;
@@ -883,6 +889,8 @@ void setup_system(ns_ctx* c, SystemDev& y, bool need32, hipStream_t st) {
             block_dinv(s.n, 1, s.rp, s.col, s.v64, 0, 0, nullptr, s.dinv64, nullptr, st);
         }
         check_launch();
+        // smoother bounds of every smoothed level (three scalars each), read back once
+        double* bnd = c->d_bnd;
         for (int h = 0; h < 2; ++h) {
             std::vector<AmgLevelDev>& H = h == 0 ? y.A : y.S;
             for (int l = 0; l < L; ++l) {
@@ -897,14 +905,29 @@ void setup_system(ns_ctx* c, SystemDev& y, bool need32, hipStream_t st) {
                 M.dextra = d.dextra64;
                 M.lanes = lanes_for(d.nnz, d.n);
                 if (l + 1 < L) {
-                    d.lmax = smoother_bound(c, M, d.bs, d.dinv64, d.x0, d.r, st);
+                    smoother_bound_dev(c, M, d.bs, d.dinv64, d.x0, d.r, bnd + 3 * (h * L + l), st);
                 } else {
                     dense_from_csr(d.n, d.bs, d.rp, d.col, d.v64, d.rstride, d.cstride, d.dextra64, d.work, st);
-                    gauss_jordan_inverse(d.n * d.bs, d.work, d.inv, st);
-                    check_launch();
                 }
             }
         }
+        {
+            // coarsest inverses of both hierarchies, concurrently
+            AmgLevelDev& a = y.A[L - 1];
+            AmgLevelDev& s = y.S[L - 1];
+            gauss_jordan_inverse2(a.n * a.bs, a.work, a.inv, s.n * s.bs, s.work, s.inv, st);
+            check_launch();
+        }
+        std::vector<double> hb(3 * 2 * (size_t)L);
+        HIPCHK(hipMemcpyAsync(hb.data(), bnd, hb.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        for (int h = 0; h < 2; ++h)
+            for (int l = 0; l + 1 < L; ++l) {
+                AmgLevelDev& d = h == 0 ? y.A[l] : y.S[l];
+                d.lmax = smoother_bound_host(&hb[3 * (h * L + l)]);
+                if (!std::isfinite(d.lmax) || !(d.lmax > 0.0))
+                    throw Fail{NS_ERR_NAN, "AMG smoother bound is not finite and positive"};
+            }
         y.ready = true;
         y.have32 = false;
         y.coef_deg = 0;
@@ -933,15 +956,16 @@ void setup_system(ns_ctx* c, SystemDev& y, bool need32, hipStream_t st) {
 
 // Chebyshev coefficients of every smoothed level for the requested degree:
 // interval [lmax/30, lmax] of D^{-1} M, theta/delta its centre/half-width.
-void upload_coef(ns_ctx* c, SystemDev& y, int deg, hipStream_t st) {
+void upload_coef(ns_ctx* c, SystemDev& y, int deg, double ratio, hipStream_t st) {
     if (deg < 1 || deg > kMaxChebDegree) throw Fail{NS_ERR_ARG, "Chebyshev degree out of range [1, 8]"};
-    if (y.coef_deg == deg) return;
+    if (!(ratio > 1.0) || !std::isfinite(ratio)) throw Fail{NS_ERR_ARG, "cheb_ratio must be finite and > 1"};
+    if (y.coef_deg == deg && y.coef_ratio == ratio) return;
     std::vector<double> host;
     std::vector<AmgLevelDev*> lv;
     for (int h = 0; h < 2; ++h) {
         std::vector<AmgLevelDev>& H = h == 0 ? y.A : y.S;
         for (int l = 0; l + 1 < (int)H.size(); ++l) {
-            const double lmax = H[l].lmax, lmin = lmax / 30.0;
+            const double lmax = H[l].lmax, lmin = lmax / ratio;
             const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin), sigma = theta / delta;
             std::vector<double> cf(kCoefLen, 0.0);
             cf[0] = 1.0 / theta;
@@ -964,6 +988,7 @@ void upload_coef(ns_ctx* c, SystemDev& y, int deg, hipStream_t st) {
     check_launch();
     HIPCHK(hipStreamSynchronize(st));  // the host buffer goes out of scope
     y.coef_deg = deg;
+    y.coef_ratio = ratio;
 }
 
 void ensure_transposed(ns_ctx* c, hipStream_t st) {
@@ -997,7 +1022,7 @@ ns_status run_solve(ns_ctx* c, int which, const ns_solve_opts* opts, const doubl
     if (which == 1) ensure_transposed(c, st);
     K.sy = &c->sys[which];
     setup_system(c, *K.sy, K.o.precision == NS_FP32_INNER, st);
-    upload_coef(c, *K.sy, dflt(K.o.cheb_degree, 1), st);
+    upload_coef(c, *K.sy, dflt(K.o.cheb_degree, kDefaultChebDegree), dfltd(K.o.cheb_ratio, kDefaultChebRatio), st);
     HIPCHK(hipStreamSynchronize(st));
     auto t1 = std::chrono::steady_clock::now();
     ns_status rs = K.o.precision == NS_FP32_INNER ? fgmres<float>(K, b, x) : fgmres<double>(K, b, x);
@@ -1402,7 +1427,7 @@ ns_status ns_apply(ns_ctx* c, int32_t op, const ns_solve_opts* opts, const doubl
         K.sy = &c->sys[0];
         const bool f32 = K.o.precision == NS_FP32_INNER;
         setup_system(c, c->sys[0], f32, st);
-        upload_coef(c, c->sys[0], dflt(K.o.cheb_degree, 1), st);
+        upload_coef(c, c->sys[0], dflt(K.o.cheb_degree, kDefaultChebDegree), dfltd(K.o.cheb_ratio, kDefaultChebRatio), st);
         const int N = c->sym.N;
         const int64_t nin[] = {4L * N, 3L * N, N, 3L * N, N, N, 3L * N, N, N, 4L * N, 3L * N};
         const int64_t nout[] = {4L * N, 3L * N, 3L * N, N, N, N, 3L * N, N, N, 4L * N, 3L * N};

@@ -123,6 +123,7 @@ struct SystemDev {
     float* shat32 = nullptr;
     std::vector<AmgLevelDev> A, S;   // hierarchies
     int coef_deg = 0;                // Chebyshev degree the device coefficients belong to
+    double coef_ratio = 0.0;         // and the interval ratio
     bool ready = false;              // per-step set-up done for the current tangent
     bool have32 = false;
     uint64_t version = 0;            // tangent version the set-up belongs to
@@ -177,6 +178,7 @@ struct ns_ctx {
     double *t_s = nullptr, *t_yhat = nullptr, *t_tp = nullptr, *t_yp = nullptr, *t_tv = nullptr,
            *t_yv = nullptr, *t_xhat = nullptr, *t_xbar = nullptr, *t_xt = nullptr, *t_r4 = nullptr;
     double* t_sf = nullptr;  // [3N] scratch of the factored S_hat application
+    double* d_bnd = nullptr; // [2 hierarchies][levels][3] smoother-bound scalars
     double* h_pinned = nullptr;  // pinned host scalars
     double* h_mapped = nullptr;  // pinned, device-mapped host scalars written by kernels
     double* d_mapped = nullptr;  // device address of h_mapped

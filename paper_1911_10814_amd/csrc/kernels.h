@@ -145,10 +145,15 @@ void block_dinv(int n, int bs, const int32_t* rp, const int32_t* col, const doub
                 const double* dextra, double* dinv, double* diag, hipStream_t st);
 void shat_numeric(int n, const int32_t* rp, const int32_t* col, const double* V, int64_t nnzb,
                   const double* dinvA, const int32_t* srp, const int32_t* scol, double* shat, hipStream_t st);
-void gauss_jordan_inverse(int n, double* work, double* inv, hipStream_t st);
+// inv_i = (left half of work_i)^{-1} by Gauss-Jordan with partial pivoting on
+// work_i [n_i][2 n_i] (right half: identity, overwritten) for two independent
+// matrices in one launch, one workgroup each
+void gauss_jordan_inverse2(int n0, double* work0, double* inv0, int n1, double* work1, double* inv1,
+                           hipStream_t st);
 void dense_from_csr(int nb, int bs, const int32_t* rp, const int32_t* col, const double* v, int64_t rs,
                     int64_t cs, const double* dextra, double* work, hipStream_t st);
-// out[0] = max_r |dinv_r| sum_c |M_rc| (Gershgorin bound of D^{-1} M); part: >= kMaxRedBlocks scratch
+// out[0] = max_r |dinv_r| sum_c |M_rc| (Gershgorin bound of D^{-1} M);
+// part: scratch of ceil(n * M.lanes / kBlock) doubles
 void gershgorin_bound(const BlockOp<double>& M, int bs, const double* dinv, double* part, double* out,
                       hipStream_t st);
 void power_start(int64_t n, double* x, hipStream_t st);

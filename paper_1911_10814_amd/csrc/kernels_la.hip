@@ -1106,8 +1106,17 @@ void dense_from_csr(int nb, int bs, const int32_t* rp, const int32_t* col, const
                        dextra, work);
 }
 
-// Gauss-Jordan with partial pivoting on work [n][2n], one workgroup of 1024.
-__global__ __launch_bounds__(1024) void k_gauss_jordan(int n, double* work, double* inv) {
+// Gauss-Jordan with partial pivoting on work [n][2n], one workgroup of 1024
+// per matrix (blockIdx.x selects one of up to two independent matrices).
+struct GjBatch {
+    int n[2];
+    double* work[2];
+    double* inv[2];
+};
+__global__ __launch_bounds__(1024) void k_gauss_jordan(GjBatch bt) {
+    const int n = bt.n[blockIdx.x];
+    double* work = bt.work[blockIdx.x];
+    double* inv = bt.inv[blockIdx.x];
     __shared__ double sval[1024];
     __shared__ int sidx[1024];
     __shared__ int piv;
@@ -1169,8 +1178,10 @@ __global__ __launch_bounds__(1024) void k_gauss_jordan(int n, double* work, doub
     }
     for (int e = threadIdx.x; e < n * n; e += 1024) inv[e] = work[(int64_t)(e / n) * n2 + n + e % n];
 }
-void gauss_jordan_inverse(int n, double* work, double* inv, hipStream_t st) {
-    hipLaunchKernelGGL(k_gauss_jordan, dim3(1), dim3(1024), 0, st, n, work, inv);
+void gauss_jordan_inverse2(int n0, double* work0, double* inv0, int n1, double* work1, double* inv1,
+                           hipStream_t st) {
+    GjBatch b{{n0, n1}, {work0, work1}, {inv0, inv1}};
+    hipLaunchKernelGGL(k_gauss_jordan, dim3(2), dim3(1024), 0, st, b);
 }
 
 __global__ void k_power_start(int64_t n, double* x) {
@@ -1184,26 +1195,42 @@ void power_start(int64_t n, double* x, hipStream_t st) {
 }
 
 // Gershgorin bound of D^{-1} M: max over point rows of |dinv_r| sum_c |M_rc|
-// (the extra diagonal added to the diagonal entry).  Per-block maxima into
-// part[blockIdx.x], then a one-block maximum into out[0].
-__global__ __launch_bounds__(kBlock) void k_gersh_part(BlockOp<double> M, int bs, const double* __restrict__ dinv,
+// (the extra diagonal added to the diagonal entry).  W lanes per block row as
+// in the SpMV; per-block maxima into part[blockIdx.x], then a one-block
+// maximum into out[0].
+template <int BS, int W>
+__global__ __launch_bounds__(kBlock) void k_gersh_part(BlockOp<double> M, const double* __restrict__ dinv,
                                                        double* __restrict__ part) {
     __shared__ double lds[kBlock / 64];
-    double mx = 0.0;
-    const int64_t nr = (int64_t)M.n * bs;
-    for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < nr; t += (int64_t)gridDim.x * kBlock) {
-        const int i = (int)(t / bs), r = (int)(t % bs);
-        double s = 0.0;
-        for (int k = M.rp[i]; k < M.rp[i + 1]; ++k) {
-            const bool diag = M.col[k] == i;
-            for (int c = 0; c < bs; ++c) {
-                double v = M.v[r * M.rs + c * M.cs + k];
-                if (diag && c == r && M.dextra) v += M.dextra[t];
-                s += fabs(v);
-            }
+    const int64_t tid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int row = (int)(tid / W);
+    const int lane = threadIdx.x % W;
+    const bool valid = row < M.n;
+    double acc[BS];
+#pragma unroll
+    for (int r = 0; r < BS; ++r) acc[r] = 0.0;
+    if (valid) {
+        const int k1 = M.rp[row + 1];
+        for (int k = M.rp[row] + lane; k < k1; k += W) {
+            const bool diag = M.col[k] == row;
+#pragma unroll
+            for (int r = 0; r < BS; ++r)
+#pragma unroll
+                for (int c = 0; c < BS; ++c) {
+                    double v = M.v[r * M.rs + c * M.cs + k];
+                    if (diag && c == r && M.dextra) v += M.dextra[(int64_t)BS * row + r];
+                    acc[r] += fabs(v);
+                }
         }
-        mx = fmax(mx, s * fabs(dinv[t]));
     }
+#pragma unroll
+    for (int off = W / 2; off > 0; off >>= 1)
+#pragma unroll
+        for (int r = 0; r < BS; ++r) acc[r] += __shfl_xor(acc[r], off, W);
+    double mx = 0.0;
+    if (valid && lane == 0)
+#pragma unroll
+        for (int r = 0; r < BS; ++r) mx = fmax(mx, acc[r] * fabs(dinv[(int64_t)BS * row + r]));
     for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
     if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = mx;
     __syncthreads();
@@ -1226,10 +1253,25 @@ __global__ void k_max_fin(const double* part, int G, double* out) {
         out[0] = m;
     }
 }
+template <int BS, int W>
+int gersh_launch(const BlockOp<double>& M, const double* dinv, double* part, hipStream_t st) {
+    const int G = (int)grid_for((int64_t)M.n * W);
+    hipLaunchKernelGGL((k_gersh_part<BS, W>), dim3(G), dim3(kBlock), 0, st, M, dinv, part);
+    return G;
+}
+template <int BS>
+int gersh_w(const BlockOp<double>& M, const double* dinv, double* part, hipStream_t st) {
+    switch (M.lanes) {
+        case 64: return gersh_launch<BS, 64>(M, dinv, part, st);
+        case 32: return gersh_launch<BS, 32>(M, dinv, part, st);
+        default: return gersh_launch<BS, 16>(M, dinv, part, st);
+    }
+}
+// part: one partial per launched block (at most n*64/kBlock + 1 entries)
 void gershgorin_bound(const BlockOp<double>& M, int bs, const double* dinv, double* part, double* out,
                       hipStream_t st) {
-    const int G = (int)std::min<int64_t>(grid_for((int64_t)M.n * bs), kMaxRedBlocks);
-    hipLaunchKernelGGL(k_gersh_part, dim3(G), dim3(kBlock), 0, st, M, bs, dinv, part);
+    if (M.n <= 0) return;
+    const int G = bs == 3 ? gersh_w<3>(M, dinv, part, st) : gersh_w<1>(M, dinv, part, st);
     hipLaunchKernelGGL(k_max_fin, dim3(1), dim3(kBlock), 0, st, part, G, out);
 }
 
