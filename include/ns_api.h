@@ -121,7 +121,9 @@ typedef struct {
     int32_t pc_A;           /* ns_pc: P_A                             [AMG]   */
     int32_t precision;      /* ns_precision                           [FP64]  */
     int32_t cheb_degree;    /* AMG Chebyshev smoother degree, 1..8    [2]     */
-    int32_t reserved;
+    int32_t cycles_S;       /* V-cycle iterations per application of P_S
+                             * (stationary iteration on S_hat from zero;
+                             * may diverge when > 1)                   [1]    */
     /* Iteration schedule.  If h_sched != NULL, the i-th Krylov call (calls
      * numbered in the order they start: FGMRES, then each GMRES on A or S)
      * runs exactly h_sched[i] iterations instead of testing its tolerance.

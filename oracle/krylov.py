@@ -210,6 +210,7 @@ class SolveOpts:
     pc_A: str = "amg"        # "amg" or "jacobi"
     cheb_degree: int = 2
     cheb_ratio: float = 10.0
+    cycles_S: int = 1        # V-cycle iterations per application of P_S
     coarse_nodes: int = 128
     max_levels: int = 16
     atol: float = 1e-50
@@ -234,6 +235,14 @@ class NestedSolver:
         import scipy.sparse as sp
         self.Shat = (S.D - S.C @ sp.diags(1.0 / dA) @ S.B).tocsr()
         self.amgS = amg_mod.AMG(self.Shat, 1, self.aggs, opts.cheb_degree, cheb_ratio=opts.cheb_ratio)
+
+    def pS(self, r):
+        """P_S: ``cycles_S`` steps of the stationary V-cycle iteration on
+        S_hat from zero, z <- z + V(r - S_hat z)."""
+        z = self.amgS.vcycle(r)
+        for _ in range(self.o.cycles_S - 1):
+            z = z + self.amgS.vcycle(r - self.Shat @ z)
+        return z
 
     def pA(self, r):
         if self.o.pc_A == "jacobi":
@@ -260,7 +269,7 @@ class NestedSolver:
         sv, sp_ = s[:n3], s[n3:]
         yv_hat = self.solve_A(sv, o.rtol_A, sched)
         tp = sp_ - S.C @ yv_hat
-        yp, _ = gmres_left(lambda q: self.schur_apply(q, sched), self.amgS.vcycle, tp, o.rtol_S,
+        yp, _ = gmres_left(lambda q: self.schur_apply(q, sched), self.pS, tp, o.rtol_S,
                            o.m_S, o.nmax_S, sched, o.atol)
         tv = sv - S.B @ yp
         yv = self.solve_A(tv, o.rtol_A, sched)

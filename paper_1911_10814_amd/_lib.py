@@ -40,7 +40,7 @@ class NsSolveOpts(C.Structure):
     _fields_ = [("rtol", C.c_double), ("atol", C.c_double), ("rtol_A", C.c_double), ("rtol_S", C.c_double),
                 ("rtol_I", C.c_double), ("cheb_ratio", C.c_double), ("m", C.c_int32), ("nmax", C.c_int32), ("m_A", C.c_int32),
                 ("nmax_A", C.c_int32), ("m_S", C.c_int32), ("nmax_S", C.c_int32), ("pc_A", C.c_int32),
-                ("precision", C.c_int32), ("cheb_degree", C.c_int32), ("reserved", C.c_int32),
+                ("precision", C.c_int32), ("cheb_degree", C.c_int32), ("cycles_S", C.c_int32),
                 ("h_sched", PI), ("sched_len", C.c_int32), ("sched_cap", C.c_int32), ("h_sched_out", PI)]
 
 

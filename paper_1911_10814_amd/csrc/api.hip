@@ -51,6 +51,10 @@ double dfltd(double v, double d) { return v > 0 ? v : d; }
 // AMG smoother defaults: Chebyshev degree 2 on [lambda/10, lambda]
 constexpr int kDefaultChebDegree = 2;
 constexpr double kDefaultChebRatio = 10.0;
+// V-cycle iterations per application of P_S.  More than one helps on small
+// meshes but the stationary V-cycle iteration on S_hat can diverge (observed
+// on the 1e6-node Y-bifurcation), so the default is a single V-cycle.
+constexpr int kDefaultCyclesS = 1;
 
 // ---------------------------------------------------------------------------
 // workspace layout (measured with a null base, then applied to the real one)
@@ -227,6 +231,7 @@ void layout(ns_ctx* c, Arena& A) {
     c->t_xbar = A.take<double>(3 * (size_t)N);
     c->t_xt = A.take<double>(3 * (size_t)N);
     c->t_sf = A.take<double>(3 * (size_t)N);
+    c->t_ps = A.take<double>(2 * (size_t)N);
     c->d_bnd = A.take<double>(3 * 2 * std::max<size_t>(S.lv.size(), 1));
     c->t_r4 = A.take<double>(4 * (size_t)N);
     A.take<char>(256);
@@ -690,7 +695,20 @@ struct Nested {
         else
             vcycle(sy.A, 0, r, z);
     }
-    void applyPS(const T* r, T* z) { vcycle(sy.S, 0, r, z); }
+    // P_S: cycles_S steps of the stationary V-cycle iteration on S_hat from
+    // zero, z <- z + V(r - S_hat z) (S_hat applied in factored form)
+    void applyPS(const T* r, T* z, bool first_done = false) {
+        vcycle(sy.S, 0, r, z, first_done);
+        const int k = dflt(K.o.cycles_S, kDefaultCyclesS);
+        T* t = as<T>(c->t_ps);
+        T* e = t + N;
+        for (int i = 1; i < k; ++i) {
+            shat_factored<T>(N, c->d_rp, c->d_col, V(), nnzb, Typed<T>::dinvA(sy), z, nullptr, nullptr,
+                             as<T>(c->t_sf), t, T(-1), r, T(1), nullptr, nullptr, nullptr, 0, nullptr, K.st);
+            vcycle(sy.S, 0, t, e);
+            axpby<T>(N, T(1), e, T(1), z, z, K.st);
+        }
+    }
 
     int solveA(const T* b, T* x, double rtol) {
         std::function<void(const T*, T*)> sM, sP;
@@ -723,7 +741,7 @@ struct Nested {
                 const FirstStep<T> f = first_step(sy.S);
                 schur(in, out, &f);
             };
-            sP = [this](const T* in, T* out) { vcycle(sy.S, 0, in, out, true); };
+            sP = [this](const T* in, T* out) { applyPS(in, out, true); };
         }
         return gmres_left<T>(
             K, c->kw_S, N, [this](const T* in, T* out) { schur(in, out); },

@@ -178,6 +178,7 @@ struct ns_ctx {
     double *t_s = nullptr, *t_yhat = nullptr, *t_tp = nullptr, *t_yp = nullptr, *t_tv = nullptr,
            *t_yv = nullptr, *t_xhat = nullptr, *t_xbar = nullptr, *t_xt = nullptr, *t_r4 = nullptr;
     double* t_sf = nullptr;  // [3N] scratch of the factored S_hat application
+    double* t_ps = nullptr;  // [2N] residual and correction of the P_S iteration
     double* d_bnd = nullptr; // [2 hierarchies][levels][3] smoother-bound scalars
     double* h_pinned = nullptr;  // pinned host scalars
     double* h_mapped = nullptr;  // pinned, device-mapped host scalars written by kernels
