@@ -55,6 +55,7 @@ constexpr double kDefaultChebRatio = 10.0;
 // meshes but the stationary V-cycle iteration on S_hat can diverge (observed
 // on the 1e6-node Y-bifurcation), so the default is a single V-cycle.
 constexpr int kDefaultCyclesS = 1;
+constexpr double kXcdMaxXBytes = 8.0e6;
 
 // ---------------------------------------------------------------------------
 // workspace layout (measured with a null base, then applied to the real one)
@@ -556,6 +557,14 @@ struct Nested {
     Nested(Ctl& k) : K(k), c(k.c), sy(*k.sy), N(k.c->sym.N), nnzb(k.c->sym.g.nnz()) {}
 
     const T* V() const { return Typed<T>::V(sy); }
+    // XCD-contiguous row ranges pay while a row range's share of the gathered
+    // vector stays L2-resident: on when the gathered vector (n*bc values) is
+    // at most kXcdMaxXBytes (measured: +15 % on the 2e5-node pipe, -5 % on the
+    // 2e6-node pipe); NS_XCD_ROWS=0/1 forces it off/on.
+    int xcd_rows(int64_t n, int bc) const {
+        if (c->xcd_mode >= 0) return c->xcd_mode;
+        return (double)n * bc * sizeof(T) <= kXcdMaxXBytes ? 1 : 0;
+    }
     BlockOp<T> op(int r0, int c0) const {
         BlockOp<T> M;
         M.n = N;
@@ -565,6 +574,7 @@ struct Nested {
         M.rs = 4 * nnzb;
         M.cs = nnzb;
         M.lanes = lanes_for(nnzb, N);
+        M.xcd = xcd_rows(N, c0 == 3 ? 1 : 3);
         return M;
     }
     BlockOp<T> level_op(const AmgLevelDev& d) const {
@@ -577,6 +587,7 @@ struct Nested {
         M.cs = d.cstride;
         M.dextra = Typed<T>::dextra(d);
         M.lanes = lanes_for(d.nnz, d.n);
+        M.xcd = xcd_rows(d.n, d.bs);
         return M;
     }
     RankOne<T> rank_one() const {
@@ -645,7 +656,7 @@ struct Nested {
                       [&] { cheb_step<T>(bs, M, xi, xo, d, b, dinv, coef, step, agg, ec, st); });
             else if (sfact)
                 shat_factored<T>(N, c->d_rp, c->d_col, V(), nnzb, Typed<T>::dinvA(sy), xi, agg, ec, tsf, xo, T(1),
-                                 nullptr, T(0), b, dinv, coef, step, d, st);
+                                 nullptr, T(0), b, dinv, coef, step, d, xcd_rows(N, 1), st);
             else
                 cheb_step<T>(bs, M, xi, xo, d, b, dinv, coef, step, agg, ec, st);
         };
@@ -670,7 +681,7 @@ struct Nested {
                       [&] { spmv<T>(bs, bs, M, a, as<T>(L.r), T(-1), b, T(1), nullptr, nullptr, st); });
             } else if (sfact) {
                 shat_factored<T>(N, c->d_rp, c->d_col, V(), nnzb, Typed<T>::dinvA(sy), a, nullptr, nullptr, tsf,
-                                 as<T>(L.r), T(-1), b, T(1), nullptr, nullptr, nullptr, 0, nullptr, st);
+                                 as<T>(L.r), T(-1), b, T(1), nullptr, nullptr, nullptr, 0, nullptr, xcd_rows(N, 1), st);
             } else {
                 spmv<T>(bs, bs, M, a, as<T>(L.r), T(-1), b, T(1), nullptr, nullptr, st);
             }
@@ -704,7 +715,8 @@ struct Nested {
         T* e = t + N;
         for (int i = 1; i < k; ++i) {
             shat_factored<T>(N, c->d_rp, c->d_col, V(), nnzb, Typed<T>::dinvA(sy), z, nullptr, nullptr,
-                             as<T>(c->t_sf), t, T(-1), r, T(1), nullptr, nullptr, nullptr, 0, nullptr, K.st);
+                             as<T>(c->t_sf), t, T(-1), r, T(1), nullptr, nullptr, nullptr, 0, nullptr, xcd_rows(N, 1),
+                             K.st);
             vcycle(sy.S, 0, t, e);
             axpby<T>(N, T(1), e, T(1), z, z, K.st);
         }
@@ -1177,6 +1189,8 @@ ns_status ns_ctx_bind(ns_ctx* c, void* ws, size_t bytes, hipStream_t st) {
             if (!c->step_ev[e]) HIPCHK(hipEventCreateWithFlags(&c->step_ev[e], hipEventDisableTiming));
         const char* ng = getenv("NS_NO_GRAPHS");
         c->use_graphs = !(ng && ng[0] == '1');
+        const char* xr = getenv("NS_XCD_ROWS");
+        c->xcd_mode = (xr && (xr[0] == '0' || xr[0] == '1')) ? xr[0] - '0' : -1;
         HIPCHK(hipStreamSynchronize(st));
         c->bound = true;
         return NS_OK;

@@ -197,6 +197,7 @@ struct ns_ctx {
     hipStream_t own = nullptr;
     hipEvent_t step_ev[2] = {nullptr, nullptr};  // completion of queued Arnoldi steps
     bool use_graphs = true;
+    int xcd_mode = -1;           // XCD-contiguous row ranges: -1 by size, 0 off, 1 on
     // captured Arnoldi steps: (kind, system, precision, pc_A, degree, j) -> executable graph
     std::map<std::tuple<int, int, int, int, int, int>, hipGraphExec_t> graphs;
     std::vector<double> ck_host;

@@ -39,6 +39,7 @@ struct BlockOp {
     int64_t rs = 0, cs = 0;
     const T* dextra = nullptr;  // optional extra diagonal [BR*n]
     int lanes = 16;             // lanes per block row (16, 32 or 64), from the mean row length
+    int xcd = 0;                // 1: each XCD takes one contiguous range of rows (xcd_block)
 };
 
 // lanes per row for a pattern with nnz blocks over n rows: one pass over a
@@ -123,7 +124,7 @@ void restrict_first(int nc, int bs, const int32_t* aptr, const int32_t* anodes, 
 template <typename T>
 void shat_factored(int n, const int32_t* rp, const int32_t* col, const T* V, int64_t nnzb, const T* dinvA, const T* x,
                    const int32_t* agg, const T* ec, T* t, T* y, T alpha, const T* z, T beta, const T* b,
-                   const T* dinv, const T* coef, int step, T* d, hipStream_t st);
+                   const T* dinv, const T* coef, int step, T* d, int xcd, hipStream_t st);
 // bc = P^T (b - M x) in one launch (residual rows summed per aggregate), plus
 // the coarse first Chebyshev step when xc != nullptr (as restrict_first)
 template <typename T>

@@ -15,6 +15,17 @@ namespace {
 
 inline unsigned grid_for(int64_t threads) { return (unsigned)((threads + kBlock - 1) / kBlock); }
 
+// The dispatcher hands workgroup b to XCD (b mod 8).  xcd_block() maps it to a
+// logical block so that each XCD processes one contiguous range of rows; its
+// own L2 then holds the x entries those rows gather instead of every XCD
+// fetching all of x.  A bijection on [0, gridDim.x).
+constexpr int kXcds = 8;
+__device__ inline int64_t xcd_block() {
+    const int64_t b = blockIdx.x, nb = gridDim.x;
+    const int64_t x = b % kXcds, q = nb / kXcds, r = nb % kXcds;
+    return x * q + (x < r ? x : r) + b / kXcds;
+}
+
 inline unsigned red_grid(int64_t n) {
     int64_t g = (n + kBlock * 4 - 1) / (kBlock * 4);
     if (g < 1) g = 1;
@@ -62,7 +73,7 @@ template <typename T, int BR, int BC, int W>
 __global__ __launch_bounds__(kBlock) void k_spmv(BlockOp<T> M, const T* __restrict__ x, T* __restrict__ y, T alpha,
                                                  const T* __restrict__ z, T beta, const T* __restrict__ rscale,
                                                  RankOne<T> ro, FirstStep<T> fs) {
-    const int64_t tid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t tid = (M.xcd ? xcd_block() : (int64_t)blockIdx.x) * kBlock + threadIdx.x;
     const int row = (int)(tid / W);
     const int lane = threadIdx.x % W;
     const bool valid = row < M.n;
@@ -673,7 +684,7 @@ __global__ __launch_bounds__(kBlock) void k_cheb_step(BlockOp<T> M, const T* __r
                                                       const T* __restrict__ dinv, const T* __restrict__ coef,
                                                       int step, const int32_t* __restrict__ agg,
                                                       const T* __restrict__ ec) {
-    const int64_t tid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t tid = (M.xcd ? xcd_block() : (int64_t)blockIdx.x) * kBlock + threadIdx.x;
     const int row = (int)(tid / W);
     const int lane = threadIdx.x % W;
     const bool valid = row < M.n;
@@ -761,8 +772,8 @@ __global__ __launch_bounds__(kBlock) void k_sfact_bt(int n, const int32_t* __res
                                                      const int32_t* __restrict__ col, const T* __restrict__ V,
                                                      int64_t nnzb, const T* __restrict__ dinvA,
                                                      const T* __restrict__ x, const int32_t* __restrict__ agg,
-                                                     const T* __restrict__ ec, T* __restrict__ t) {
-    const int64_t tid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+                                                     const T* __restrict__ ec, T* __restrict__ t, int xcd) {
+    const int64_t tid = (xcd ? xcd_block() : (int64_t)blockIdx.x) * kBlock + threadIdx.x;
     const int row = (int)(tid / W);
     const int lane = threadIdx.x % W;
     const bool valid = row < n;
@@ -794,8 +805,9 @@ __global__ __launch_bounds__(kBlock) void k_sfact_dc(int n, const int32_t* __res
                                                      const int32_t* __restrict__ agg, const T* __restrict__ ec,
                                                      T* __restrict__ y, T alpha, const T* __restrict__ z, T beta,
                                                      const T* __restrict__ b, const T* __restrict__ dinv,
-                                                     const T* __restrict__ coef, int step, T* __restrict__ d) {
-    const int64_t tid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+                                                     const T* __restrict__ coef, int step, T* __restrict__ d,
+                                                     int xcd) {
+    const int64_t tid = (xcd ? xcd_block() : (int64_t)blockIdx.x) * kBlock + threadIdx.x;
     const int row = (int)(tid / W);
     const int lane = threadIdx.x % W;
     const bool valid = row < n;
@@ -833,12 +845,13 @@ __global__ __launch_bounds__(kBlock) void k_sfact_dc(int n, const int32_t* __res
 template <typename T>
 void shat_factored(int n, const int32_t* rp, const int32_t* col, const T* V, int64_t nnzb, const T* dinvA, const T* x,
                    const int32_t* agg, const T* ec, T* t, T* y, T alpha, const T* z, T beta, const T* b,
-                   const T* dinv, const T* coef, int step, T* d, hipStream_t st) {
+                   const T* dinv, const T* coef, int step, T* d, int xcd, hipStream_t st) {
     if (n <= 0) return;
     const dim3 grid(grid_for((int64_t)n * 16));
-    hipLaunchKernelGGL((k_sfact_bt<T, 16>), grid, dim3(kBlock), 0, st, n, rp, col, V, nnzb, dinvA, x, agg, ec, t);
+    hipLaunchKernelGGL((k_sfact_bt<T, 16>), grid, dim3(kBlock), 0, st, n, rp, col, V, nnzb, dinvA, x, agg, ec, t,
+                       xcd);
     hipLaunchKernelGGL((k_sfact_dc<T, 16>), grid, dim3(kBlock), 0, st, n, rp, col, V, nnzb, t, x, agg, ec, y, alpha,
-                       z, beta, b, dinv, coef, step, d);
+                       z, beta, b, dinv, coef, step, d, xcd);
 }
 
 // Restriction bc = P^T r of a precomputed residual; when xc != nullptr also
@@ -1352,7 +1365,7 @@ void newton_update(int64_t n, double gdt, const double* dx, double* y, double* y
     template void restrict_agg<T>(int, int, const int32_t*, const int32_t*, const T*, T*, hipStream_t);              \
     template void shat_factored<T>(int, const int32_t*, const int32_t*, const T*, int64_t, const T*, const T*,       \
                                    const int32_t*, const T*, T*, T*, T, const T*, T, const T*, const T*, const T*,   \
-                                   int, T*, hipStream_t);                                                            \
+                                   int, T*, int, hipStream_t);                                                       \
     template void resid_restrict<T>(int, const BlockOp<T>&, const T*, const T*, int, const int32_t*, const int32_t*, \
                                     T*, T*, T*, const T*, const T*, hipStream_t);                                    \
     template void prolong_add<T>(int, int, const int32_t*, const T*, T*, hipStream_t);                               \

@@ -48,12 +48,30 @@ def main():
     for _ in range(args.reps):
         dst.copy_(src)
     torch.cuda.synchronize()
+    # measured streaming ceilings of the part (device copy and a read-only sum),
+    # beside the nominal 8 TB/s
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 2 * n * 4 * args.reps / (e0.elapsed_time(e1) * 1e6)
+    t = src.sum()  # first call initialises the reduction
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(args.reps):
+        t = src.sum()
+    e1.record()
+    torch.cuda.synchronize()
+    read_gbs = n * 4 * args.reps / (e0.elapsed_time(e1) * 1e6)
     s = 4 if args.precision == "fp32_inner" else 8
     N, nnzb = case.n_nodes, ctx.nnzb
     print(json.dumps({
         "config": args.config, "N": N, "nnzb": nnzb, "precision": args.precision, "reps": args.reps,
         "spmv_A_bytes": nnzb * (9 * s + 4) + 4 * (N + 1) + 6 * s * N,
         "copy_bytes_read": n * 4, "copy_bytes_written": n * 4,
+        "measured_copy_GBps": copy_gbs, "measured_read_GBps": read_gbs,
     }))
 
 
