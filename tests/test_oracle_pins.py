@@ -547,3 +547,99 @@ def test_transpose_identity_and_adjoint_gradient():
         Rm[k] -= h
         fd = (L(Rp) - L(Rm)) / (2 * h)
         assert gr[k] == pytest.approx(fd, rel=1e-7)
+
+
+# --------------------------------------------------------------------------- time step (predictor multi-corrector)
+
+from oracle import newton as nt  # noqa: E402
+
+
+def test_windkessel_rk4_matches_closed_form():
+    """dPi/dt = -Pi/(Rd C) + Q(t)/C with Q linear over the step has the closed
+    form Pi(T) = Pi_0 e^{-T/tau} + (1/C) int_0^T e^{-(T-s)/tau} (a + b s) ds."""
+    Rp, C, Rd, Pd = 120.0, 1.5e-3, 900.0, 7.0
+    Pi0, Qa, Qb, T = 40.0, 2.0, 3.5, 0.01
+    tau = Rd * C
+    e = np.exp(-T / tau)
+    a, b = Qa, (Qb - Qa) / T
+    integral = a * tau * (1 - e) + b * (tau * T - tau ** 2 * (1 - e))
+    Pi_exact = Pi0 * e + integral / C
+    P, Pi = nt.windkessel(Rp, C, Rd, Pd, Pi0, Qa, Qb, 100, T)
+    assert Pi == pytest.approx(Pi_exact, rel=1e-12)
+    assert P == pytest.approx(Rp * Qb + Pi_exact + Pd, rel=1e-12)
+    # fourth order: over a step of ~1 time constant the error falls ~16x
+    # when the sub-step is halved
+    T = 1.0
+    e = np.exp(-T / tau)
+    b = (Qb - Qa) / T
+    Pi_exact = Pi0 * e + (a * tau * (1 - e) + b * (tau * T - tau ** 2 * (1 - e))) / C
+    e1 = abs(nt.windkessel(Rp, C, Rd, Pd, Pi0, Qa, Qb, 5, T)[1] - Pi_exact)
+    e2 = abs(nt.windkessel(Rp, C, Rd, Pd, Pi0, Qa, Qb, 10, T)[1] - Pi_exact)
+    assert 13.0 < e1 / e2 < 19.0
+
+
+def test_windkessel_limits():
+    """Constant flow for many time constants: P -> (Rp + Rd) Q + Pd, the
+    resistance model; zero compliance is that model at once."""
+    Rp, C, Rd, Pd, Q = 100.0, 1e-3, 1000.0, 5.0, 2.0
+    Pi = 0.0
+    for _ in range(1000):  # 50 time constants R_d C
+        P, Pi = nt.windkessel(Rp, C, Rd, Pd, Pi, Q, Q, 20, 0.05)
+    assert P == pytest.approx((Rp + Rd) * Q + Pd, rel=1e-12)
+    assert nt.windkessel(Rp, 0.0, Rd, Pd, 123.0, 9.0, Q, 20, 0.05) == ((Rp + Rd) * Q + Pd, 0.0)
+
+
+def _step_inputs(name, seed=3):
+    c = get_case(name)
+    N = c.n_nodes
+    y_n = np.concatenate([c.v.ravel(), c.p])
+    rng = np.random.default_rng(seed)
+    ydot_n = rng.standard_normal(4 * N) * 0.5
+    dm = np.concatenate([c.mask[:, :3].ravel(), c.mask[:, 3]]).astype(bool)
+    ydot_n[dm] = 0.0
+    a_raw, _, _ = dz.outlet_vectors(c)
+    Q_n = np.array([np.sum(a_raw[k] * c.v) for k in range(c.n_outlets)])
+    model = nt.OutletModel(Rp=c.R.copy(), C=np.zeros(c.n_outlets), Rd=np.zeros(c.n_outlets),
+                           Pd=np.zeros(c.n_outlets), Pi=np.zeros(c.n_outlets), P=c.R * Q_n, Q=Q_n)
+    return c, y_n, ydot_n, model
+
+
+def test_time_step_update_and_converged_residual():
+    """The predictor and every update keep y = y_n + dt ydot_n + gamma dt
+    (ydot - ydot_n); the accepted state's residual, evaluated at the
+    generalized-alpha intermediate states built here from their definitions,
+    meets the tolerance; a resistance outlet ends with P = R Q."""
+    c, y_n, ydot_n, model = _step_inputs("channel2")
+    ph = dz.physics_of(c)
+    am, af, gam = ph.alphas
+    y, ydot, info, out = nt.time_step(c, y_n, ydot_n, model, nt.NewtonOpts(tol_R=1e-9, tol_A=1e-14),
+                                      kr.SolveOpts(rtol=1e-12, rtol_A=1e-10, rtol_S=1e-10, rtol_I=1e-10))
+    assert info["converged"] and info["iterations"] >= 2
+    assert np.allclose(y, y_n + ph.dt * ydot_n + gam * ph.dt * (ydot - ydot_n), rtol=0, atol=1e-13 * np.abs(y).max())
+    N = c.n_nodes
+    yaf = y_n + af * (y - y_n)
+    ydam = ydot_n + am * (ydot - ydot_n)
+    a_raw, _, _ = dz.outlet_vectors(c)
+    Q = np.array([np.sum(a_raw[k] * y[:3 * N].reshape(N, 3)) for k in range(c.n_outlets)])
+    Paf = (1 - af) * model.P + af * c.R * Q
+    S = dz.assemble(c, P_af=Paf, R=c.R, v=yaf[:3 * N].reshape(N, 3), p=yaf[3 * N:], vdot=ydam[:3 * N].reshape(N, 3))
+    assert np.linalg.norm(S.rhs) <= 1e-9 * info["res0"]
+    assert np.allclose(out.Q, Q, rtol=1e-14) and np.allclose(out.P, c.R * Q, rtol=1e-14)
+    # the residual history decreases at every corrector
+    h = info["res_hist"]
+    assert all(b < a for a, b in zip(h, h[1:]))
+
+
+def test_time_step_nested_matches_dense_newton():
+    """The same corrector loop with every linear system solved densely gives
+    the same iterates as with the nested solver at tight tolerances."""
+    c, y_n, ydot_n, model = _step_inputs("channel2")
+    tight = kr.SolveOpts(rtol=1e-13, rtol_A=1e-11, rtol_S=1e-11, rtol_I=1e-11)
+    nopt = nt.NewtonOpts(tol_R=1e-10, tol_A=1e-15, l_max=6)
+    y1, yd1, i1, _ = nt.time_step(c, y_n, ydot_n, model, nopt, tight)
+    y2, yd2, i2, _ = nt.time_step(c, y_n, ydot_n, model, nopt, tight,
+                                  linear_solve=lambda S: np.linalg.solve(S.dense(), S.rhs))
+    assert i1["iterations"] == i2["iterations"]
+    assert np.allclose(i1["res_hist"], i2["res_hist"], rtol=1e-6, atol=1e-12 * i1["res0"])
+    assert np.linalg.norm(y1 - y2) <= 1e-10 * np.linalg.norm(y2)
+    assert np.linalg.norm(yd1 - yd2) <= 1e-8 * np.linalg.norm(yd2)
