@@ -213,6 +213,67 @@ ns_status ns_nested_solve(ns_ctx* ctx, const ns_solve_opts* opts, const double* 
 ns_status ns_adjoint_solve(ns_ctx* ctx, const ns_solve_opts* opts, const double* d_g,
                            double* d_lambda, ns_stats* h_stats, hipStream_t stream);
 
+/* Reduced model of every outlet (Sec. 2.3): the three-element Windkessel
+ *   dPi/dt = -Pi / (R_d C) + Q / C,   P = R_p Q + Pi + P_d,
+ * integrated over (t_n, t_{n+1}) with n_ts steps of the fourth-order
+ * Runge-Kutta scheme of Algorithm 1 (flow rate interpolated linearly between
+ * Q_n and Q_{n+1}).  C = 0 selects the resistance model P = (R_p + R_d) Q + P_d.
+ * Host arrays of n_outlets entries; h_Pi, h_P, h_Q are read as the values at
+ * t_n and overwritten with those at t_{n+1} by ns_time_step. */
+typedef struct {
+    const double* h_Rp;     /* proximal resistance                        */
+    const double* h_C;      /* compliance (0: resistance outlet)          */
+    const double* h_Rd;     /* distal resistance                          */
+    const double* h_Pd;     /* distal pressure at t_{n+1}                 */
+    double* h_Pi;           /* Pi^k: in t_n, out t_{n+1}                  */
+    double* h_P;            /* P^k:  in t_n, out t_{n+1}                  */
+    double* h_Q;            /* Q^k:  in t_n, out t_{n+1}                  */
+    int32_t n_ts;           /* Runge-Kutta steps per time step        [100] */
+    int32_t reserved;
+} ns_outlet_model;
+
+/* Options of the predictor multi-corrector stage (Sec. 2.5).  0 = default. */
+typedef struct {
+    double tol_R;           /* relative residual tolerance            [1e-6] */
+    double tol_A;           /* absolute residual tolerance            [1e-6] */
+    double eps_abs;         /* difference-quotient step for m^k       [1e-8] */
+    double eps_rel;         /*   eps = max(eps_abs, eps_rel |Q^k|)    [1e-5] */
+    int32_t l_max;          /* maximum corrector iterations           [20]   */
+    int32_t reserved;
+} ns_newton_opts;
+
+/* Per-time-step statistics. */
+typedef struct {
+    int32_t iterations;     /* corrector iterations that solved a linear system */
+    int32_t converged;      /* 1 if a stopping criterion was met               */
+    double res0;            /* ||R_(1)||, the first residual                   */
+    double res;             /* ||R|| at the accepted iterate                   */
+    double res_hist[32];    /* ||R_(l)|| for l = 1 .. min(iterations + 1, 32)  */
+    int32_t lin_outer, lin_a, lin_s, lin_inner;  /* summed Krylov iterations  */
+    double assemble_ms, solve_ms, total_ms;
+} ns_step_stats;
+
+/* ns_time_step: one time step t_n -> t_{n+1} by the predictor
+ * multi-corrector algorithm of Sec. 2.5.  Predictor y = y_n,
+ * ydot = (gamma - 1)/gamma ydot_n; then for l = 1 .. l_max: outlet flows
+ * Q^k of the current iterate, P^k_{n+1} from the reduced model and m^k from
+ * its central difference quotient; the state at n+af / n+am and
+ * P^k_{n+af} = (1 - af) P^k_n + af P^k_{n+1}; assembly; stop when
+ * ||R_(l)|| <= tol_R ||R_(1)|| or ||R_(l)|| <= tol_A (the l2 norm of the
+ * assembled residual, Dirichlet entries excluded); else solve the tangent
+ * system with ns_nested_solve options `solve` and apply the update of step 10.
+ *   phys       rho, mu, dt, rho_inf, beta_bf, c_t, c_i (h_m, h_P_af unused)
+ *   d_y_n, d_ydot_n   [4 n_nodes] field-split state at t_n (Dirichlet values
+ *                     imposed in d_y_n)
+ *   d_y, d_ydot       [4 n_nodes] out: state at t_{n+1} (may not alias inputs)
+ * The assembled tangent of the last corrector stays in the workspace.
+ * Errors: as ns_assemble_tangent and ns_nested_solve; NS_NOT_CONVERGED when
+ * l_max iterations did not meet a tolerance (outputs hold the last iterate). */
+ns_status ns_time_step(ns_ctx* ctx, const ns_phys* phys, ns_outlet_model* model,
+                       const ns_newton_opts* newton, const ns_solve_opts* solve,
+                       const double* d_y_n, const double* d_ydot_n, double* d_y, double* d_ydot,
+                       ns_step_stats* h_stats, hipStream_t stream);
+
 /* ns_newton_update: the update of step 10 of the multi-corrector (Sec. 2.5):
  * y += gamma dt dy_dot, y_dot += dy_dot, on d_y, d_ydot [4 n_nodes]
  * (field-split) with d_dx [4 n_nodes]; FP64.  Asynchronous. */

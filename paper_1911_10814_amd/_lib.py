@@ -55,6 +55,28 @@ class NsStats(C.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+class NsOutletModel(C.Structure):
+    _fields_ = [("h_Rp", PD), ("h_C", PD), ("h_Rd", PD), ("h_Pd", PD), ("h_Pi", PD), ("h_P", PD), ("h_Q", PD),
+                ("n_ts", C.c_int32), ("reserved", C.c_int32)]
+
+
+class NsNewtonOpts(C.Structure):
+    _fields_ = [("tol_R", C.c_double), ("tol_A", C.c_double), ("eps_abs", C.c_double), ("eps_rel", C.c_double),
+                ("l_max", C.c_int32), ("reserved", C.c_int32)]
+
+
+class NsStepStats(C.Structure):
+    _fields_ = [("iterations", C.c_int32), ("converged", C.c_int32), ("res0", C.c_double), ("res", C.c_double),
+                ("res_hist", C.c_double * 32), ("lin_outer", C.c_int32), ("lin_a", C.c_int32),
+                ("lin_s", C.c_int32), ("lin_inner", C.c_int32), ("assemble_ms", C.c_double),
+                ("solve_ms", C.c_double), ("total_ms", C.c_double)]
+
+    def as_dict(self):
+        d = {name: getattr(self, name) for name, _ in self._fields_ if name != "res_hist"}
+        d["res_hist"] = list(self.res_hist[:min(self.iterations + 1, 32)])
+        return d
+
+
 # name -> (restype, argtypes)
 SIGNATURES = {
     "ns_ctx_create": (C.c_int, [C.POINTER(NsMesh), C.POINTER(NsCtxOpts), C.POINTER(C.c_void_p),
@@ -71,6 +93,9 @@ SIGNATURES = {
     "ns_adjoint_solve": (C.c_int, [C.c_void_p, C.POINTER(NsSolveOpts), C.c_void_p, C.c_void_p,
                                    C.POINTER(NsStats), C.c_void_p]),
     "ns_newton_update": (C.c_int, [C.c_void_p, C.c_double, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "ns_time_step": (C.c_int, [C.c_void_p, C.POINTER(NsPhys), C.POINTER(NsOutletModel), C.POINTER(NsNewtonOpts),
+                               C.POINTER(NsSolveOpts), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                               C.POINTER(NsStepStats), C.c_void_p]),
     "ns_query": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
     "ns_kernel_timing": (C.c_int, [C.c_void_p, C.c_int32]),
     "ns_kernel_timing_read": (C.c_int, [C.c_void_p, C.c_int32, PD]),

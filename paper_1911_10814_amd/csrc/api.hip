@@ -233,6 +233,11 @@ void layout(ns_ctx* c, Arena& A) {
     c->t_xt = A.take<double>(3 * (size_t)N);
     c->t_sf = A.take<double>(3 * (size_t)N);
     c->t_ps = A.take<double>(2 * (size_t)N);
+    c->nt_yaf = A.take<double>(4 * (size_t)N);
+    c->nt_ydam = A.take<double>(4 * (size_t)N);
+    c->nt_rhs = A.take<double>(4 * (size_t)N);
+    c->nt_dx = A.take<double>(4 * (size_t)N);
+    c->nt_scal = A.take<double>(8);
     c->d_bnd = A.take<double>(3 * 2 * std::max<size_t>(S.lv.size(), 1));
     c->t_r4 = A.take<double>(4 * (size_t)N);
     A.take<char>(256);
@@ -1082,6 +1087,33 @@ ns_status guard(ns_ctx* c, F&& f) {
     }
 }
 
+// Three-element Windkessel over one time step (Algorithm 1): n_ts steps of the
+// Runge-Kutta scheme with K2, K3 at the thirds of each sub-interval and weights
+// 1/8, 3/8, 3/8, 1/8, the flow rate interpolated linearly between Q_n and
+// Q_np1.  Returns P_{n+1} = R_p Q_np1 + Pi_{n+1} + P_d and Pi_{n+1} in *Pi_end.
+// C == 0: resistance model (R_p + R_d) Q + P_d, Pi_end = 0.
+double windkessel(double Rp, double C, double Rd, double Pd, double Pi_n, double Q_n, double Q_np1, int nts,
+                  double dt, double* Pi_end) {
+    if (C == 0.0) {
+        if (Pi_end) *Pi_end = 0.0;
+        return (Rp + Rd) * Q_np1 + Pd;
+    }
+    const double h = dt / nts;
+    auto F = [&](double Pi, double Q) { return -Pi / (Rd * C) + Q / C; };
+    auto Qm = [&](int m) { return (1.0 - (double)m / nts) * Q_n + ((double)m / nts) * Q_np1; };
+    double Pi = Pi_n;
+    for (int m = 0; m < nts; ++m) {
+        const double q0 = Qm(m), q1 = Qm(m + 1);
+        const double k1 = F(Pi, q0);
+        const double k2 = F(Pi + k1 * h / 3.0, 2.0 * q0 / 3.0 + q1 / 3.0);
+        const double k3 = F(Pi - k1 * h / 3.0 + k2 * h, q0 / 3.0 + 2.0 * q1 / 3.0);
+        const double k4 = F(Pi + k1 * h - k2 * h + k3 * h, q1);
+        Pi = Pi + k1 * h / 8.0 + 3.0 * k2 * h / 8.0 + 3.0 * k3 * h / 8.0 + k4 * h / 8.0;
+    }
+    if (Pi_end) *Pi_end = Pi;
+    return Rp * Q_np1 + Pi + Pd;
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -1340,6 +1372,120 @@ ns_status ns_newton_update(ns_ctx* c, double gamma_dt, const double* d_dx, doubl
         newton_update(4 * (int64_t)c->sym.N, gamma_dt, d_dx, d_y, d_ydot, st);
         check_launch();
         return NS_OK;
+    });
+}
+
+ns_status ns_time_step(ns_ctx* c, const ns_phys* phys, ns_outlet_model* om, const ns_newton_opts* nopt,
+                       const ns_solve_opts* sopt, const double* d_y_n, const double* d_ydot_n, double* d_y,
+                       double* d_ydot, ns_step_stats* hs, hipStream_t st) {
+    if (!c) return NS_ERR_ARG;
+    return guard(c, [&]() -> ns_status {
+        if (!c->bound) throw Fail{NS_ERR_STATE, "context not bound"};
+        if (!phys || !d_y_n || !d_ydot_n || !d_y || !d_ydot) throw Fail{NS_ERR_ARG, "null argument"};
+        if (d_y == d_y_n || d_ydot == d_ydot_n || d_y == d_ydot) throw Fail{NS_ERR_ARG, "outputs alias inputs"};
+        const Symbolic& S = c->sym;
+        const int N = S.N, NO = S.n_out;
+        const int64_t n4 = 4 * (int64_t)N;
+        if (NO > 0 && (!om || !om->h_Rp || !om->h_C || !om->h_Rd || !om->h_Pd || !om->h_Pi || !om->h_P || !om->h_Q))
+            throw Fail{NS_ERR_ARG, "outlet model missing"};
+        for (int k = 0; k < NO; ++k)
+            if (om->h_C[k] < 0 || (om->h_C[k] > 0 && !(om->h_Rd[k] > 0)))
+                throw Fail{NS_ERR_ARG, "Windkessel needs C >= 0 and R_d > 0 when C > 0"};
+        ns_newton_opts no{};
+        if (nopt) no = *nopt;
+        const double tol_R = dfltd(no.tol_R, 1e-6), tol_A = dfltd(no.tol_A, 1e-6);
+        const double eps_abs = dfltd(no.eps_abs, 1e-8), eps_rel = dfltd(no.eps_rel, 1e-5);
+        const int l_max = dflt(no.l_max, 20);
+        const int nts = om ? dflt(om->n_ts, 100) : 100;
+        const double am = 0.5 * (3.0 - phys->rho_inf) / (1.0 + phys->rho_inf);
+        const double af = 1.0 / (1.0 + phys->rho_inf), gam = af;
+        const double dt = phys->dt;
+        ns_step_stats st_out{};
+        auto t0 = std::chrono::steady_clock::now();
+        HIPCHK(hipSetDevice(c->device));
+        // predictor
+        axpby<double>(n4, 1.0, d_y_n, 0.0, d_y_n, d_y, st);
+        axpby<double>(n4, (gam - 1.0) / gam, d_ydot_n, 0.0, d_ydot_n, d_ydot, st);
+        check_launch();
+        std::vector<double> Qn(NO), Pn(NO), Pin(NO), Q(NO), P(NO), m(NO), Paf(NO);
+        for (int k = 0; k < NO; ++k) {
+            Qn[k] = om->h_Q[k];
+            Pn[k] = om->h_P[k];
+            Pin[k] = om->h_Pi[k];
+        }
+        auto flows = [&](const double* y) {
+            if (NO == 0) return;
+            ns_status r = ns_outlet_flow(c, y, Q.data(), st);
+            if (r != NS_OK) throw Fail{r, c->err};
+        };
+        auto G = [&](int k, double q, double* pi_end) {
+            return windkessel(om->h_Rp[k], om->h_C[k], om->h_Rd[k], om->h_Pd[k], Pin[k], Qn[k], q, nts, dt, pi_end);
+        };
+        ns_phys ph = *phys;
+        ph.h_m = m.data();
+        ph.h_P_af = Paf.data();
+        double r0 = 0.0, r = 0.0;
+        bool conv = false;
+        double asm_ms = 0.0, sol_ms = 0.0;
+        for (int l = 1; l <= l_max; ++l) {
+            flows(d_y);
+            for (int k = 0; k < NO; ++k) {
+                const double eps = std::max(eps_abs, eps_rel * std::fabs(Q[k]));
+                P[k] = G(k, Q[k], nullptr);
+                m[k] = (G(k, Q[k] + 0.5 * eps, nullptr) - G(k, Q[k] - 0.5 * eps, nullptr)) / eps;
+                Paf[k] = (1.0 - af) * Pn[k] + af * P[k];
+            }
+            axpby<double>(n4, 1.0 - af, d_y_n, af, d_y, c->nt_yaf, st);
+            axpby<double>(n4, 1.0 - am, d_ydot_n, am, d_ydot, c->nt_ydam, st);
+            check_launch();
+            auto ta = std::chrono::steady_clock::now();
+            ns_status ra = ns_assemble_tangent(c, &ph, c->nt_yaf, c->nt_yaf + 3 * (int64_t)N, c->nt_ydam, c->nt_rhs,
+                                               st);
+            if (ra != NS_OK) throw Fail{ra, c->err};
+            norm2<double>(n4, c->nt_rhs, c->nt_scal, c->d_red, st);
+            check_launch();
+            HIPCHK(hipMemcpyAsync(c->h_pinned, c->nt_scal, sizeof(double), hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            asm_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - ta).count();
+            r = c->h_pinned[0];
+            if (!std::isfinite(r)) throw Fail{NS_ERR_NAN, "residual is not finite"};
+            if (l == 1) r0 = r;
+            if (l - 1 < 32) st_out.res_hist[l - 1] = r;
+            if (r <= tol_R * r0 || r <= tol_A) {
+                conv = true;
+                break;
+            }
+            ns_stats ls{};
+            auto tsol = std::chrono::steady_clock::now();
+            ns_status rs = ns_nested_solve(c, sopt, c->nt_rhs, c->nt_dx, &ls, st);
+            sol_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tsol).count();
+            if (rs < 0) throw Fail{rs, c->err};
+            st_out.lin_outer += ls.outer_iters;
+            st_out.lin_a += ls.a_iters;
+            st_out.lin_s += ls.s_iters;
+            st_out.lin_inner += ls.inner_iters;
+            newton_update(n4, gam * dt, c->nt_dx, d_y, d_ydot, st);
+            check_launch();
+            st_out.iterations = l;
+        }
+        // reduced model at the accepted iterate
+        flows(d_y);
+        for (int k = 0; k < NO; ++k) {
+            double pi_end = 0.0;
+            const double pk = G(k, Q[k], &pi_end);
+            om->h_Q[k] = Q[k];
+            om->h_P[k] = pk;
+            om->h_Pi[k] = pi_end;
+        }
+        HIPCHK(hipStreamSynchronize(st));
+        st_out.converged = conv ? 1 : 0;
+        st_out.res0 = r0;
+        st_out.res = r;
+        st_out.assemble_ms = asm_ms;
+        st_out.solve_ms = sol_ms;
+        st_out.total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        if (hs) *hs = st_out;
+        return conv ? NS_OK : NS_NOT_CONVERGED;
     });
 }
 

@@ -179,6 +179,8 @@ struct ns_ctx {
            *t_yv = nullptr, *t_xhat = nullptr, *t_xbar = nullptr, *t_xt = nullptr, *t_r4 = nullptr;
     double* t_sf = nullptr;  // [3N] scratch of the factored S_hat application
     double* t_ps = nullptr;  // [2N] residual and correction of the P_S iteration
+    // time step: state at n+af / n+am, residual, Newton correction [4N], scalars
+    double *nt_yaf = nullptr, *nt_ydam = nullptr, *nt_rhs = nullptr, *nt_dx = nullptr, *nt_scal = nullptr;
     double* d_bnd = nullptr; // [2 hierarchies][levels][3] smoother-bound scalars
     double* h_pinned = nullptr;  // pinned host scalars
     double* h_mapped = nullptr;  // pinned, device-mapped host scalars written by kernels

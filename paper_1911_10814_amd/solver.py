@@ -223,6 +223,44 @@ class NsContext:
         self._check(self.lib.ns_newton_update(self.h, float(gamma_dt), _ptr(dx), _ptr(y), _ptr(ydot),
                                               _stream_handle(self.device)))
 
+    def time_step(self, y_n, ydot_n, *, rho, mu, dt, rho_inf, model=None, newton=None,
+                  opts: SolveOptions | None = None, beta_bf=0.2, c_t=4.0, c_i=36.0):
+        """One time step by the predictor multi-corrector algorithm (``ns_time_step``).
+
+        y_n, ydot_n: [4N] field-split state at t_n.  ``model``: dict of per-outlet
+        arrays Rp, C, Rd, Pd (P_d at t_{n+1}), Pi, P, Q (values at t_n) and n_ts;
+        C = 0 gives the resistance outlet (Rp + Rd) Q + Pd.  ``newton``: dict
+        with tol_R, tol_A, eps_abs, eps_rel, l_max.  Returns (y, ydot, stats,
+        model') with model' holding Pi, P, Q at t_{n+1}."""
+        opts = opts or SolveOptions()
+        y_n = self._dev(y_n).reshape(-1)
+        ydot_n = self._dev(ydot_n).reshape(-1)
+        if y_n.numel() != 4 * self.N or ydot_n.numel() != 4 * self.N:
+            raise ValueError("states must have 4N entries")
+        y = torch.empty_like(y_n)
+        ydot = torch.empty_like(ydot_n)
+        no = self.n_out
+        model = dict(model or {})
+        arrs = {}
+        for k, dflt in (("Rp", 0.0), ("C", 0.0), ("Rd", 0.0), ("Pd", 0.0), ("Pi", 0.0), ("P", 0.0), ("Q", 0.0)):
+            a = np.ascontiguousarray(np.broadcast_to(np.asarray(model.get(k, dflt), dtype=np.float64), (no,)))
+            arrs[k] = a.copy()
+        om = _lib.NsOutletModel(*(arrs[k].ctypes.data_as(_lib.PD) for k in ("Rp", "C", "Rd", "Pd", "Pi", "P", "Q")),
+                                int(model.get("n_ts", 100)), 0)
+        nw = dict(newton or {})
+        nopt = _lib.NsNewtonOpts(nw.get("tol_R", 0.0), nw.get("tol_A", 0.0), nw.get("eps_abs", 0.0),
+                                 nw.get("eps_rel", 0.0), int(nw.get("l_max", 0)), 0)
+        ph = _lib.NsPhys(rho, mu, dt, rho_inf, beta_bf, c_t, c_i, None, None)
+        co, keep, _ = opts.to_c()
+        stats = _lib.NsStepStats()
+        st = self._check(self.lib.ns_time_step(self.h, C.byref(ph), C.byref(om), C.byref(nopt), C.byref(co),
+                                               _ptr(y_n), _ptr(ydot_n), _ptr(y), _ptr(ydot), C.byref(stats),
+                                               _stream_handle(self.device)))
+        info = stats.as_dict()
+        info["status"] = _lib.STATUS_NAMES[st]
+        out = {k: arrs[k] for k in ("Pi", "P", "Q")}
+        return y, ydot, info, out
+
     def kernel_timing(self, classes=()):
         """Time launches of the given kernel classes (see ``ns_kernel_class``) in later solves."""
         mask = 0
