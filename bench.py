@@ -200,6 +200,15 @@ def main():
                           "true_rel_res": runs[-1]["true_rel_res"]}
         print(f"[bench] {name}: {variants[name]}", file=sys.stderr, flush=True)
 
+    # one time step of the predictor multi-corrector (Sec. 2.5) from the state,
+    # resistance outlet, tol_R = tol_A = 1e-6, FP32-inner solves
+    model = {"Rp": case.R, "P": case.R * Q, "Q": Q}
+    tsr = ctx.time_step(y0, yd0, rho=case.rho, mu=case.mu, dt=case.dt, rho_inf=case.rho_inf, model=model,
+                        opts=o32)[2]
+    tstep = {k: tsr[k] for k in ("iterations", "converged", "res_hist", "lin_outer", "lin_a", "lin_s", "lin_inner",
+                                 "assemble_ms", "solve_ms", "total_ms")}
+    print(f"[bench] time step: {tstep}", file=sys.stderr, flush=True)
+
     solve32 = statistics.median(t["solve_ms"] for t in times)
     solve64 = statistics.median(i["wall_ms"] for i in f64)
     # dominant kernel: largest total time among the timed classes
@@ -236,6 +245,7 @@ def main():
         "iterations_fp64": {k: f64[-1][k] for k in ("outer_iters", "a_iters", "s_iters", "inner_iters")},
         "setup_ms": {"fp32_inner": info["setup_ms"], "fp64": f64[-1]["setup_ms"]},
         "variants": variants,
+        "time_step_fp32_inner": tstep,
         "true_rel_res": {"fp32_inner": info["true_rel_res"], "fp64": f64[-1]["true_rel_res"]},
         "kernels": kernels,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
