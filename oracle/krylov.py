@@ -12,6 +12,12 @@ TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).
   both), stopping on the preconditioned relative residual.
 * ``schur_apply`` -- Algorithm 2: D x - C A^{-1}(B x) with an inner GMRES on A.
 * ``scr_apply``   -- Algorithm 3: the action of P_SCR^{-1}.
+* ``simple_apply`` -- the action of P_SIMPLE^{-1} (Sec. 3.2): the inverse of
+  the three factors  [I 0; C A^{-1} I] [A 0; 0 S_hat] [I diag(A)^{-1} B; 0 I]
+  taken in turn, i.e. Algorithm 3 with its Schur solve on the sparse S_hat
+  (no inner solver) and its second A-solve replaced by the diagonal update
+  y_v = yhat_v - diag(A)^{-1} B y_p.  The intermediate solvers follow the
+  P_SCR settings (delta_A, delta_S, m_A, m_S, P_A, P_S).
 
 Readings where the paper is silent: all Krylov solves start from zero;
 orthogonalisation is classical Gram-Schmidt applied twice; the Hessenberg
@@ -211,6 +217,7 @@ class SolveOpts:
     cheb_degree: int = 2
     cheb_ratio: float = 10.0
     cycles_S: int = 1        # V-cycle iterations per application of P_S
+    pc: str = "scr"          # outer preconditioner: "scr" (Algorithm 3) or "simple" (Sec. 3.2)
     coarse_nodes: int = 128
     max_levels: int = 16
     atol: float = 1e-50
@@ -275,9 +282,23 @@ class NestedSolver:
         yv = self.solve_A(tv, o.rtol_A, sched)
         return np.concatenate([yv, yp])
 
+    def simple_apply(self, s, sched):
+        """P_SIMPLE^{-1} s (Sec. 3.2): lower factor, block diagonal, upper factor."""
+        S, o = self.S, self.o
+        n3 = 3 * self.N
+        sv, sp_ = s[:n3], s[n3:]
+        yv_hat = self.solve_A(sv, o.rtol_A, sched)
+        tp = sp_ - S.C @ yv_hat
+        yp, _ = gmres_left(lambda q: self.Shat @ q, self.pS, tp, o.rtol_S, o.m_S, o.nmax_S, sched, o.atol)
+        yv = yv_hat - (S.B @ yp) / self.dA
+        return np.concatenate([yv, yp])
+
     def solve(self, rhs, replay=None):
         sched = Schedule(replay)
         o = self.o
-        x, its, relres, conv = fgmres(self.S.apply, lambda v: self.scr_apply(v, sched), rhs, o.rtol,
+        if o.pc not in ("scr", "simple"):
+            raise ValueError(f"unknown outer preconditioner {o.pc!r}")
+        apply_pc = self.scr_apply if o.pc == "scr" else self.simple_apply
+        x, its, relres, conv = fgmres(self.S.apply, lambda v: apply_pc(v, sched), rhs, o.rtol,
                                       o.m, o.nmax, sched, o.atol)
         return x, dict(outer=its, true_rel_res=relres, converged=conv, schedule=sched.log)

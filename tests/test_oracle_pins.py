@@ -413,6 +413,45 @@ def test_nested_solve_matches_dense_lu(name):
     assert np.array_equal(x, x2) and info2["schedule"] == info["schedule"]
 
 
+@pytest.mark.parametrize("name,transposed", [("cube", False), ("channel2", False), ("channel2", True)])
+def test_exact_subsolves_make_simple_the_factored_product(name, transposed):
+    """With exact A- and S_hat-solves the SIMPLE preconditioner is the product of
+    its three factors, [A  A diag(A)^{-1} B; C  D] (Sec. 3.2): applying the
+    oracle's P_SIMPLE^{-1} and then that dense matrix returns the input."""
+    S = get_assembled(name)
+    if transposed:
+        S = S.transposed()
+    c = get_case(name)
+    o = kr.SolveOpts(pc="simple", rtol_A=1e-14, rtol_S=1e-14)
+    ns = kr.NestedSolver(S, amg.node_adjacency(c.n_nodes, c.tets), o)
+    n3 = 3 * S.n_nodes
+    Ad = S.dense()
+    A, B, C, D = Ad[:n3, :n3], Ad[:n3, n3:], Ad[n3:, :n3], Ad[n3:, n3:]
+    dA = np.diag(A)
+    P = np.block([[A, A @ (B / dA[:, None])], [C, D]])
+    s = np.random.default_rng(11).standard_normal(4 * S.n_nodes)
+    y = ns.simple_apply(s, kr.Schedule())
+    assert np.linalg.norm(P @ y - s) <= 1e-10 * np.linalg.norm(s)
+    # and it is not the tangent's inverse (the (1,2) block differs)
+    assert np.linalg.norm(Ad @ y - s) > 1e-6 * np.linalg.norm(s)
+
+
+@pytest.mark.parametrize("name", ["cube", "channel2"])
+def test_simple_outer_solve_matches_dense_lu(name):
+    S = get_assembled(name)
+    c = get_case(name)
+    ns = kr.NestedSolver(S, amg.node_adjacency(c.n_nodes, c.tets), kr.SolveOpts(rtol=1e-8, pc="simple"))
+    x, info = ns.solve(S.rhs)
+    Ad = S.dense()
+    assert info["converged"] and np.linalg.norm(S.rhs - Ad @ x) <= 1e-8 * np.linalg.norm(S.rhs)
+    xs = np.linalg.solve(Ad, S.rhs)
+    assert np.linalg.norm(x - xs) <= np.linalg.cond(Ad) * 1e-8 * np.linalg.norm(xs)
+    # two Krylov calls per preconditioner application (A, then S_hat), replayable
+    assert len(info["schedule"]) == 1 + 2 * info["outer"]
+    x2, info2 = ns.solve(S.rhs, replay=info["schedule"])
+    assert np.array_equal(x, x2)
+
+
 def test_jacobi_variant_converges():
     S = get_assembled("channel2")
     c = get_case("channel2")
