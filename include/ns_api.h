@@ -103,6 +103,14 @@ typedef struct {
 } ns_phys;
 
 typedef enum { NS_PC_AMG = 0, NS_PC_JACOBI = 1 } ns_pc;
+/* Outer (FGMRES) preconditioner.  NS_OUTER_SCR: the nested Schur complement
+ * reduction of Algorithm 3, whose S-solve applies S = D - C A^-1 B
+ * matrix-free (Algorithm 2).  NS_OUTER_SIMPLE: the SIMPLE preconditioner of
+ * Sec. 3.2, the product [I 0; C A^-1 I][A 0; 0 S_hat][I diag(A)^-1 B; 0 I]
+ * inverted factor by factor: one A-solve (rtol_A), one GMRES(m_S) solve on
+ * the sparse S_hat = D - C diag(A)^-1 B (rtol_S, P_S), then
+ * y_v = yhat_v - diag(A)^-1 B y_p; no inner solver (rtol_I unused). */
+typedef enum { NS_OUTER_SCR = 0, NS_OUTER_SIMPLE = 1 } ns_outer_pc;
 typedef enum { NS_FP64 = 0, NS_FP32_INNER = 1 } ns_precision;
 
 /* Solver options (Sec. 3 and 3.1; paper defaults in brackets).  A field set
@@ -124,6 +132,8 @@ typedef struct {
     int32_t cycles_S;       /* V-cycle iterations per application of P_S
                              * (stationary iteration on S_hat from zero;
                              * may diverge when > 1)                   [1]    */
+    int32_t pc;             /* ns_outer_pc: outer preconditioner      [SCR]   */
+    int32_t reserved;       /* must be 0 */
     /* Iteration schedule.  If h_sched != NULL, the i-th Krylov call (calls
      * numbered in the order they start: FGMRES, then each GMRES on A or S)
      * runs exactly h_sched[i] iterations instead of testing its tolerance.
@@ -138,8 +148,10 @@ typedef struct {
 
 typedef struct {
     int32_t outer_iters;    /* FGMRES iterations */
-    int32_t a_solves, a_iters;         /* intermediate A-solves (Alg. 3 steps 1, 5) */
-    int32_t s_solves, s_iters;         /* Schur solves (Alg. 3 step 3) */
+    int32_t a_solves, a_iters;         /* intermediate A-solves (Alg. 3 steps 1, 5;
+                                        * SIMPLE: one per application) */
+    int32_t s_solves, s_iters;         /* Schur solves (Alg. 3 step 3; SIMPLE:
+                                        * the S_hat solve) */
     int32_t inner_solves, inner_iters; /* inner A-solves (Alg. 2 step 3) */
     int32_t n_calls;        /* Krylov calls (schedule entries) */
     int32_t amg_levels_A, amg_levels_S;
@@ -339,7 +351,8 @@ typedef enum {
     NS_OP_VCYCLE_S = 7, /* y = one AMG V-cycle of the S_hat hierarchy [N]  */
     NS_OP_SCHUR = 8,  /* y = Algorithm 2 applied to x [N] (inner rtol_I)  */
     NS_OP_PSCR = 9,   /* y = Algorithm 3 applied to x [4N]                */
-    NS_OP_SOLVE_A = 10 /* y = GMRES(m_A) solution of A y = x to rtol_A    */
+    NS_OP_SOLVE_A = 10, /* y = GMRES(m_A) solution of A y = x to rtol_A   */
+    NS_OP_PSIMPLE = 11  /* y = P_SIMPLE^-1 x (Sec. 3.2), x, y: [4N]        */
 } ns_op;
 
 /* ns_apply: one operator of the forward system, after the per-step set-up

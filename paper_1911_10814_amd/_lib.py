@@ -14,7 +14,7 @@ STATUS_NAMES = {0: "NS_OK", 1: "NS_NOT_CONVERGED", -1: "NS_ERR_ARG", -2: "NS_ERR
 KERNEL_CLASSES = {"spmv_A": 0, "cheb_A0": 1, "spmv_full": 2}
 
 OPS = {"full": 0, "A": 1, "B": 2, "C": 3, "D": 4, "shat": 5, "vcycle_A": 6, "vcycle_S": 7, "schur": 8,
-       "pscr": 9, "solve_A": 10}
+       "pscr": 9, "solve_A": 10, "psimple": 11}
 
 PD = C.POINTER(C.c_double)
 PI = C.POINTER(C.c_int32)
@@ -41,6 +41,7 @@ class NsSolveOpts(C.Structure):
                 ("rtol_I", C.c_double), ("cheb_ratio", C.c_double), ("m", C.c_int32), ("nmax", C.c_int32), ("m_A", C.c_int32),
                 ("nmax_A", C.c_int32), ("m_S", C.c_int32), ("nmax_S", C.c_int32), ("pc_A", C.c_int32),
                 ("precision", C.c_int32), ("cheb_degree", C.c_int32), ("cycles_S", C.c_int32),
+                ("pc", C.c_int32), ("reserved", C.c_int32),
                 ("h_sched", PI), ("sched_len", C.c_int32), ("sched_cap", C.c_int32), ("h_sched_out", PI)]
 
 

@@ -352,6 +352,8 @@ void read_status(ns_ctx* c, const double* d_status, int n, hipStream_t st) {
 // host-mapped scalar slots written by kernels: [0..1] Arnoldi status, [8] norms
 // [9 + kind] initial residual norm of a left GMRES call of that kind
 constexpr int kMapStatus = 0, kMapNorm = 8, kMapNorm0 = 9;
+// graph kinds of Arnoldi steps (one mapped initial-norm slot each)
+constexpr int kKindA = 0, kKindS = 1, kKindOuter = 2, kKindShat = 3;
 
 template <typename T>
 double dev_norm(ns_ctx* c, int64_t n, const T* x, double* slot, hipStream_t st) {
@@ -373,7 +375,8 @@ void run_step(ns_ctx* c, const Ctl& K, int kind, int j, F&& body) {
         return;
     }
     const int sys = K.sy == &c->sys[0] ? 0 : 1;
-    const auto key = std::make_tuple(kind, sys, K.o.precision, K.o.pc_A, dflt(K.o.cheb_degree, kDefaultChebDegree), j);
+    const auto key = std::make_tuple(kind, sys, K.o.precision, K.o.pc_A, dflt(K.o.cheb_degree, kDefaultChebDegree),
+                                     dflt(K.o.cycles_S, kDefaultCyclesS), j);
     auto it = c->graphs.find(key);
     if (it == c->graphs.end()) {
         HIPCHK(hipStreamBeginCapture(K.st, hipStreamCaptureModeThreadLocal));
@@ -739,7 +742,7 @@ struct Nested {
         return gmres_left<T>(
             K, c->kw_A, 3 * (int64_t)N, [this](const T* in, T* out) { applyA(in, out); },
             [this](const T* in, T* out) { applyPA(in, out); }, b, x, rtol, dflt(K.o.m_A, 200),
-            dflt(K.o.nmax_A, 200), 0, true, sM, sP);
+            dflt(K.o.nmax_A, 200), kKindA, true, sM, sP);
     }
     // Algorithm 2: y = D x - C A^{-1} (B x)
     void schur(const T* xp, T* y, const FirstStep<T>* fs = nullptr) {
@@ -763,7 +766,47 @@ struct Nested {
         return gmres_left<T>(
             K, c->kw_S, N, [this](const T* in, T* out) { schur(in, out); },
             [this](const T* in, T* out) { applyPS(in, out); }, b, x, dfltd(K.o.rtol_S, 1e-3), dflt(K.o.m_S, 200),
-            dflt(K.o.nmax_S, 200), 1, false, sM, sP);
+            dflt(K.o.nmax_S, 200), kKindS, false, sM, sP);
+    }
+    // GMRES(m_S) on the sparse S_hat = D - C diag(A)^{-1} B, left
+    // preconditioned by P_S (the Schur solve of SIMPLE); S_hat is applied in
+    // factored form, so the operator launches kernels only and each Arnoldi
+    // step is one graph.
+    int solveShat(const T* b, T* x) {
+        auto applyM = [this](const T* in, T* out) {
+            shat_factored<T>(N, c->d_rp, c->d_col, V(), nnzb, Typed<T>::dinvA(sy), in, nullptr, nullptr,
+                             as<T>(c->t_sf), out, T(1), nullptr, T(0), nullptr, nullptr, nullptr, 0, nullptr,
+                             xcd_rows(N, 1), K.st);
+        };
+        return gmres_left<T>(K, c->kw_S, N, applyM, [this](const T* in, T* out) { applyPS(in, out); }, b, x,
+                             dfltd(K.o.rtol_S, 1e-3), dflt(K.o.m_S, 200), dflt(K.o.nmax_S, 200), kKindShat, true);
+    }
+    // SIMPLE (Sec. 3.2): y = P_SIMPLE^{-1} s, the factors of
+    // [I 0; C A^{-1} I][A 0; 0 S_hat][I diag(A)^{-1} B; 0 I] inverted in turn.
+    void simple(const T* s, T* y) {
+        hipStream_t st = K.st;
+        const int64_t n3 = 3 * (int64_t)N;
+        const T* sv = s;
+        const T* sp = s + n3;
+        T* yhat = as<T>(c->t_yhat);
+        int it = solveA(sv, yhat, dfltd(K.o.rtol_A, 1e-3));
+        K.stats.a_solves++;
+        K.stats.a_iters += it;
+        spmv<T>(1, 3, op(3, 0), yhat, as<T>(c->t_tp), T(-1), sp, T(1), nullptr, nullptr, st);
+        T* yp = y + n3;
+        it = solveShat(as<T>(c->t_tp), yp);
+        K.stats.s_solves++;
+        K.stats.s_iters += it;
+        T* tv = as<T>(c->t_tv);
+        spmv<T>(3, 1, op(0, 3), yp, tv, T(1), nullptr, T(0), nullptr, nullptr, st);
+        mul<T>(n3, Typed<T>::dinvA(sy), tv, tv, st);
+        axpby<T>(n3, T(1), yhat, T(-1), tv, y, st);
+    }
+    void apply_pc(const T* s, T* y) {
+        if (K.o.pc == NS_OUTER_SIMPLE)
+            simple(s, y);
+        else
+            scr(s, y);
     }
     // Algorithm 3: y = P_SCR^{-1} s   (s, y: [4N], field-split)
     void scr(const T* s, T* y) {
@@ -832,13 +875,13 @@ ns_status fgmres(Ctl& K, const double* b, double* x) {
             double* vj = V + (int64_t)j * kw.ld;
             double* zj = Z + (int64_t)j * kw.ld;
             if (std::is_same<T, double>::value) {
-                P.scr(reinterpret_cast<const T*>(vj), reinterpret_cast<T*>(zj));
+                P.apply_pc(reinterpret_cast<const T*>(vj), reinterpret_cast<T*>(zj));
             } else {
                 convert<double, T>(n, vj, as<T>(c->t_s), st);
-                P.scr(as<T>(c->t_s), as<T>(c->t_yp));
+                P.apply_pc(as<T>(c->t_s), as<T>(c->t_yp));
                 convert<T, double>(n, as<T>(c->t_yp), zj, st);
             }
-            run_step(c, K, 2, j, [&] {
+            run_step(c, K, kKindOuter, j, [&] {
                 applyFull(zj, V + (int64_t)(j + 1) * kw.ld, 1.0, nullptr, 0.0);
                 cgs2_launch<double>(c, kw, n, j, V, st);
             });
@@ -1034,6 +1077,13 @@ void ensure_transposed(ns_ctx* c, hipStream_t st) {
     t.ready = false;
 }
 
+void check_solve_opts(const ns_solve_opts& o) {
+    if (o.precision != NS_FP64 && o.precision != NS_FP32_INNER) throw Fail{NS_ERR_ARG, "unknown precision"};
+    if (o.pc != NS_OUTER_SCR && o.pc != NS_OUTER_SIMPLE) throw Fail{NS_ERR_ARG, "unknown outer preconditioner"};
+    if (o.pc_A != NS_PC_AMG && o.pc_A != NS_PC_JACOBI) throw Fail{NS_ERR_ARG, "unknown P_A"};
+    if (o.reserved != 0) throw Fail{NS_ERR_ARG, "reserved option field must be 0"};
+}
+
 ns_status run_solve(ns_ctx* c, int which, const ns_solve_opts* opts, const double* b, double* x, ns_stats* hs,
                     hipStream_t st) {
     if (!c->bound) throw Fail{NS_ERR_STATE, "context not bound"};
@@ -1046,7 +1096,7 @@ ns_status run_solve(ns_ctx* c, int which, const ns_solve_opts* opts, const doubl
     K.o.atol = K.o.atol > 0 ? K.o.atol : 1e-50;
     if (dflt(K.o.m, 200) > c->kw_out.m || dflt(K.o.m_A, 200) > c->kw_A.m || dflt(K.o.m_S, 200) > c->kw_S.m)
         throw Fail{NS_ERR_ARG, "restart length exceeds the context's Krylov workspace"};
-    if (K.o.precision != NS_FP64 && K.o.precision != NS_FP32_INNER) throw Fail{NS_ERR_ARG, "unknown precision"};
+    check_solve_opts(K.o);
     K.sc.replay = K.o.h_sched;
     K.sc.replay_len = K.o.sched_len;
     HIPCHK(hipSetDevice(c->device));
@@ -1607,9 +1657,10 @@ ns_status ns_apply(ns_ctx* c, int32_t op, const ns_solve_opts* opts, const doubl
         setup_system(c, c->sys[0], f32, st);
         upload_coef(c, c->sys[0], dflt(K.o.cheb_degree, kDefaultChebDegree), dfltd(K.o.cheb_ratio, kDefaultChebRatio), st);
         const int N = c->sym.N;
-        const int64_t nin[] = {4L * N, 3L * N, N, 3L * N, N, N, 3L * N, N, N, 4L * N, 3L * N};
-        const int64_t nout[] = {4L * N, 3L * N, 3L * N, N, N, N, 3L * N, N, N, 4L * N, 3L * N};
-        if (op < 0 || op > NS_OP_SOLVE_A) throw Fail{NS_ERR_ARG, "unknown operator"};
+        const int64_t nin[] = {4L * N, 3L * N, N, 3L * N, N, N, 3L * N, N, N, 4L * N, 3L * N, 4L * N};
+        const int64_t nout[] = {4L * N, 3L * N, 3L * N, N, N, N, 3L * N, N, N, 4L * N, 3L * N, 4L * N};
+        if (op < 0 || op > NS_OP_PSIMPLE) throw Fail{NS_ERR_ARG, "unknown operator"};
+        check_solve_opts(K.o);
         auto run = [&](auto tag) {
             using T = decltype(tag);
             Nested<T> P(K);
@@ -1647,6 +1698,7 @@ ns_status ns_apply(ns_ctx* c, int32_t op, const ns_solve_opts* opts, const doubl
                 case NS_OP_SCHUR: P.schur(x, y); break;
                 case NS_OP_PSCR: P.scr(x, y); break;
                 case NS_OP_SOLVE_A: P.solveA(x, y, dfltd(K.o.rtol_A, 1e-3)); break;
+                case NS_OP_PSIMPLE: P.simple(x, y); break;
             }
             if (!std::is_same<T, double>::value) convert<T, double>(nout[op], y, d_y, st);
         };

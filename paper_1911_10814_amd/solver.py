@@ -36,6 +36,7 @@ class SolveOptions:
     cheb_degree: int = 2
     cheb_ratio: float = 10.0     # smoother interval [lambda/cheb_ratio, lambda]
     cycles_S: int = 1            # V-cycle iterations per application of P_S
+    pc: str = "scr"              # outer preconditioner: "scr" (Algorithm 3) | "simple" (Sec. 3.2)
     schedule: list | None = None  # fixed iteration counts per Krylov call (replay)
     record: bool = True           # record the iteration count of every Krylov call
 
@@ -46,6 +47,7 @@ class SolveOptions:
             setattr(o, f, getattr(self, f))
         o.pc_A = {"amg": 0, "jacobi": 1}[self.pc_A]
         o.precision = {"fp64": 0, "fp32_inner": 1}[self.precision]
+        o.pc = {"scr": 0, "simple": 1}[self.pc]
         keep = []
         if self.schedule is not None:
             arr = np.ascontiguousarray(self.schedule, dtype=np.int32)
@@ -296,9 +298,9 @@ class NsContext:
     def apply(self, op: str, x, opts: SolveOptions | None = None):
         """One operator of the forward system (see ``ns_op``); returns (y, schedule)."""
         sizes_in = {"full": 4, "A": 3, "B": 1, "C": 3, "D": 1, "shat": 1, "vcycle_A": 3, "vcycle_S": 1,
-                    "schur": 1, "pscr": 4, "solve_A": 3}
+                    "schur": 1, "pscr": 4, "solve_A": 3, "psimple": 4}
         sizes_out = {"full": 4, "A": 3, "B": 3, "C": 1, "D": 1, "shat": 1, "vcycle_A": 3, "vcycle_S": 1,
-                     "schur": 1, "pscr": 4, "solve_A": 3}
+                     "schur": 1, "pscr": 4, "solve_A": 3, "psimple": 4}
         x = self._dev(x).reshape(-1)
         if x.numel() != sizes_in[op] * self.N:
             raise ValueError(f"operator {op} takes {sizes_in[op]}N entries")

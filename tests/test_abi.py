@@ -69,3 +69,36 @@ def test_invalid_mesh_is_rejected():
     bad2.outlet_ptr[1] = c.outlet_ptr[2]
     with pytest.raises(NsError, match="share"):
         NsContext(bad2)
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """Every ctypes structure of the binding has the size and field offsets
+    the C compiler gives the header's struct."""
+    import shutil
+    import subprocess
+    from paper_1911_10814_amd import _lib
+    if shutil.which("gcc") is None:
+        pytest.skip("no C compiler")
+    pairs = {"ns_mesh": _lib.NsMesh, "ns_ctx_opts": _lib.NsCtxOpts, "ns_phys": _lib.NsPhys,
+             "ns_solve_opts": _lib.NsSolveOpts, "ns_stats": _lib.NsStats, "ns_outlet_model": _lib.NsOutletModel,
+             "ns_newton_opts": _lib.NsNewtonOpts, "ns_step_stats": _lib.NsStepStats}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "ns_api.h"', "int main(void) {"]
+    for cname, cls in pairs.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in cls._fields_:
+            lines.append(f'  printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), "-I", "/opt/rocm/include", "-D__HIP_PLATFORM_AMD__",
+                    str(src), "-o", str(exe)], check=True)
+    got = {}
+    for ln in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.splitlines():
+        cname, field, val = ln.split()
+        got[(cname, field)] = int(val)
+    import ctypes
+    for cname, cls in pairs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(cls), cname
+        for f, _ in cls._fields_:
+            assert got[(cname, f)] == getattr(cls, f).offset, (cname, f)
