@@ -539,7 +539,7 @@ int gmres_left(Ctl& K, KrylovWs& kw, int64_t n, const std::function<void(const T
             check_launch();
             break;
         }
-        backsolve(k, m + 1, kw.H, kw.g, kw.y, st);
+        backsolve(k, kw.m + 1, kw.H, kw.g, kw.y, st);  // H is stored with the workspace leading dimension
         combine<T, T>(n, k, V, kw.ld, kw.y, x, !first, st);
         check_launch();
         first = false;
@@ -893,7 +893,7 @@ ns_status fgmres(Ctl& K, const double* b, double* x) {
             const bool done = forced >= 0 ? total >= forced : resid <= tol;
             if (done || bd || total >= nmax) break;
         }
-        backsolve(k, m + 1, kw.H, kw.g, kw.y, st);
+        backsolve(k, kw.m + 1, kw.H, kw.g, kw.y, st);  // H is stored with the workspace leading dimension
         combine<double, double>(n, k, Z, kw.ld, kw.y, x, true, st);
         // true residual in FP64
         applyFull(x, V, -1.0, b, 1.0);

@@ -150,6 +150,22 @@ def test_nested_solve_fp64_replay_and_tolerance(name):
         assert rel(xt.cpu().numpy(), xo) <= 1e-10
 
 
+@pytest.mark.parametrize("name,pc_A", [("channel2", "amg"), ("pipe_tiny", "jacobi"), ("ybif_small", "amg")])
+def test_short_restart_lengths_replay_matches_oracle(name, pc_A):
+    """Restart lengths below the context's maximum (the Hessenberg storage
+    keeps the workspace's leading dimension): FGMRES(2) and GMRES(8) capped at
+    20 iterations on A and S, so both levels restart."""
+    from paper_1911_10814_amd import SolveOptions
+    kw = dict(m=2, m_A=8, m_S=8, nmax_A=20, nmax_S=20, pc_A=pc_A)
+    ctx = ctx_for(name)
+    S = get_assembled(name)
+    xo, info = oracle_solver(name, **kw).solve(S.rhs)
+    xg, gi = ctx.solve(ctx._rhs, SolveOptions(schedule=info["schedule"], **kw))
+    assert rel(xg.cpu().numpy(), xo) <= 1e-10
+    xt, ti = ctx.solve(ctx._rhs, SolveOptions(**kw))
+    assert ti["converged"] and ti["true_rel_res"] <= 1e-8
+
+
 @pytest.mark.parametrize("name", CASES)
 def test_nested_solve_fp32_inner(name):
     from paper_1911_10814_amd import SolveOptions
