@@ -327,6 +327,76 @@ def conexp(size: str = "conexp_4m", seed: int = 5, R: float = 1e5, re_t: float =
                     "pressure": "p = 0 everywhere"})
 
 
+# ----------------------------------------------------------------------------
+# Box with a perforated top: many resistance / Windkessel outlets
+# ----------------------------------------------------------------------------
+
+PLATE_SIZES = {
+    # name: (patches per side, quads per patch side, layers) -> patches^2 outlets
+    "plate_small": (4, 3, 4),
+    "plate_784": (28, 3, 10),    # as many outlets as the paper's pulmonary model (772)
+}
+
+
+def plate(size: str = "plate_784", seed: int = 6, umax: float = 10.0, noise: float = 0.01, height: float = 0.5,
+          R_range=(1e4, 1e5), tau_range=(0.05, 0.5), rho: float = 1.06, mu: float = 0.04, dt: float = 1e-3) -> Case:
+    """Box [0,1]^2 x [0,height] (Kuhn lattice); inflow v_z = umax 16 x(1-x)
+    y(1-y) at z = 0; no-slip side walls.  The top z = height carries
+    patches^2 square outlet patches of q x q quads on a grid of cells of
+    (q+1) x (q+1) quads: one quad row of no-slip wall separates neighbouring
+    patches (and the patches from the side walls), so the outlets share no
+    node and every patch rim is wall.  Outlet parameters (seeded,
+    log-uniform): R_k in R_range; for the three-element Windkessel
+    Rp = R/10, Rd = 9R/10 and C = tau/Rd with tau in tau_range (meta['rcr']).
+    State: the inflow profile continued along z plus N(0, (noise umax)^2) on
+    free components; p = 0."""
+    npch, q, nz = PLATE_SIZES[size]
+    c = q + 1
+    n = npch * c + 1
+    xyz, tets = meshes.kuhn_box(n, n, nz, 1.0, 1.0, height)
+    N = len(xyz)
+    tol = 1e-12
+    x, y, z = xyz[:, 0], xyz[:, 1], xyz[:, 2]
+    ix = np.rint(x * n).astype(int)
+    iy = np.rint(y * n).astype(int)
+    top = np.abs(z - height) < tol
+
+    def inner(i):  # node index strictly inside a patch along one axis
+        t = (i - 1) % c
+        return (i >= 1) & (i <= n - 1) & (t >= 1) & (t <= q - 1)
+
+    free_top = top & inner(ix) & inner(iy)
+    side = (x < tol) | (x > 1 - tol) | (y < tol) | (y > 1 - tol)
+    bottom = z < tol
+    dir_nodes = side | bottom | (top & ~free_top)
+    mask = np.zeros((N, 4), np.uint8)
+    mask[dir_nodes, :3] = 1
+    bf = meshes.boundary_faces(xyz, tets)
+    on_top = np.all(np.abs(xyz[bf][:, :, 2] - height) < tol, axis=1)
+    tf = bf[on_top]
+    u = xyz[tf].mean(axis=1)[:, :2] * n - 1.0    # face centroid in quad units from the first gap
+    cell = np.floor(u / c).astype(int)
+    inpatch = np.all((u - cell * c) < q, axis=1) & np.all(u > 0, axis=1)
+    pid = cell[:, 0] * npch + cell[:, 1]
+    outlets = [tf[inpatch & (pid == k)] for k in range(npch * npch)]
+    prof = umax * 16.0 * x * (1 - x) * y * (1 - y)
+    v = np.zeros((N, 3))
+    v[:, 2] = prof
+    rng = np.random.Generator(np.random.PCG64(seed))
+    free = ~dir_nodes
+    v[free] += rng.normal(0.0, noise * umax, size=(int(free.sum()), 3))
+    v[dir_nodes] = 0.0
+    v[bottom & ~side, 2] = prof[bottom & ~side]
+    n_out = npch * npch
+    R = np.exp(rng.uniform(np.log(R_range[0]), np.log(R_range[1]), size=n_out))
+    tau = np.exp(rng.uniform(np.log(tau_range[0]), np.log(tau_range[1]), size=n_out))
+    Rd = 0.9 * R
+    rcr = {"Rp": 0.1 * R, "Rd": Rd, "C": tau / Rd}
+    return _finish(size, xyz, tets, mask, outlets, v, np.zeros(N), rho, mu, dt, 0.5, R,
+                   {"seed": seed, "patches": npch, "q": q, "layers": nz, "rcr": rcr,
+                    "pressure": "p = 0 everywhere"})
+
+
 def build(name: str, **kw) -> Case:
     if name.startswith("cube"):
         return cube_lid(**kw)
@@ -338,4 +408,6 @@ def build(name: str, **kw) -> Case:
         return ybif(name, **kw)
     if name in CONEXP_SIZES:
         return conexp(name, **kw)
+    if name in PLATE_SIZES:
+        return plate(name, **kw)
     raise KeyError(name)

@@ -3,6 +3,7 @@
     python -m paper_1911_10814_amd.studies tolerances [--config conexp_150k] [--cr 0.5 2.0]
     python -m paper_1911_10814_amd.studies resistance [--config pipe_200k] [--cr 1.0]
     python -m paper_1911_10814_amd.studies pa         [--config pipe_200k]
+    python -m paper_1911_10814_amd.studies outlets    [--config plate_784]
 
 * ``tolerances`` -- the nozzle study: FGMRES at delta^r = 1e-8 with the nested
   preconditioner at delta_A = delta_S = delta_I in {1e-8, 1e-6, 1e-4, 1e-2}
@@ -16,6 +17,10 @@
   with either preconditioner, and whole solves with the settings used for
   the patient-specific models (delta^r = 1e-2, delta_A = 1e-3,
   delta_S = delta_I = 1e-2, m_A = m_S = n^max_A = n^max_S = 20).
+* ``outlets`` -- many reduced-model outlets (the perforated plate: 784
+  outlets, as many as the pulmonary model's): the Newton-step solve with all
+  rank-one terms, and time steps of the predictor multi-corrector algorithm
+  with a three-element Windkessel on every outlet (Algorithm 1).
 
 Every solve prints one JSON line as soon as it ends (iteration counts per
 level, true relative residual, set-up and solve time of the best of
@@ -135,19 +140,45 @@ def study_pa(a):
         run(s, SolveOptions(precision=a.precision, pc_A=pc_A), a.repeat, study="pa_default_settings")
 
 
+def study_outlets(a):
+    s = System(a.config, a.cr[0] if a.cr else None, None)
+    c, ctx = s.case, s.ctx
+    for prec in ("fp32_inner", "fp64"):
+        run(s, SolveOptions(precision=prec), a.repeat, study="outlets_solve", n_outlets=c.n_outlets)
+    w = c.meta["rcr"]
+    y = torch.as_tensor(np.concatenate([c.v.ravel(), c.p]), device="cuda")
+    yd = torch.zeros_like(y)
+    Q = ctx.outlet_flow(c.v)
+    Pi = w["Rd"] * Q
+    model = {"Rp": w["Rp"], "C": w["C"], "Rd": w["Rd"], "Pd": np.zeros(c.n_outlets), "Pi": Pi,
+             "P": w["Rp"] * Q + Pi, "Q": Q, "n_ts": 100}
+    for step in range(a.steps):
+        y, yd, info, out = ctx.time_step(y, yd, rho=c.rho, mu=c.mu, dt=c.dt, rho_inf=c.rho_inf, model=model,
+                                         opts=SolveOptions(precision=a.precision))
+        model.update(Pi=out["Pi"], P=out["P"], Q=out["Q"])
+        rec = {k: info[k] for k in ("iterations", "converged", "res_hist", "lin_outer", "lin_a", "lin_s",
+                                    "lin_inner", "assemble_ms", "solve_ms", "total_ms")}
+        print(json.dumps(dict(study="outlets_time_step", config=c.name, n_nodes=c.n_nodes, n_outlets=c.n_outlets,
+                              step=step, precision=a.precision, P_mean=float(np.mean(out["P"])),
+                              Q_sum=float(np.sum(out["Q"])), **rec)), flush=True)
+
+
 def main(argv=None):
     p = argparse.ArgumentParser(description=__doc__.splitlines()[0])
-    p.add_argument("study", choices=["tolerances", "resistance", "pa"])
+    p.add_argument("study", choices=["tolerances", "resistance", "pa", "outlets"])
     p.add_argument("--config", default=None)
     p.add_argument("--cr", type=float, nargs="*", default=None, help="target Courant number(s)")
     p.add_argument("--precision", default="fp32_inner", choices=["fp64", "fp32_inner"])
     p.add_argument("--pc-A", dest="pc_A", nargs="+", default=["amg", "jacobi"], choices=["amg", "jacobi"])
     p.add_argument("--repeat", type=int, default=2)
+    p.add_argument("--steps", type=int, default=3, help="time steps of the outlets study")
     a = p.parse_args(argv)
     if not torch.cuda.is_available():
         sys.exit("the studies run the HIP library and need a GPU")
-    a.config = a.config or {"tolerances": "conexp_150k", "resistance": "pipe_200k", "pa": "pipe_200k"}[a.study]
-    {"tolerances": study_tolerances, "resistance": study_resistance, "pa": study_pa}[a.study](a)
+    a.config = a.config or {"tolerances": "conexp_150k", "resistance": "pipe_200k", "pa": "pipe_200k",
+                            "outlets": "plate_784"}[a.study]
+    {"tolerances": study_tolerances, "resistance": study_resistance, "pa": study_pa,
+     "outlets": study_outlets}[a.study](a)
 
 
 if __name__ == "__main__":

@@ -21,7 +21,7 @@ from oracle import discretization as dz
 
 pytestmark = pytest.mark.gpu
 
-FULL = ["pipe_200k", "pipe_2m", "ybif_1m", "conexp_4m"]
+FULL = ["pipe_200k", "pipe_2m", "ybif_1m", "conexp_4m", "plate_784"]
 
 
 def sampled_nodes(case, k=48, seed=7):
@@ -145,7 +145,7 @@ def test_sampled_tangent_rows_and_residual(full):
     assert np.abs(rg - S.rhs[d]).max() <= 1e-12 * max(np.abs(S.rhs[d]).max(), 1e-300)
 
 
-def _solve_and_check(full, opts, label):
+def _solve_and_check(full, opts, label, with_info=False):
     x, info = full.ctx.solve(full.rhs, opts)
     print(full.case.name, label, {k: info[k] for k in ("outer_iters", "a_iters", "s_iters", "inner_iters",
                                                         "true_rel_res", "solve_ms")}, flush=True)
@@ -156,7 +156,7 @@ def _solve_and_check(full, opts, label):
     # rounding of the oracle's own row products)
     bn = float(torch.linalg.norm(full.rhs))
     assert np.abs(r).max() <= (1.01 * info["true_rel_res"] + 1e-12) * bn
-    return xn
+    return (xn, info) if with_info else xn
 
 
 def _rel(a, b):
@@ -165,23 +165,26 @@ def _rel(a, b):
 
 def test_solves_fp64_and_fp32_inner(full):
     """FP64 and FP32-inner solves at rtol 1e-8.  Their solutions agree to
-    1e-6 when the tangent is well conditioned; otherwise (the difference is
-    bounded only by the residual tolerance times the conditioning) both are
-    compared with an FP64 reference at rtol 1e-10 and the FP32-inner error
-    must stay within 10x the FP64 solve's."""
+    1e-6 when the tangent is well conditioned.  Otherwise the error of either
+    solve is bounded only by its final true relative residual times the
+    conditioning, so both are compared with an FP64 reference at rtol 1e-10
+    per unit of their own final residual: the FP32-inner error per unit
+    residual must stay within 3x the FP64 solve's."""
     from paper_1911_10814_amd import SolveOptions
     n3 = 3 * full.case.n_nodes
-    x64 = _solve_and_check(full, SolveOptions(precision="fp64"), "fp64")
-    x32 = _solve_and_check(full, SolveOptions(precision="fp32_inner"), "fp32_inner")
+    x64, i64 = _solve_and_check(full, SolveOptions(precision="fp64"), "fp64", with_info=True)
+    x32, i32 = _solve_and_check(full, SolveOptions(precision="fp32_inner"), "fp32_inner", with_info=True)
     ev, ep = _rel(x32[:n3], x64[:n3]), _rel(x32[n3:], x64[n3:])
     print(full.case.name, "fp32_inner vs fp64: v %.2e p %.2e" % (ev, ep), flush=True)
     if ev <= 1e-6 and ep <= 1e-6:
         return
     xr = _solve_and_check(full, SolveOptions(precision="fp64", rtol=1e-10), "fp64 reference")
+    r64, r32 = i64["true_rel_res"], i32["true_rel_res"]
     for part in (slice(0, n3), slice(n3, None)):
         e64, e32 = _rel(x64[part], xr[part]), _rel(x32[part], xr[part])
-        print(full.case.name, f"error vs reference: fp64 {e64:.2e} fp32_inner {e32:.2e}", flush=True)
-        assert e32 <= max(1e-6, 10 * e64)
+        print(full.case.name, f"error vs reference: fp64 {e64:.2e} (res {r64:.2e}) fp32_inner {e32:.2e} "
+              f"(res {r32:.2e})", flush=True)
+        assert e32 <= max(1e-6, 3 * (e64 / r64) * r32)
 
 
 def test_resistance_sweep(full):

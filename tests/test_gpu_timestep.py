@@ -35,7 +35,12 @@ def inputs(name, rcr, seed=3):
     a_raw, _, _ = dz.outlet_vectors(c)
     no = c.n_outlets
     Q_n = np.array([np.sum(a_raw[k] * c.v) for k in range(no)])
-    if rcr:   # three-element Windkessel: R_p = R/10, R_d = 9R/10, C such that R_d C = 10 dt
+    if rcr == "meta":   # per-outlet Windkessel parameters of the workload, steady start
+        w = c.meta["rcr"]
+        Pi = w["Rd"] * Q_n
+        model = nt.OutletModel(Rp=w["Rp"], C=w["C"], Rd=w["Rd"], Pd=np.zeros(no), Pi=Pi, P=w["Rp"] * Q_n + Pi,
+                               Q=Q_n, n_ts=100)
+    elif rcr:   # three-element Windkessel: R_p = R/10, R_d = 9R/10, C such that R_d C = 10 dt
         Rp, Rd = 0.1 * c.R, 0.9 * c.R
         C = 10 * c.dt / Rd
         Pi = Rd * Q_n
@@ -48,7 +53,7 @@ def inputs(name, rcr, seed=3):
 
 
 @pytest.mark.parametrize("name,rcr", [("cube", False), ("channel2", False), ("channel2", True),
-                                      ("pipe_tiny", False)])
+                                      ("pipe_tiny", False), ("plate_small", "meta")])
 def test_time_step_matches_oracle(name, rcr):
     from paper_1911_10814_amd import SolveOptions
     c, y_n, ydot_n, model = inputs(name, rcr)

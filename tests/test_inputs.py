@@ -7,7 +7,7 @@ import pytest
 
 from ns_inputs import build, meshes
 
-SMALL = ["cube", "channel2", "pipe_tiny", "ybif_small", "conexp_small"]
+SMALL = ["cube", "channel2", "pipe_tiny", "ybif_small", "conexp_small", "plate_small"]
 
 
 def _faces(tets):
@@ -27,7 +27,7 @@ def test_mesh_conforming_and_oriented(name):
     assert len(np.unique(c.tets)) == c.n_nodes
 
 
-@pytest.mark.parametrize("name", ["channel2", "pipe_tiny", "ybif_small", "conexp_small"])
+@pytest.mark.parametrize("name", ["channel2", "pipe_tiny", "ybif_small", "conexp_small", "plate_small"])
 def test_outlets_planar_outward_disjoint(name):
     c = build(name)
     bf = {tuple(f) for f in np.sort(meshes.boundary_faces(c.xyz, c.tets), axis=1)}
@@ -47,7 +47,7 @@ def test_outlets_planar_outward_disjoint(name):
         assert np.all(np.einsum("fi,i->f", cen - inner, n[0]) > 0)
 
 
-@pytest.mark.parametrize("name", ["pipe_tiny", "ybif_small", "conexp_small"])
+@pytest.mark.parametrize("name", ["pipe_tiny", "ybif_small", "conexp_small", "plate_small"])
 def test_wall_is_dirichlet_and_outlet_interior_is_free(name):
     c = build(name)
     bf = meshes.boundary_faces(c.xyz, c.tets)
@@ -88,3 +88,20 @@ def test_conexp_throat_reynolds_number():
     # parabolic inflow with the throat's flow rate: peak 2 u_t (r_t / r_i)^2
     assert np.isclose(c.v[inlet, 2].max(), 2 * u_t * (0.2 / 0.6) ** 2, rtol=1e-12)
     assert np.all(c.v[inlet][r > 0.6 - 1e-9] == 0)
+
+
+def test_plate_outlet_patches():
+    c = build("plate_small")
+    npch, q = c.meta["patches"], c.meta["q"]
+    assert c.n_outlets == npch * npch
+    rcr = c.meta["rcr"]
+    assert np.allclose(rcr["Rp"] + rcr["Rd"], c.R) and (rcr["C"] > 0).all()
+    for k in range(c.n_outlets):
+        f = c.faces[c.outlet_ptr[k]:c.outlet_ptr[k + 1]]
+        assert len(f) == 2 * q * q                                # q x q quads, two triangles each
+        nodes = np.unique(f)
+        assert (c.mask[nodes, 0] == 0).sum() == (q - 1) ** 2      # interior nodes are free, the rim is wall
+        area = 0.5 * np.linalg.norm(np.cross(c.xyz[f[:, 1]] - c.xyz[f[:, 0]], c.xyz[f[:, 2]] - c.xyz[f[:, 0]]),
+                                    axis=1).sum()
+        n_quads = npch * (q + 1) + 1
+        assert np.isclose(area, (q / n_quads) ** 2)
