@@ -86,6 +86,10 @@ typedef struct {
     int32_t max_m_S;      /* largest m_S                          [200] */
     int32_t coarse_nodes; /* AMG coarsening stops at <= this many nodes [128] */
     int32_t max_levels;   /* AMG levels including the coarsest    [16]  */
+    int32_t coarse_matchings; /* greedy pairwise matchings composed per
+                           * coarsening step below the finest level, 2..4
+                           * (aggregates of at most 2^k nodes); the finest
+                           * step always uses two              [2]   */
 } ns_ctx_opts;
 
 /* Physics of one Newton step (Sec. 2.3, 2.4.1, 2.5).

@@ -74,15 +74,22 @@ def quotient(adj, agg, nc):
     return [np.array(sorted(s), dtype=np.int64) for s in sets]
 
 
-def build_aggregates(adj, coarse_nodes: int = 128, max_levels: int = 16):
-    """List of fine->coarse maps, one per coarsening level."""
+def build_aggregates(adj, coarse_nodes: int = 128, max_levels: int = 16, coarse_matchings: int = 2):
+    """List of fine->coarse maps, one per coarsening level.  Each step
+    composes greedy pairwise matchings (each on the quotient graph of the
+    previous one): two on the finest level, ``coarse_matchings`` below it."""
     aggs = []
     cur = adj
     while len(cur) > coarse_nodes and len(aggs) + 1 < max_levels:
-        a1, n1 = greedy_matching(cur)
-        q1 = quotient(cur, a1, n1)
-        a2, n2 = greedy_matching(q1)
-        agg = a2[a1]
+        k = 2 if not aggs else coarse_matchings
+        agg = np.arange(len(cur))
+        g = cur
+        n2 = len(cur)
+        for m in range(k):
+            am, n2 = greedy_matching(g)
+            agg = am[agg]
+            if m + 1 < k:
+                g = quotient(g, am, n2)
         if n2 >= len(cur):
             break
         aggs.append(agg)

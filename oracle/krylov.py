@@ -219,6 +219,7 @@ class SolveOpts:
     cycles_S: int = 1        # V-cycle iterations per application of P_S
     pc: str = "scr"          # outer preconditioner: "scr" (Algorithm 3) or "simple" (Sec. 3.2)
     coarse_nodes: int = 128
+    coarse_matchings: int = 2   # greedy matchings composed per coarsening step below the finest
     max_levels: int = 16
     atol: float = 1e-50
 
@@ -230,7 +231,7 @@ class NestedSolver:
         self.S = S
         self.o = opts
         self.N = S.n_nodes
-        self.aggs = amg_mod.build_aggregates(adj, opts.coarse_nodes, opts.max_levels)
+        self.aggs = amg_mod.build_aggregates(adj, opts.coarse_nodes, opts.max_levels, opts.coarse_matchings)
         dA = S.diag_A()
         self.dA = dA
         # lumped rank-one diagonal added to F for the A-hierarchy (diag(K))

@@ -28,7 +28,7 @@ class NsMesh(C.Structure):
 
 class NsCtxOpts(C.Structure):
     _fields_ = [("max_m", C.c_int32), ("max_m_A", C.c_int32), ("max_m_S", C.c_int32),
-                ("coarse_nodes", C.c_int32), ("max_levels", C.c_int32)]
+                ("coarse_nodes", C.c_int32), ("max_levels", C.c_int32), ("coarse_matchings", C.c_int32)]
 
 
 class NsPhys(C.Structure):

@@ -200,6 +200,7 @@ struct ns_ctx {
     hipEvent_t step_ev[2] = {nullptr, nullptr};  // completion of queued Arnoldi steps
     bool use_graphs = true;
     int xcd_mode = -1;           // XCD-contiguous row ranges: -1 by size, 0 off, 1 on
+    int tail_mode = 0;           // coarse V-cycle levels in one workgroup: 1 on, 0 off
     // captured Arnoldi steps: (kind, system, precision, pc_A, degree, j) -> executable graph
     std::map<std::tuple<int, int, int, int, int, int, int>, hipGraphExec_t> graphs;
     std::vector<double> ck_host;

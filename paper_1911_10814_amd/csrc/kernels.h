@@ -42,6 +42,40 @@ struct BlockOp {
     int xcd = 0;                // 1: each XCD takes one contiguous range of rows (xcd_block)
 };
 
+// The coarse end of a V-cycle (the levels from one with at most a few
+// thousand unknowns down to the coarsest) run by one workgroup: every step of
+// those levels is latency-bound, so one launch with workgroup barriers
+// replaces a launch per step.  Level buffers as in the multi-launch cycle:
+// on entry the first level holds b, and x0 = d = its first Chebyshev step;
+// on exit its x1 holds the cycle's result.
+constexpr int kTailMaxLevels = 8;
+constexpr int kTailBlock = 1024;
+
+template <typename T>
+struct TailLevel {
+    int n = 0;
+    const int32_t* rp = nullptr;
+    const int32_t* col = nullptr;
+    const T* v = nullptr;
+    int64_t rs = 0, cs = 0;
+    const T* dextra = nullptr;
+    const T* dinv = nullptr;
+    const T* coef = nullptr;
+    T *x0 = nullptr, *x1 = nullptr, *d = nullptr, *r = nullptr, *b = nullptr;
+    const int32_t *agg = nullptr, *aptr = nullptr, *anodes = nullptr;  // to the next level
+};
+
+template <typename T>
+struct TailArgs {
+    int nl = 0;                    // levels; the last one is the coarsest
+    int deg = 2;                   // Chebyshev degree
+    const double* inv = nullptr;   // dense inverse of the coarsest level [n bs]^2
+    TailLevel<T> L[kTailMaxLevels];
+};
+
+template <typename T>
+void vcycle_tail(int bs, const TailArgs<T>& a, hipStream_t st);
+
 // lanes per row for a pattern with nnz blocks over n rows: one pass over a
 // typical row, so consecutive rows give contiguous loads across the wavefront
 inline int lanes_for(int64_t nnz, int n) {

@@ -1008,6 +1008,156 @@ void dense_gemv(int n, const double* Minv, const T* b, T* x, hipStream_t st) {
 }
 
 // ---------------------------------------------------------------------------
+// Coarse end of the V-cycle in one workgroup (see TailArgs)
+// ---------------------------------------------------------------------------
+
+// One Chebyshev step on a tail level (the row computation of k_cheb_step),
+// rows spread over the workgroup, W lanes per row.
+template <typename T, int BS, int W>
+__device__ void tail_cheb(const TailLevel<T>& L, const T* xin, T* xout, int step, const int32_t* agg,
+                          const T* ec) {
+    const int lane = threadIdx.x % W;
+    for (int row = threadIdx.x / W; row < L.n; row += kTailBlock / W) {
+        T acc[BS];
+#pragma unroll
+        for (int r = 0; r < BS; ++r) acc[r] = 0;
+        const int k1 = L.rp[row + 1];
+        for (int k = L.rp[row] + lane; k < k1; k += W) {
+            const int j = L.col[k];
+            T xj[BS];
+#pragma unroll
+            for (int c = 0; c < BS; ++c) xj[c] = xin[(int64_t)BS * j + c] + (agg ? ec[BS * agg[j] + c] : T(0));
+#pragma unroll
+            for (int r = 0; r < BS; ++r)
+#pragma unroll
+                for (int c = 0; c < BS; ++c) acc[r] += L.v[r * L.rs + c * L.cs + k] * xj[c];
+        }
+#pragma unroll
+        for (int off = W / 2; off > 0; off >>= 1)
+#pragma unroll
+            for (int r = 0; r < BS; ++r) acc[r] += __shfl_xor(acc[r], off, W);
+        if (lane < BS) {
+            T s = acc[0];
+#pragma unroll
+            for (int r = 1; r < BS; ++r)
+                if (lane == r) s = acc[r];
+            const int64_t i = (int64_t)BS * row + lane;
+            T xi = xin[i];
+            if (agg) xi += ec[(int64_t)BS * agg[row] + lane];
+            if (L.dextra) s += L.dextra[i] * xi;
+            T c1, c2;
+            cheb_coef(L.coef, step, c1, c2);
+            T di = c2 * L.dinv[i] * (L.b[i] - s);
+            if (step != 0) di += c1 * L.d[i];
+            L.d[i] = di;
+            xout[i] = xi + di;
+        }
+    }
+}
+
+// r = b - M x on a tail level
+template <typename T, int BS, int W>
+__device__ void tail_resid(const TailLevel<T>& L, const T* x) {
+    const int lane = threadIdx.x % W;
+    for (int row = threadIdx.x / W; row < L.n; row += kTailBlock / W) {
+        T acc[BS];
+#pragma unroll
+        for (int r = 0; r < BS; ++r) acc[r] = 0;
+        const int k1 = L.rp[row + 1];
+        for (int k = L.rp[row] + lane; k < k1; k += W) {
+            const int j = L.col[k];
+#pragma unroll
+            for (int r = 0; r < BS; ++r)
+#pragma unroll
+                for (int c = 0; c < BS; ++c) acc[r] += L.v[r * L.rs + c * L.cs + k] * x[(int64_t)BS * j + c];
+        }
+#pragma unroll
+        for (int off = W / 2; off > 0; off >>= 1)
+#pragma unroll
+            for (int r = 0; r < BS; ++r) acc[r] += __shfl_xor(acc[r], off, W);
+        if (lane < BS) {
+            T s = acc[0];
+#pragma unroll
+            for (int r = 1; r < BS; ++r)
+                if (lane == r) s = acc[r];
+            const int64_t i = (int64_t)BS * row + lane;
+            if (L.dextra) s += L.dextra[i] * x[i];
+            L.r[i] = L.b[i] - s;
+        }
+    }
+}
+
+// C.b = P^T F.r; unless C is the coarsest level also its first Chebyshev step
+template <typename T, int BS>
+__device__ void tail_restrict(const TailLevel<T>& F, const TailLevel<T>& C, bool first) {
+    for (int t = threadIdx.x; t < C.n * BS; t += kTailBlock) {
+        const int I = t / BS, c = t % BS;
+        T s = 0;
+        for (int q = F.aptr[I]; q < F.aptr[I + 1]; ++q) s += F.r[(int64_t)BS * F.anodes[q] + c];
+        C.b[t] = s;
+        if (first) {
+            const T di = C.coef[0] * C.dinv[t] * s;
+            C.x0[t] = di;
+            C.d[t] = di;
+        }
+    }
+}
+
+template <typename T, int BS>
+__global__ __launch_bounds__(kTailBlock) void k_vcycle_tail(TailArgs<T> A) {
+    const int last = A.nl - 1;
+    for (int l = 0; l < last; ++l) {
+        const TailLevel<T>& L = A.L[l];
+        T* a = L.x0;
+        T* bb = L.x1;
+        for (int s = 1; s < A.deg; ++s) {
+            tail_cheb<T, BS, 16>(L, a, bb, s, nullptr, nullptr);
+            __syncthreads();
+            T* t = a;
+            a = bb;
+            bb = t;
+        }
+        tail_resid<T, BS, 16>(L, a);
+        __syncthreads();
+        tail_restrict<T, BS>(L, A.L[l + 1], l + 1 < last);
+        __syncthreads();
+    }
+    {
+        // coarsest: x1 = inv b, one wavefront per row
+        const TailLevel<T>& C = A.L[last];
+        const int n = C.n * BS;
+        const int w = threadIdx.x >> 6, ln = threadIdx.x & 63;
+        for (int row = w; row < n; row += kTailBlock / 64) {
+            double s = 0.0;
+            for (int c = ln; c < n; c += 64) s += A.inv[(int64_t)row * n + c] * (double)C.b[c];
+            s = wave_sum(s);
+            if (ln == 0) C.x1[row] = (T)s;
+        }
+        __syncthreads();
+    }
+    for (int l = last - 1; l >= 0; --l) {
+        const TailLevel<T>& L = A.L[l];
+        T* a = ((A.deg - 1) % 2 == 0) ? L.x0 : L.x1;   // where pre-smoothing left the iterate
+        T* bb = a == L.x0 ? L.x1 : L.x0;
+        for (int s = 0; s < A.deg; ++s) {
+            tail_cheb<T, BS, 16>(L, a, bb, s, s == 0 ? L.agg : nullptr, s == 0 ? A.L[l + 1].x1 : nullptr);
+            __syncthreads();
+            T* t = a;
+            a = bb;
+            bb = t;
+        }
+    }
+}
+
+template <typename T>
+void vcycle_tail(int bs, const TailArgs<T>& a, hipStream_t st) {
+    if (bs == 3)
+        hipLaunchKernelGGL((k_vcycle_tail<T, 3>), dim3(1), dim3(kTailBlock), 0, st, a);
+    else
+        hipLaunchKernelGGL((k_vcycle_tail<T, 1>), dim3(1), dim3(kTailBlock), 0, st, a);
+}
+
+// ---------------------------------------------------------------------------
 // Set-up numerics (FP64)
 // ---------------------------------------------------------------------------
 
@@ -1369,7 +1519,8 @@ void newton_update(int64_t n, double gdt, const double* dx, double* y, double* y
     template void resid_restrict<T>(int, const BlockOp<T>&, const T*, const T*, int, const int32_t*, const int32_t*, \
                                     T*, T*, T*, const T*, const T*, hipStream_t);                                    \
     template void prolong_add<T>(int, int, const int32_t*, const T*, T*, hipStream_t);                               \
-    template void dense_gemv<T>(int, const double*, const T*, T*, hipStream_t);
+    template void dense_gemv<T>(int, const double*, const T*, T*, hipStream_t);                                      \
+    template void vcycle_tail<T>(int, const TailArgs<T>&, hipStream_t);
 
 NS_INST(double)
 NS_INST(float)

@@ -300,10 +300,12 @@ std::string build_symbolic(const ns_mesh* m, const ns_ctx_opts& o, Symbolic& S) 
         S.shat.col.swap(col);
     }
 
-    // AMG hierarchy: levels of node aggregates (two greedy matchings each)
+    // AMG hierarchy: levels of node aggregates (composed greedy matchings)
     {
         const int coarse_nodes = o.coarse_nodes > 0 ? o.coarse_nodes : 128;
         const int max_levels = o.max_levels > 0 ? o.max_levels : 16;
+        const int coarse_matchings = o.coarse_matchings > 0 ? o.coarse_matchings : 2;
+        if (coarse_matchings < 2 || coarse_matchings > 4) return "coarse_matchings must be in [2, 4]";
         S.lv.clear();
         S.lv.emplace_back();
         S.lv[0].n = N;
@@ -311,13 +313,21 @@ std::string build_symbolic(const ns_mesh* m, const ns_ctx_opts& o, Symbolic& S) 
         S.lv[0].s = S.shat;
         while (S.lv.back().n > coarse_nodes && (int)S.lv.size() < max_levels) {
             AmgLevelSym& f = S.lv.back();
-            int n1 = 0, n2 = 0;
-            std::vector<int32_t> a1 = greedy_matching(f.a, n1);
-            Csr q1 = quotient(f.a, a1, n1);
-            std::vector<int32_t> a2 = greedy_matching(q1, n2);
+            // compose k greedy matchings: node -> pair -> ... -> aggregate
+            const int k = S.lv.size() == 1 ? 2 : coarse_matchings;
+            std::vector<int32_t> agg(f.n);
+            for (int i = 0; i < f.n; ++i) agg[i] = i;
+            Csr cur = f.a;
+            int n2 = f.n;
+            for (int m = 0; m < k; ++m) {
+                int nm = 0;
+                std::vector<int32_t> am = greedy_matching(cur, nm);
+                for (int i = 0; i < f.n; ++i) agg[i] = am[agg[i]];
+                if (m + 1 < k) cur = quotient(cur, am, nm);
+                n2 = nm;
+            }
             if (n2 >= f.n) break;
-            f.agg.resize(f.n);
-            for (int i = 0; i < f.n; ++i) f.agg[i] = a2[a1[i]];
+            f.agg.swap(agg);
             f.aptr.assign(n2 + 1, 0);
             for (int i = 0; i < f.n; ++i) f.aptr[f.agg[i] + 1]++;
             for (int c = 0; c < n2; ++c) f.aptr[c + 1] += f.aptr[c];

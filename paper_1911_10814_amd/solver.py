@@ -78,7 +78,7 @@ class NsContext:
     mask, outlet_ptr, faces; n_nodes, n_elems, n_outlets)."""
 
     def __init__(self, case, *, max_m=200, max_m_A=200, max_m_S=200, coarse_nodes=128, max_levels=16,
-                 device="cuda:0"):
+                 coarse_matchings=2, device="cuda:0"):
         self.lib = _lib.load()
         self.device = torch.device(device)
         self.N = int(case.n_nodes)
@@ -92,7 +92,7 @@ class NsContext:
                            self._tets.ctypes.data_as(_lib.PI), self._optr.ctypes.data_as(_lib.PI),
                            self._faces.ctypes.data_as(_lib.PI),
                            self._mask.ctypes.data_as(C.POINTER(C.c_uint8)))
-        opts = _lib.NsCtxOpts(max_m, max_m_A, max_m_S, coarse_nodes, max_levels)
+        opts = _lib.NsCtxOpts(max_m, max_m_A, max_m_S, coarse_nodes, max_levels, coarse_matchings)
         handle = C.c_void_p()
         nbytes = C.c_size_t()
         st = self.lib.ns_ctx_create(C.byref(mesh), C.byref(opts), C.byref(handle), C.byref(nbytes))

@@ -51,6 +51,14 @@ def test_symbolic_setup_matches_oracle(name):
     for k in range(colors.max() + 1):
         t = c.tets[colors == k]
         assert len(np.unique(t)) == t.size  # no shared node inside a colour
+    # deeper aggregation below the finest level (three or four composed matchings)
+    for cm in (3, 4):
+        ctx_cm = NsContext(c, coarse_matchings=cm)
+        aggs = amg.build_aggregates(adj, coarse_matchings=cm)
+        assert ctx_cm.sizes[5] == len(aggs) + 1
+        for lev, a in enumerate(aggs):
+            assert np.array_equal(ctx_cm.aggregates(lev), a)
+            assert np.bincount(a).max() <= (2 if lev == 0 else 2 ** (cm - 1)) * 2
 
 
 def test_invalid_mesh_is_rejected():
