@@ -89,7 +89,7 @@ typedef struct {
     int32_t coarse_matchings; /* greedy pairwise matchings composed per
                            * coarsening step below the finest level, 2..4
                            * (aggregates of at most 2^k nodes); the finest
-                           * step always uses two              [2]   */
+                           * step always uses two              [3]   */
 } ns_ctx_opts;
 
 /* Physics of one Newton step (Sec. 2.3, 2.4.1, 2.5).

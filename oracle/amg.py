@@ -8,11 +8,14 @@ package choice is prior art here; this module follows the repository's own
 written definition, which the GPU library implements independently:
 
 * node graph: i ~ j when i and j share a tetrahedron edge;
-* one coarsening level = two greedy pairwise matchings: visit nodes in
+* one coarsening level = composed greedy pairwise matchings: visit nodes in
   ascending order; an unmatched node is paired with its first (lowest index)
   unmatched neighbour, or left single; coarse ids are handed out in the order
-  the pairs/singles are created; the second matching runs on the quotient
-  graph of the first; levels are added while the level has more than
+  the pairs/singles are created; each further matching runs on the quotient
+  graph of the previous one; two matchings from the finest level, three
+  (``coarse_matchings``) on every coarser one (aggregates of at most 4, then
+  8 nodes: fewer levels, each a latency-bound launch on the GPU, at the same
+  or lower iteration counts); levels are added while the level has more than
   ``coarse_nodes`` nodes (and coarsening still reduces the count), up to
   ``max_levels`` levels;
 * unsmoothed (piecewise-constant) prolongation, nodal for A (3x3 blocks, the
@@ -74,7 +77,7 @@ def quotient(adj, agg, nc):
     return [np.array(sorted(s), dtype=np.int64) for s in sets]
 
 
-def build_aggregates(adj, coarse_nodes: int = 128, max_levels: int = 16, coarse_matchings: int = 2):
+def build_aggregates(adj, coarse_nodes: int = 128, max_levels: int = 16, coarse_matchings: int = 3):
     """List of fine->coarse maps, one per coarsening level.  Each step
     composes greedy pairwise matchings (each on the quotient graph of the
     previous one): two on the finest level, ``coarse_matchings`` below it."""

@@ -219,7 +219,7 @@ class SolveOpts:
     cycles_S: int = 1        # V-cycle iterations per application of P_S
     pc: str = "scr"          # outer preconditioner: "scr" (Algorithm 3) or "simple" (Sec. 3.2)
     coarse_nodes: int = 128
-    coarse_matchings: int = 2   # greedy matchings composed per coarsening step below the finest
+    coarse_matchings: int = 3   # greedy matchings composed per coarsening step below the finest
     max_levels: int = 16
     atol: float = 1e-50
 

@@ -195,7 +195,7 @@ void layout(ns_ctx* c, Arena& A) {
                 }
                 if (l == L - 1) {
                     d.inv = A.take<double>((size_t)nv * nv);
-                    d.work = A.take<double>((size_t)nv * 2 * nv);
+                    d.work = A.take<double>((size_t)nv * 4 * nv);  // two halves of [M | I]
                 } else {
                     d.coef64 = A.take<double>(kCoefLen);
                     d.coef32 = A.take<float>(kCoefLen);
@@ -352,8 +352,6 @@ void read_status(ns_ctx* c, const double* d_status, int n, hipStream_t st) {
 // host-mapped scalar slots written by kernels: [0..1] Arnoldi status, [8] norms
 // [9 + kind] initial residual norm of a left GMRES call of that kind
 constexpr int kMapStatus = 0, kMapNorm = 8, kMapNorm0 = 9;
-// size limits of the first level of a single-workgroup V-cycle tail
-constexpr int kTailNodes3 = 1024, kTailNodes1 = 4096;
 // graph kinds of Arnoldi steps (one mapped initial-norm slot each)
 constexpr int kKindA = 0, kKindS = 1, kKindOuter = 2, kKindShat = 3;
 
@@ -636,47 +634,6 @@ struct Nested {
     // One V-cycle on level l for right-hand side b, result in xout.  On levels
     // l > 0 the caller has already done the first pre-smoothing step
     // (x = d = dinv b / theta into L.x0, L.d) inside the restriction kernel.
-    // First level of H whose cycle runs in one workgroup (vcycle_tail), or -1:
-    // a level below the finest, not the coarsest, small enough that its steps
-    // are latency-bound (at most kTailNodes3 nodes of 3x3 blocks or kTailNodes1
-    // scalar nodes), with at most kTailMaxLevels levels from it down.
-    int tail_level(const std::vector<AmgLevelDev>& H) const {
-        if (!c->tail_mode) return -1;
-        const int nl = (int)H.size();
-        for (int l = 1; l + 1 < nl; ++l) {
-            const int cap = H[l].bs == 3 ? kTailNodes3 : kTailNodes1;
-            if (H[l].n <= cap) return nl - l <= kTailMaxLevels ? l : -1;
-        }
-        return -1;
-    }
-    void run_tail(std::vector<AmgLevelDev>& H, int l, int deg) {
-        TailArgs<T> A;
-        A.nl = (int)H.size() - l;
-        A.deg = deg;
-        A.inv = H.back().inv;
-        for (int i = 0; i < A.nl; ++i) {
-            const AmgLevelDev& d = H[l + i];
-            TailLevel<T>& t = A.L[i];
-            t.n = d.n;
-            t.rp = d.rp;
-            t.col = d.col;
-            t.v = Typed<T>::lv(d);
-            t.rs = d.rstride;
-            t.cs = d.cstride;
-            t.dextra = Typed<T>::dextra(d);
-            t.dinv = Typed<T>::dinv(d);
-            t.coef = Typed<T>::coef(d);
-            t.x0 = as<T>(d.x0);
-            t.x1 = as<T>(d.x1);
-            t.d = as<T>(d.d);
-            t.r = as<T>(d.r);
-            t.b = as<T>(d.b);
-            t.agg = d.agg;
-            t.aptr = d.aptr;
-            t.anodes = d.anodes;
-        }
-        vcycle_tail<T>(H[l].bs, A, K.st);
-    }
     void vcycle(std::vector<AmgLevelDev>& H, int l, const T* b, T* xout, bool first_done = false) {
         AmgLevelDev& L = H[l];
         const int bs = L.bs;
@@ -687,12 +644,6 @@ struct Nested {
             return;
         }
         const int deg = dflt(K.o.cheb_degree, kDefaultChebDegree);
-        // below the finest level the cycle is always entered with b in L.b,
-        // xout = L.x1 and the first pre-smoothing step done by the parent
-        if (l >= 1 && l == tail_level(H) && b == as<T>(L.b) && xout == as<T>(L.x1)) {
-            run_tail(H, l, deg);
-            return;
-        }
         const BlockOp<T> M = level_op(L);
         const T* dinv = Typed<T>::dinv(L);
         const T* coef = Typed<T>::coef(L);
@@ -1322,8 +1273,6 @@ ns_status ns_ctx_bind(ns_ctx* c, void* ws, size_t bytes, hipStream_t st) {
         c->use_graphs = !(ng && ng[0] == '1');
         const char* xr = getenv("NS_XCD_ROWS");
         c->xcd_mode = (xr && (xr[0] == '0' || xr[0] == '1')) ? xr[0] - '0' : -1;
-        const char* tl = getenv("NS_VCYCLE_TAIL");
-        c->tail_mode = (tl && tl[0] == '1') ? 1 : 0;
         HIPCHK(hipStreamSynchronize(st));
         c->bound = true;
         return NS_OK;

@@ -108,7 +108,8 @@ struct AmgLevelDev {
     int32_t *agg = nullptr, *aptr = nullptr, *anodes = nullptr;
     // work vectors (sized for FP64, reused for FP32): x0, x1, d, r, b
     double *x0 = nullptr, *x1 = nullptr, *d = nullptr, *r = nullptr, *b = nullptr;
-    // coarsest level: dense inverse [n*bs][n*bs] FP64 and its work matrix
+    // coarsest level: dense inverse [n*bs][n*bs] FP64 and its work matrices
+    // (two halves of [M | I], [2][n*bs][2*n*bs])
     double* inv = nullptr;
     double* work = nullptr;
 };
@@ -200,7 +201,6 @@ struct ns_ctx {
     hipEvent_t step_ev[2] = {nullptr, nullptr};  // completion of queued Arnoldi steps
     bool use_graphs = true;
     int xcd_mode = -1;           // XCD-contiguous row ranges: -1 by size, 0 off, 1 on
-    int tail_mode = 0;           // coarse V-cycle levels in one workgroup: 1 on, 0 off
     // captured Arnoldi steps: (kind, system, precision, pc_A, degree, j) -> executable graph
     std::map<std::tuple<int, int, int, int, int, int, int>, hipGraphExec_t> graphs;
     std::vector<double> ck_host;

@@ -42,40 +42,6 @@ struct BlockOp {
     int xcd = 0;                // 1: each XCD takes one contiguous range of rows (xcd_block)
 };
 
-// The coarse end of a V-cycle (the levels from one with at most a few
-// thousand unknowns down to the coarsest) run by one workgroup: every step of
-// those levels is latency-bound, so one launch with workgroup barriers
-// replaces a launch per step.  Level buffers as in the multi-launch cycle:
-// on entry the first level holds b, and x0 = d = its first Chebyshev step;
-// on exit its x1 holds the cycle's result.
-constexpr int kTailMaxLevels = 8;
-constexpr int kTailBlock = 1024;
-
-template <typename T>
-struct TailLevel {
-    int n = 0;
-    const int32_t* rp = nullptr;
-    const int32_t* col = nullptr;
-    const T* v = nullptr;
-    int64_t rs = 0, cs = 0;
-    const T* dextra = nullptr;
-    const T* dinv = nullptr;
-    const T* coef = nullptr;
-    T *x0 = nullptr, *x1 = nullptr, *d = nullptr, *r = nullptr, *b = nullptr;
-    const int32_t *agg = nullptr, *aptr = nullptr, *anodes = nullptr;  // to the next level
-};
-
-template <typename T>
-struct TailArgs {
-    int nl = 0;                    // levels; the last one is the coarsest
-    int deg = 2;                   // Chebyshev degree
-    const double* inv = nullptr;   // dense inverse of the coarsest level [n bs]^2
-    TailLevel<T> L[kTailMaxLevels];
-};
-
-template <typename T>
-void vcycle_tail(int bs, const TailArgs<T>& a, hipStream_t st);
-
 // lanes per row for a pattern with nnz blocks over n rows: one pass over a
 // typical row, so consecutive rows give contiguous loads across the wavefront
 inline int lanes_for(int64_t nnz, int n) {
@@ -181,8 +147,9 @@ void block_dinv(int n, int bs, const int32_t* rp, const int32_t* col, const doub
 void shat_numeric(int n, const int32_t* rp, const int32_t* col, const double* V, int64_t nnzb,
                   const double* dinvA, const int32_t* srp, const int32_t* scol, double* shat, hipStream_t st);
 // inv_i = (left half of work_i)^{-1} by Gauss-Jordan with partial pivoting on
-// work_i [n_i][2 n_i] (right half: identity, overwritten) for two independent
-// matrices in one launch, one workgroup each
+// [M_i | I] for two independent matrices, one launch per pivot step for both;
+// work_i holds [2][n_i][2 n_i]: the input [M_i | I] in the first half, the
+// second half is the ping-pong buffer (both overwritten)
 void gauss_jordan_inverse2(int n0, double* work0, double* inv0, int n1, double* work1, double* inv1,
                            hipStream_t st);
 void dense_from_csr(int nb, int bs, const int32_t* rp, const int32_t* col, const double* v, int64_t rs,

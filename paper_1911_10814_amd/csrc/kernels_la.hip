@@ -1008,156 +1008,6 @@ void dense_gemv(int n, const double* Minv, const T* b, T* x, hipStream_t st) {
 }
 
 // ---------------------------------------------------------------------------
-// Coarse end of the V-cycle in one workgroup (see TailArgs)
-// ---------------------------------------------------------------------------
-
-// One Chebyshev step on a tail level (the row computation of k_cheb_step),
-// rows spread over the workgroup, W lanes per row.
-template <typename T, int BS, int W>
-__device__ void tail_cheb(const TailLevel<T>& L, const T* xin, T* xout, int step, const int32_t* agg,
-                          const T* ec) {
-    const int lane = threadIdx.x % W;
-    for (int row = threadIdx.x / W; row < L.n; row += kTailBlock / W) {
-        T acc[BS];
-#pragma unroll
-        for (int r = 0; r < BS; ++r) acc[r] = 0;
-        const int k1 = L.rp[row + 1];
-        for (int k = L.rp[row] + lane; k < k1; k += W) {
-            const int j = L.col[k];
-            T xj[BS];
-#pragma unroll
-            for (int c = 0; c < BS; ++c) xj[c] = xin[(int64_t)BS * j + c] + (agg ? ec[BS * agg[j] + c] : T(0));
-#pragma unroll
-            for (int r = 0; r < BS; ++r)
-#pragma unroll
-                for (int c = 0; c < BS; ++c) acc[r] += L.v[r * L.rs + c * L.cs + k] * xj[c];
-        }
-#pragma unroll
-        for (int off = W / 2; off > 0; off >>= 1)
-#pragma unroll
-            for (int r = 0; r < BS; ++r) acc[r] += __shfl_xor(acc[r], off, W);
-        if (lane < BS) {
-            T s = acc[0];
-#pragma unroll
-            for (int r = 1; r < BS; ++r)
-                if (lane == r) s = acc[r];
-            const int64_t i = (int64_t)BS * row + lane;
-            T xi = xin[i];
-            if (agg) xi += ec[(int64_t)BS * agg[row] + lane];
-            if (L.dextra) s += L.dextra[i] * xi;
-            T c1, c2;
-            cheb_coef(L.coef, step, c1, c2);
-            T di = c2 * L.dinv[i] * (L.b[i] - s);
-            if (step != 0) di += c1 * L.d[i];
-            L.d[i] = di;
-            xout[i] = xi + di;
-        }
-    }
-}
-
-// r = b - M x on a tail level
-template <typename T, int BS, int W>
-__device__ void tail_resid(const TailLevel<T>& L, const T* x) {
-    const int lane = threadIdx.x % W;
-    for (int row = threadIdx.x / W; row < L.n; row += kTailBlock / W) {
-        T acc[BS];
-#pragma unroll
-        for (int r = 0; r < BS; ++r) acc[r] = 0;
-        const int k1 = L.rp[row + 1];
-        for (int k = L.rp[row] + lane; k < k1; k += W) {
-            const int j = L.col[k];
-#pragma unroll
-            for (int r = 0; r < BS; ++r)
-#pragma unroll
-                for (int c = 0; c < BS; ++c) acc[r] += L.v[r * L.rs + c * L.cs + k] * x[(int64_t)BS * j + c];
-        }
-#pragma unroll
-        for (int off = W / 2; off > 0; off >>= 1)
-#pragma unroll
-            for (int r = 0; r < BS; ++r) acc[r] += __shfl_xor(acc[r], off, W);
-        if (lane < BS) {
-            T s = acc[0];
-#pragma unroll
-            for (int r = 1; r < BS; ++r)
-                if (lane == r) s = acc[r];
-            const int64_t i = (int64_t)BS * row + lane;
-            if (L.dextra) s += L.dextra[i] * x[i];
-            L.r[i] = L.b[i] - s;
-        }
-    }
-}
-
-// C.b = P^T F.r; unless C is the coarsest level also its first Chebyshev step
-template <typename T, int BS>
-__device__ void tail_restrict(const TailLevel<T>& F, const TailLevel<T>& C, bool first) {
-    for (int t = threadIdx.x; t < C.n * BS; t += kTailBlock) {
-        const int I = t / BS, c = t % BS;
-        T s = 0;
-        for (int q = F.aptr[I]; q < F.aptr[I + 1]; ++q) s += F.r[(int64_t)BS * F.anodes[q] + c];
-        C.b[t] = s;
-        if (first) {
-            const T di = C.coef[0] * C.dinv[t] * s;
-            C.x0[t] = di;
-            C.d[t] = di;
-        }
-    }
-}
-
-template <typename T, int BS>
-__global__ __launch_bounds__(kTailBlock) void k_vcycle_tail(TailArgs<T> A) {
-    const int last = A.nl - 1;
-    for (int l = 0; l < last; ++l) {
-        const TailLevel<T>& L = A.L[l];
-        T* a = L.x0;
-        T* bb = L.x1;
-        for (int s = 1; s < A.deg; ++s) {
-            tail_cheb<T, BS, 16>(L, a, bb, s, nullptr, nullptr);
-            __syncthreads();
-            T* t = a;
-            a = bb;
-            bb = t;
-        }
-        tail_resid<T, BS, 16>(L, a);
-        __syncthreads();
-        tail_restrict<T, BS>(L, A.L[l + 1], l + 1 < last);
-        __syncthreads();
-    }
-    {
-        // coarsest: x1 = inv b, one wavefront per row
-        const TailLevel<T>& C = A.L[last];
-        const int n = C.n * BS;
-        const int w = threadIdx.x >> 6, ln = threadIdx.x & 63;
-        for (int row = w; row < n; row += kTailBlock / 64) {
-            double s = 0.0;
-            for (int c = ln; c < n; c += 64) s += A.inv[(int64_t)row * n + c] * (double)C.b[c];
-            s = wave_sum(s);
-            if (ln == 0) C.x1[row] = (T)s;
-        }
-        __syncthreads();
-    }
-    for (int l = last - 1; l >= 0; --l) {
-        const TailLevel<T>& L = A.L[l];
-        T* a = ((A.deg - 1) % 2 == 0) ? L.x0 : L.x1;   // where pre-smoothing left the iterate
-        T* bb = a == L.x0 ? L.x1 : L.x0;
-        for (int s = 0; s < A.deg; ++s) {
-            tail_cheb<T, BS, 16>(L, a, bb, s, s == 0 ? L.agg : nullptr, s == 0 ? A.L[l + 1].x1 : nullptr);
-            __syncthreads();
-            T* t = a;
-            a = bb;
-            bb = t;
-        }
-    }
-}
-
-template <typename T>
-void vcycle_tail(int bs, const TailArgs<T>& a, hipStream_t st) {
-    if (bs == 3)
-        hipLaunchKernelGGL((k_vcycle_tail<T, 3>), dim3(1), dim3(kTailBlock), 0, st, a);
-    else
-        hipLaunchKernelGGL((k_vcycle_tail<T, 1>), dim3(1), dim3(kTailBlock), 0, st, a);
-}
-
-// ---------------------------------------------------------------------------
 // Set-up numerics (FP64)
 // ---------------------------------------------------------------------------
 
@@ -1269,82 +1119,107 @@ void dense_from_csr(int nb, int bs, const int32_t* rp, const int32_t* col, const
                        dextra, work);
 }
 
-// Gauss-Jordan with partial pivoting on work [n][2n], one workgroup of 1024
-// per matrix (blockIdx.x selects one of up to two independent matrices).
-struct GjBatch {
+// Gauss-Jordan with partial pivoting on [M | I] (n x 2n), one launch per
+// pivot step spread over many workgroups (one wavefront per row): each step
+// reads the rows from one half of the work buffer and writes them to the
+// other, so no workgroup overwrites a row that another still reads.  Two
+// independent matrices share every launch (the coarsest levels of both
+// hierarchies).  work: [2][n][2n], the input in the first half.
+constexpr int kGjRows = kBlock / 64;
+
+struct GjStep {
     int n[2];
-    double* work[2];
-    double* inv[2];
+    const double* src[2];
+    double* dst[2];
+    int blocks0;   // workgroups of matrix 0; the rest belong to matrix 1
 };
-__global__ __launch_bounds__(1024) void k_gauss_jordan(GjBatch bt) {
-    const int n = bt.n[blockIdx.x];
-    double* work = bt.work[blockIdx.x];
-    double* inv = bt.inv[blockIdx.x];
-    __shared__ double sval[1024];
-    __shared__ int sidx[1024];
-    __shared__ int piv;
-    const int n2 = 2 * n;
-    for (int k = 0; k < n; ++k) {
-        double best = -1.0;
-        int bi = k;
-        for (int r = k + threadIdx.x; r < n; r += 1024) {
-            const double a = fabs(work[(int64_t)r * n2 + k]);
-            if (a > best) {
-                best = a;
-                bi = r;
-            }
-        }
-        sval[threadIdx.x] = best;
-        sidx[threadIdx.x] = bi;
-        __syncthreads();
-        for (int s = 512; s > 0; s >>= 1) {
-            if ((int)threadIdx.x < s) {
-                const double o = sval[threadIdx.x + s];
-                const int oi = sidx[threadIdx.x + s];
-                if (o > sval[threadIdx.x] || (o == sval[threadIdx.x] && oi < sidx[threadIdx.x])) {
-                    sval[threadIdx.x] = o;
-                    sidx[threadIdx.x] = oi;
-                }
-            }
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) piv = sidx[0];
-        __syncthreads();
-        const int p = piv;
-        if (p != k)
-            for (int c = threadIdx.x; c < n2; c += 1024) {
-                const double t = work[(int64_t)k * n2 + c];
-                work[(int64_t)k * n2 + c] = work[(int64_t)p * n2 + c];
-                work[(int64_t)p * n2 + c] = t;
-            }
-        __syncthreads();
-        const double inv_p = 1.0 / work[(int64_t)k * n2 + k];
-        __syncthreads();
-        for (int c = threadIdx.x; c < n2; c += 1024) work[(int64_t)k * n2 + c] *= inv_p;
-        __syncthreads();
-        // eliminate column k from all other rows, 1024 rows at a time (factors first)
-        for (int r0 = 0; r0 < n; r0 += 1024) {
-            const int r = r0 + threadIdx.x;
-            double f = 0.0;
-            if (r < n && r != k) f = work[(int64_t)r * n2 + k];
-            __syncthreads();
-            sval[threadIdx.x] = f;
-            __syncthreads();
-            const int rows = min(1024, n - r0);
-            for (int e = threadIdx.x; e < rows * n2; e += 1024) {
-                const int rr = e / n2, c = e % n2;
-                const double fr = sval[rr];
-                if (fr != 0.0) work[(int64_t)(r0 + rr) * n2 + c] -= fr * work[(int64_t)k * n2 + c];
-            }
-            __syncthreads();
+
+__global__ __launch_bounds__(kBlock) void k_gj_step(GjStep a, int k) {
+    const int m = (int)blockIdx.x < a.blocks0 ? 0 : 1;
+    const int n = a.n[m];
+    const int b = m == 0 ? (int)blockIdx.x : (int)blockIdx.x - a.blocks0;
+    const double* src = a.src[m];
+    double* dst = a.dst[m];
+    const int64_t n2 = 2 * (int64_t)n;
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int r = b * kGjRows + w;
+    if (k >= n) {  // this matrix is finished: carry its rows over
+        if (r < n)
+            for (int64_t c = l; c < n2; c += 64) dst[r * n2 + c] = src[r * n2 + c];
+        return;
+    }
+    // pivot: the largest |M_rk| over r >= k, the smallest row on ties
+    __shared__ double sval[kBlock];
+    __shared__ int sidx[kBlock];
+    double best = -1.0;
+    int bi = k;
+    for (int q = k + (int)threadIdx.x; q < n; q += kBlock) {
+        const double v = fabs(src[q * n2 + k]);
+        if (v > best) {
+            best = v;
+            bi = q;
         }
     }
-    for (int e = threadIdx.x; e < n * n; e += 1024) inv[e] = work[(int64_t)(e / n) * n2 + n + e % n];
+    sval[threadIdx.x] = best;
+    sidx[threadIdx.x] = bi;
+    __syncthreads();
+    for (int s = kBlock / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            const double o = sval[threadIdx.x + s];
+            const int oi = sidx[threadIdx.x + s];
+            if (o > sval[threadIdx.x] || (o == sval[threadIdx.x] && oi < sidx[threadIdx.x])) {
+                sval[threadIdx.x] = o;
+                sidx[threadIdx.x] = oi;
+            }
+        }
+        __syncthreads();
+    }
+    const int p = sidx[0];
+    if (r >= n) return;
+    const double inv_p = 1.0 / src[p * n2 + k];
+    const double* prow = src + p * n2;
+    double* drow = dst + r * n2;
+    if (r == k) {
+        for (int64_t c = l; c < n2; c += 64) drow[c] = prow[c] * inv_p;
+    } else {
+        // after exchanging rows k and p, row r holds the old row sr
+        const double* srow = src + (r == p ? k : r) * n2;
+        const double f = srow[k];
+        for (int64_t c = l; c < n2; c += 64) drow[c] = srow[c] - f * (prow[c] * inv_p);
+    }
 }
+
+__global__ void k_gj_extract(int n0, const double* w0, double* inv0, int n1, const double* w1, double* inv1) {
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t s0 = (int64_t)n0 * n0;
+    if (t < s0) {
+        inv0[t] = w0[(t / n0) * 2 * n0 + n0 + t % n0];
+    } else if (t < s0 + (int64_t)n1 * n1) {
+        const int64_t u = t - s0;
+        inv1[u] = w1[(u / n1) * 2 * n1 + n1 + u % n1];
+    }
+}
+
 void gauss_jordan_inverse2(int n0, double* work0, double* inv0, int n1, double* work1, double* inv1,
                            hipStream_t st) {
-    GjBatch b{{n0, n1}, {work0, work1}, {inv0, inv1}};
-    hipLaunchKernelGGL(k_gauss_jordan, dim3(2), dim3(1024), 0, st, b);
+    const int steps = std::max(n0, n1);
+    GjStep a;
+    a.n[0] = n0;
+    a.n[1] = n1;
+    a.blocks0 = (n0 + kGjRows - 1) / kGjRows;
+    const int blocks = a.blocks0 + (n1 + kGjRows - 1) / kGjRows;
+    double* half0[2] = {work0, work0 + 2 * (int64_t)n0 * n0};
+    double* half1[2] = {work1, work1 + 2 * (int64_t)n1 * n1};
+    for (int k = 0; k < steps; ++k) {
+        a.src[0] = half0[k & 1];
+        a.dst[0] = half0[(k + 1) & 1];
+        a.src[1] = half1[k & 1];
+        a.dst[1] = half1[(k + 1) & 1];
+        hipLaunchKernelGGL(k_gj_step, dim3(blocks), dim3(kBlock), 0, st, a, k);
+    }
+    const int64_t tot = (int64_t)n0 * n0 + (int64_t)n1 * n1;
+    hipLaunchKernelGGL(k_gj_extract, dim3(grid_for(tot)), dim3(kBlock), 0, st, n0, half0[steps & 1], inv0, n1,
+                       half1[steps & 1], inv1);
 }
 
 __global__ void k_power_start(int64_t n, double* x) {
@@ -1519,8 +1394,7 @@ void newton_update(int64_t n, double gdt, const double* dx, double* y, double* y
     template void resid_restrict<T>(int, const BlockOp<T>&, const T*, const T*, int, const int32_t*, const int32_t*, \
                                     T*, T*, T*, const T*, const T*, hipStream_t);                                    \
     template void prolong_add<T>(int, int, const int32_t*, const T*, T*, hipStream_t);                               \
-    template void dense_gemv<T>(int, const double*, const T*, T*, hipStream_t);                                      \
-    template void vcycle_tail<T>(int, const TailArgs<T>&, hipStream_t);
+    template void dense_gemv<T>(int, const double*, const T*, T*, hipStream_t);
 
 NS_INST(double)
 NS_INST(float)

@@ -304,7 +304,7 @@ std::string build_symbolic(const ns_mesh* m, const ns_ctx_opts& o, Symbolic& S) 
     {
         const int coarse_nodes = o.coarse_nodes > 0 ? o.coarse_nodes : 128;
         const int max_levels = o.max_levels > 0 ? o.max_levels : 16;
-        const int coarse_matchings = o.coarse_matchings > 0 ? o.coarse_matchings : 2;
+        const int coarse_matchings = o.coarse_matchings > 0 ? o.coarse_matchings : 3;
         if (coarse_matchings < 2 || coarse_matchings > 4) return "coarse_matchings must be in [2, 4]";
         S.lv.clear();
         S.lv.emplace_back();

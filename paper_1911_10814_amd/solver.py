@@ -78,7 +78,7 @@ class NsContext:
     mask, outlet_ptr, faces; n_nodes, n_elems, n_outlets)."""
 
     def __init__(self, case, *, max_m=200, max_m_A=200, max_m_S=200, coarse_nodes=128, max_levels=16,
-                 coarse_matchings=2, device="cuda:0"):
+                 coarse_matchings=3, device="cuda:0"):
         self.lib = _lib.load()
         self.device = torch.device(device)
         self.N = int(case.n_nodes)
