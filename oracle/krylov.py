@@ -215,6 +215,7 @@ class SolveOpts:
     nmax_S: int = 200
     pc_A: str = "amg"        # "amg" or "jacobi"
     cheb_degree: int = 2
+    cheb_degree_S: int = 0   # Chebyshev degree on the S_hat hierarchy (0: cheb_degree)
     cheb_ratio: float = 10.0
     cycles_S: int = 1        # V-cycle iterations per application of P_S
     pc: str = "scr"          # outer preconditioner: "scr" (Algorithm 3) or "simple" (Sec. 3.2)
@@ -242,7 +243,8 @@ class NestedSolver:
         # S_hat = D - C diag(A)^{-1} B  (Sec. 3.1)
         import scipy.sparse as sp
         self.Shat = (S.D - S.C @ sp.diags(1.0 / dA) @ S.B).tocsr()
-        self.amgS = amg_mod.AMG(self.Shat, 1, self.aggs, opts.cheb_degree, cheb_ratio=opts.cheb_ratio)
+        self.amgS = amg_mod.AMG(self.Shat, 1, self.aggs, opts.cheb_degree_S or opts.cheb_degree,
+                                cheb_ratio=opts.cheb_ratio)
 
     def pS(self, r):
         """P_S: ``cycles_S`` steps of the stationary V-cycle iteration on

@@ -375,7 +375,8 @@ void run_step(ns_ctx* c, const Ctl& K, int kind, int j, F&& body) {
         return;
     }
     const int sys = K.sy == &c->sys[0] ? 0 : 1;
-    const auto key = std::make_tuple(kind, sys, K.o.precision, K.o.pc_A, dflt(K.o.cheb_degree, kDefaultChebDegree),
+    const int degA = dflt(K.o.cheb_degree, kDefaultChebDegree);
+    const auto key = std::make_tuple(kind, sys, K.o.precision, K.o.pc_A, degA, dflt(K.o.cheb_degree_S, degA),
                                      dflt(K.o.cycles_S, kDefaultCyclesS), j);
     auto it = c->graphs.find(key);
     if (it == c->graphs.end()) {
@@ -643,7 +644,8 @@ struct Nested {
             dense_gemv<T>((int)nv, L.inv, b, xout, st);
             return;
         }
-        const int deg = dflt(K.o.cheb_degree, kDefaultChebDegree);
+        const int degA = dflt(K.o.cheb_degree, kDefaultChebDegree);
+        const int deg = &H == &sy.S ? dflt(K.o.cheb_degree_S, degA) : degA;
         const BlockOp<T> M = level_op(L);
         const T* dinv = Typed<T>::dinv(L);
         const T* coef = Typed<T>::coef(L);
@@ -1034,9 +1036,13 @@ void setup_system(ns_ctx* c, SystemDev& y, bool need32, hipStream_t st) {
 
 // Chebyshev coefficients of every smoothed level for the requested degree:
 // interval [lmax/30, lmax] of D^{-1} M, theta/delta its centre/half-width.
+// Step coefficients of the Chebyshev recurrence for every step up to the
+// largest degree (a step's coefficients do not depend on the degree in use,
+// so both hierarchies can run different degrees from one table).
 void upload_coef(ns_ctx* c, SystemDev& y, int deg, double ratio, hipStream_t st) {
     if (deg < 1 || deg > kMaxChebDegree) throw Fail{NS_ERR_ARG, "Chebyshev degree out of range [1, 8]"};
     if (!(ratio > 1.0) || !std::isfinite(ratio)) throw Fail{NS_ERR_ARG, "cheb_ratio must be finite and > 1"};
+    deg = kMaxChebDegree;
     if (y.coef_deg == deg && y.coef_ratio == ratio) return;
     std::vector<double> host;
     std::vector<AmgLevelDev*> lv;
@@ -1081,7 +1087,9 @@ void check_solve_opts(const ns_solve_opts& o) {
     if (o.precision != NS_FP64 && o.precision != NS_FP32_INNER) throw Fail{NS_ERR_ARG, "unknown precision"};
     if (o.pc != NS_OUTER_SCR && o.pc != NS_OUTER_SIMPLE) throw Fail{NS_ERR_ARG, "unknown outer preconditioner"};
     if (o.pc_A != NS_PC_AMG && o.pc_A != NS_PC_JACOBI) throw Fail{NS_ERR_ARG, "unknown P_A"};
-    if (o.reserved != 0) throw Fail{NS_ERR_ARG, "reserved option field must be 0"};
+    if (o.cheb_degree < 0 || o.cheb_degree > kMaxChebDegree || o.cheb_degree_S < 0 ||
+        o.cheb_degree_S > kMaxChebDegree)
+        throw Fail{NS_ERR_ARG, "Chebyshev degree out of range [1, 8]"};
 }
 
 ns_status run_solve(ns_ctx* c, int which, const ns_solve_opts* opts, const double* b, double* x, ns_stats* hs,

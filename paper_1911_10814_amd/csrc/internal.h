@@ -123,7 +123,7 @@ struct SystemDev {
     double* shat64 = nullptr;  // [nnz S_hat]
     float* shat32 = nullptr;
     std::vector<AmgLevelDev> A, S;   // hierarchies
-    int coef_deg = 0;                // Chebyshev degree the device coefficients belong to
+    int coef_deg = 0;                // number of Chebyshev steps the device coefficients cover
     double coef_ratio = 0.0;         // and the interval ratio
     bool ready = false;              // per-step set-up done for the current tangent
     bool have32 = false;
@@ -202,6 +202,6 @@ struct ns_ctx {
     bool use_graphs = true;
     int xcd_mode = -1;           // XCD-contiguous row ranges: -1 by size, 0 off, 1 on
     // captured Arnoldi steps: (kind, system, precision, pc_A, degree, j) -> executable graph
-    std::map<std::tuple<int, int, int, int, int, int, int>, hipGraphExec_t> graphs;
+    std::map<std::tuple<int, int, int, int, int, int, int, int>, hipGraphExec_t> graphs;
     std::vector<double> ck_host;
 };

@@ -34,6 +34,7 @@ class SolveOptions:
     pc_A: str = "amg"            # "amg" | "jacobi"
     precision: str = "fp64"      # "fp64" | "fp32_inner"
     cheb_degree: int = 2
+    cheb_degree_S: int = 0       # degree on the S_hat hierarchy (0: cheb_degree)
     cheb_ratio: float = 10.0     # smoother interval [lambda/cheb_ratio, lambda]
     cycles_S: int = 1            # V-cycle iterations per application of P_S
     pc: str = "scr"              # outer preconditioner: "scr" (Algorithm 3) | "simple" (Sec. 3.2)
@@ -43,7 +44,7 @@ class SolveOptions:
     def to_c(self):
         o = _lib.NsSolveOpts()
         for f in ("rtol", "atol", "rtol_A", "rtol_S", "rtol_I", "m", "nmax", "m_A", "nmax_A", "m_S", "nmax_S",
-                  "cheb_degree", "cheb_ratio", "cycles_S"):
+                  "cheb_degree", "cheb_degree_S", "cheb_ratio", "cycles_S"):
             setattr(o, f, getattr(self, f))
         o.pc_A = {"amg": 0, "jacobi": 1}[self.pc_A]
         o.precision = {"fp64": 0, "fp32_inner": 1}[self.precision]

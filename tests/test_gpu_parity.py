@@ -166,6 +166,17 @@ def test_short_restart_lengths_replay_matches_oracle(name, pc_A):
     assert ti["converged"] and ti["true_rel_res"] <= 1e-8
 
 
+@pytest.mark.parametrize("name", ["channel2", "ybif_small"])
+def test_separate_schur_smoother_degree_replay_matches_oracle(name):
+    """A different Chebyshev degree on the S_hat hierarchy (3) than on A (2)."""
+    from paper_1911_10814_amd import SolveOptions
+    ctx = ctx_for(name)
+    S = get_assembled(name)
+    xo, info = oracle_solver(name, cheb_degree_S=3).solve(S.rhs)
+    xg, _ = ctx.solve(ctx._rhs, SolveOptions(cheb_degree_S=3, schedule=info["schedule"]))
+    assert rel(xg.cpu().numpy(), xo) <= 1e-10
+
+
 @pytest.mark.parametrize("name", CASES)
 def test_nested_solve_fp32_inner(name):
     from paper_1911_10814_amd import SolveOptions
