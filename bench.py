@@ -88,7 +88,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="pipe_200k")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", default="pipe_small")
+    ap.add_argument("--cpu-sample", default="pipe_20k")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (--gpus {args.gpus} requested); the multi-GPU decomposition is a "
@@ -186,13 +186,16 @@ def main():
     xa, xb = x32.cpu().numpy(), x64.cpu().numpy()
     err_v = float(np.linalg.norm(xa[:n3] - xb[:n3]) / np.linalg.norm(xb[:n3]))
     err_p = float(np.linalg.norm(xa[n3:] - xb[n3:]) / np.linalg.norm(xb[n3:]))
-    # the paper's lighter P_A option (point Jacobi) in both precisions
+    # the paper's lighter P_A option (point Jacobi) in both precisions, other
+    # smoother settings, and the SIMPLE outer preconditioner
     variants = {}
     for name, o in (("fp32_inner_jacobi", SolveOptions(precision="fp32_inner", pc_A="jacobi")),
                     ("fp64_jacobi", SolveOptions(precision="fp64", pc_A="jacobi")),
                     ("fp32_inner_cheb1", SolveOptions(precision="fp32_inner", cheb_degree=1)),
                     ("fp32_inner_cheb2_ratio30", SolveOptions(precision="fp32_inner", cheb_ratio=30.0)),
-                    ("fp32_inner_cheb3", SolveOptions(precision="fp32_inner", cheb_degree=3))):
+                    ("fp32_inner_cheb3", SolveOptions(precision="fp32_inner", cheb_degree=3)),
+                    ("fp32_inner_cheb3_S", SolveOptions(precision="fp32_inner", cheb_degree_S=3)),
+                    ("fp32_inner_simple", SolveOptions(precision="fp32_inner", pc="simple"))):
         runs = [solve_fresh(o)[1] for _ in range(args.steps)]
         variants[name] = {"solve_ms": round(statistics.median(r["wall_ms"] for r in runs), 3),
                           "outer_iters": runs[-1]["outer_iters"], "a_iters": runs[-1]["a_iters"],

@@ -140,6 +140,7 @@ PIPE_SIZES = {
     # name: (m, nr, layers) -> nodes = ((m+1)^2 + 4 m nr) * (layers + 1)
     "pipe_tiny": (4, 2, 12),
     "pipe_small": (8, 4, 40),
+    "pipe_20k": (10, 5, 60),
     "pipe_200k": (20, 10, 160),
     "pipe_2m": (44, 22, 340),
 }
