@@ -141,6 +141,7 @@ PIPE_SIZES = {
     "pipe_tiny": (4, 2, 12),
     "pipe_small": (8, 4, 40),
     "pipe_20k": (10, 5, 60),
+    "pipe_40k": (12, 6, 96),
     "pipe_200k": (20, 10, 160),
     "pipe_2m": (44, 22, 340),
 }

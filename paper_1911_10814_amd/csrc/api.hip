@@ -928,16 +928,18 @@ ns_status fgmres(Ctl& K, const double* b, double* x) {
 // Writes ||y_k||, ||y_{k-1}|| and the Gershgorin bound to out[0..2].
 constexpr int kPowerIters = 20;
 constexpr double kPowerSafety = 1.2;
+// red: reduction partials of this chain (at least n/1024 + 1 doubles), so
+// chains of different levels can run concurrently
 void smoother_bound_dev(ns_ctx* c, const BlockOp<double>& M, int bs, const double* dinv, double* x, double* y,
-                        double* out, hipStream_t st) {
+                        double* red, double* out, hipStream_t st) {
     const int64_t n = (int64_t)M.n * bs;
     power_start(n, x, st);
     for (int it = 0; it < kPowerIters; ++it) {
         spmv<double>(bs, bs, M, x, y, 1.0, nullptr, 0.0, dinv, nullptr, st);
         std::swap(x, y);
     }
-    norm2<double>(n, x, out, c->d_red, st);
-    norm2<double>(n, y, out + 1, c->d_red, st);
+    norm2<double>(n, x, out, red, st);
+    norm2<double>(n, y, out + 1, red, st);
     // the iterates are no longer needed: x holds the per-block partials
     // (at most n/4 + 1 <= n*bs of them)
     gershgorin_bound(M, bs, dinv, x, out + 2, st);
@@ -969,8 +971,14 @@ void setup_system(ns_ctx* c, SystemDev& y, bool need32, hipStream_t st) {
             block_dinv(s.n, 1, s.rp, s.col, s.v64, 0, 0, nullptr, s.dinv64, nullptr, st);
         }
         check_launch();
-        // smoother bounds of every smoothed level (three scalars each), read back once
+        // smoother bounds of every smoothed level (three scalars each), read back
+        // once: each level's chain on an auxiliary stream (its own iterates and
+        // reduction partials: the level's x0, r and b), while the coarsest
+        // inverses of both hierarchies run on the main stream
         double* bnd = c->d_bnd;
+        HIPCHK(hipEventRecord(c->fork_ev, st));
+        for (int a = 0; a < ns_ctx::kAux; ++a) HIPCHK(hipStreamWaitEvent(c->aux[a], c->fork_ev, 0));
+        int chain = 0;
         for (int h = 0; h < 2; ++h) {
             std::vector<AmgLevelDev>& H = h == 0 ? y.A : y.S;
             for (int l = 0; l < L; ++l) {
@@ -985,18 +993,22 @@ void setup_system(ns_ctx* c, SystemDev& y, bool need32, hipStream_t st) {
                 M.dextra = d.dextra64;
                 M.lanes = lanes_for(d.nnz, d.n);
                 if (l + 1 < L) {
-                    smoother_bound_dev(c, M, d.bs, d.dinv64, d.x0, d.r, bnd + 3 * (h * L + l), st);
+                    smoother_bound_dev(c, M, d.bs, d.dinv64, d.x0, d.r, d.b, bnd + 3 * (h * L + l),
+                                       c->aux[chain++ % ns_ctx::kAux]);
                 } else {
                     dense_from_csr(d.n, d.bs, d.rp, d.col, d.v64, d.rstride, d.cstride, d.dextra64, d.work, st);
                 }
             }
         }
         {
-            // coarsest inverses of both hierarchies, concurrently
             AmgLevelDev& a = y.A[L - 1];
             AmgLevelDev& s = y.S[L - 1];
             gauss_jordan_inverse2(a.n * a.bs, a.work, a.inv, s.n * s.bs, s.work, s.inv, st);
             check_launch();
+        }
+        for (int a = 0; a < ns_ctx::kAux; ++a) {
+            HIPCHK(hipEventRecord(c->aux_ev[a], c->aux[a]));
+            HIPCHK(hipStreamWaitEvent(st, c->aux_ev[a], 0));
         }
         std::vector<double> hb(3 * 2 * (size_t)L);
         HIPCHK(hipMemcpyAsync(hb.data(), bnd, hb.size() * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -1034,8 +1046,8 @@ void setup_system(ns_ctx* c, SystemDev& y, bool need32, hipStream_t st) {
     }
 }
 
-// Chebyshev coefficients of every smoothed level for the requested degree:
-// interval [lmax/30, lmax] of D^{-1} M, theta/delta its centre/half-width.
+// Chebyshev coefficients of every smoothed level: interval
+// [lmax/ratio, lmax] of D^{-1} M, theta/delta its centre/half-width.
 // Step coefficients of the Chebyshev recurrence for every step up to the
 // largest degree (a step's coefficients do not depend on the degree in use,
 // so both hierarchies can run different degrees from one table).
@@ -1277,6 +1289,11 @@ ns_status ns_ctx_bind(ns_ctx* c, void* ws, size_t bytes, hipStream_t st) {
         if (!c->own) HIPCHK(hipStreamCreateWithFlags(&c->own, hipStreamNonBlocking));
         for (int e = 0; e < 2; ++e)
             if (!c->step_ev[e]) HIPCHK(hipEventCreateWithFlags(&c->step_ev[e], hipEventDisableTiming));
+        for (int a = 0; a < ns_ctx::kAux; ++a) {
+            if (!c->aux[a]) HIPCHK(hipStreamCreateWithFlags(&c->aux[a], hipStreamNonBlocking));
+            if (!c->aux_ev[a]) HIPCHK(hipEventCreateWithFlags(&c->aux_ev[a], hipEventDisableTiming));
+        }
+        if (!c->fork_ev) HIPCHK(hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming));
         const char* ng = getenv("NS_NO_GRAPHS");
         c->use_graphs = !(ng && ng[0] == '1');
         const char* xr = getenv("NS_XCD_ROWS");
@@ -1295,6 +1312,12 @@ void ns_ctx_destroy(ns_ctx* c) {
     for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
     for (int e = 0; e < 2; ++e)
         if (c->step_ev[e]) (void)hipEventDestroy(c->step_ev[e]);
+    for (int a = 0; a < ns_ctx::kAux; ++a) {
+        if (c->aux[a]) (void)hipStreamSynchronize(c->aux[a]);
+        if (c->aux_ev[a]) (void)hipEventDestroy(c->aux_ev[a]);
+        if (c->aux[a]) (void)hipStreamDestroy(c->aux[a]);
+    }
+    if (c->fork_ev) (void)hipEventDestroy(c->fork_ev);
     if (c->own) (void)hipStreamDestroy(c->own);
     delete c;
 }

@@ -199,6 +199,12 @@ struct ns_ctx {
     // library-owned stream (solves run here; graph capture needs a non-default stream)
     hipStream_t own = nullptr;
     hipEvent_t step_ev[2] = {nullptr, nullptr};  // completion of queued Arnoldi steps
+    // set-up: the smoother-bound chains of the AMG levels run on auxiliary
+    // streams (default priority) beside the coarsest inverses on `own`
+    static constexpr int kAux = 4;
+    hipStream_t aux[kAux] = {};
+    hipEvent_t aux_ev[kAux] = {};
+    hipEvent_t fork_ev = nullptr;
     bool use_graphs = true;
     int xcd_mode = -1;           // XCD-contiguous row ranges: -1 by size, 0 off, 1 on
     // captured Arnoldi steps: (kind, system, precision, pc_A, degree, j) -> executable graph
