@@ -279,6 +279,9 @@ typedef struct {
  * ||R_(l)|| <= tol_R ||R_(1)|| or ||R_(l)|| <= tol_A (the l2 norm of the
  * assembled residual, Dirichlet entries excluded); else solve the tangent
  * system with ns_nested_solve options `solve` and apply the update of step 10.
+ * At most l_max systems are solved; the residual of the returned iterate is
+ * always assembled and tested (after the l_max-th update too), and
+ * NS_NOT_CONVERGED is returned when it misses both tolerances.
  *   phys       rho, mu, dt, rho_inf, beta_bf, c_t, c_i (h_m, h_P_af unused)
  *   d_y_n, d_ydot_n   [4 n_nodes] field-split state at t_n (Dirichlet values
  *                     imposed in d_y_n)

@@ -18,7 +18,9 @@ TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).
 Readings: the residual norm is the l2 norm of the assembled residual with the
 Dirichlet entries removed (the rhs of the linear system); ||R_(0)|| is the
 first corrector's residual; the returned state is the last iterate (the one
-whose residual met the tolerance).
+whose residual met the tolerance); at most l_max systems are solved and the
+residual of the returned iterate is always evaluated, also after the l_max-th
+update (one more assembly), so the history ends with it.
 """
 from __future__ import annotations
 
@@ -104,7 +106,7 @@ def time_step(case, y_n, ydot_n, model: OutletModel, nopt: NewtonOpts = NewtonOp
     iterations = 0
     converged = False
     r0 = None
-    for l in range(1, nopt.l_max + 1):
+    for l in range(1, nopt.l_max + 2):
         Q = _flows(case, a_raw, y)
         m = np.zeros(no)
         Paf = np.zeros(no)
@@ -122,6 +124,8 @@ def time_step(case, y_n, ydot_n, model: OutletModel, nopt: NewtonOpts = NewtonOp
             r0 = r
         if r <= nopt.tol_R * r0 or r <= nopt.tol_A:
             converged = True
+            break
+        if l > nopt.l_max:
             break
         if linear_solve is None:
             dx, _ = kr.NestedSolver(S, adj, sopt).solve(S.rhs)

@@ -1508,7 +1508,9 @@ ns_status ns_time_step(ns_ctx* c, const ns_phys* phys, ns_outlet_model* om, cons
         double r0 = 0.0, r = 0.0;
         bool conv = false;
         double asm_ms = 0.0, sol_ms = 0.0;
-        for (int l = 1; l <= l_max; ++l) {
+        // at most l_max corrector solves; the residual of the returned iterate
+        // is always evaluated (assembly l_max + 1 when the solves run out)
+        for (int l = 1; l <= l_max + 1; ++l) {
             flows(d_y);
             for (int k = 0; k < NO; ++k) {
                 const double eps = std::max(eps_abs, eps_rel * std::fabs(Q[k]));
@@ -1536,6 +1538,7 @@ ns_status ns_time_step(ns_ctx* c, const ns_phys* phys, ns_outlet_model* om, cons
                 conv = true;
                 break;
             }
+            if (l > l_max) break;
             ns_stats ls{};
             auto tsol = std::chrono::steady_clock::now();
             ns_status rs = ns_nested_solve(c, sopt, c->nt_rhs, c->nt_dx, &ls, st);

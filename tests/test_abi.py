@@ -110,3 +110,32 @@ def test_struct_layouts_match_header(tmp_path):
         assert got[(cname, "size")] == ctypes.sizeof(cls), cname
         for f, _ in cls._fields_:
             assert got[(cname, f)] == getattr(cls, f).offset, (cname, f)
+
+
+def test_entry_points_reject_an_unbound_context_without_a_gpu():
+    """Every device entry point checks its state before any HIP call: on a
+    context that was created but never bound it returns NS_ERR_STATE (-6)
+    with a message, and ns_ctx_create rejects bad options."""
+    import ctypes as C
+    from paper_1911_10814_amd import NsContext, NsError, SolveOptions, _lib
+    c = get_case("channel2")
+    ctx = NsContext(c)
+    lib = _lib.load()
+    o, keep, _ = SolveOptions().to_c()
+    st = _lib.NsStats()
+    nul = C.c_void_p(0)
+    rc = lib.ns_nested_solve(ctx.h, C.byref(o), nul, nul, C.byref(st), nul)
+    assert rc == -6 and b"not bound" in lib.ns_last_error(ctx.h)
+    rc = lib.ns_adjoint_solve(ctx.h, C.byref(o), nul, nul, C.byref(st), nul)
+    assert rc == -6
+    ph = _lib.NsPhys(1.0, 0.04, 1e-3, 0.5, 0.2, 4.0, 36.0, None, None)
+    assert lib.ns_assemble_tangent(ctx.h, C.byref(ph), nul, nul, nul, nul, nul) == -6
+    assert lib.ns_newton_update(ctx.h, 1.0, nul, nul, nul, nul) == -6
+    step = _lib.NsStepStats()
+    assert lib.ns_time_step(ctx.h, C.byref(ph), None, None, C.byref(o), nul, nul, nul, nul, C.byref(step),
+                            nul) == -6
+    out = np.zeros(2)
+    assert lib.ns_outlet_flow(ctx.h, nul, out.ctypes.data_as(_lib.PD), nul) == -6
+    # context options out of range
+    with pytest.raises(NsError, match="coarse_matchings"):
+        NsContext(c, coarse_matchings=7)

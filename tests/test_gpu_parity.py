@@ -262,6 +262,34 @@ def test_newton_update():
     assert torch.equal(y, y0 + 0.25 * dx) and torch.equal(yd, yd0 + dx)
 
 
+def test_failure_statuses():
+    """NS_NOT_CONVERGED returns the best iterate with its true residual;
+    options beyond the bound workspace are NS_ERR_ARG and leave the context
+    usable; a time step that runs out of correctors reports it."""
+    from paper_1911_10814_amd import NsError, SolveOptions
+    name = "channel2"
+    ctx = ctx_for(name)
+    S = get_assembled(name)
+    x, info = ctx.solve(ctx._rhs, SolveOptions(rtol=1e-14, nmax=1))
+    assert info["status"] == "NS_NOT_CONVERGED" and not info["converged"] and info["outer_iters"] == 1
+    r = np.linalg.norm(S.rhs - S.dense() @ x.cpu().numpy()) / np.linalg.norm(S.rhs)
+    assert abs(r - info["true_rel_res"]) <= 1e-6 * r and 1e-14 < r < 1.0
+    with pytest.raises(NsError, match="restart length"):
+        ctx.solve(ctx._rhs, SolveOptions(m_A=100000))
+    with pytest.raises(NsError, match="Chebyshev degree"):
+        ctx.solve(ctx._rhs, SolveOptions(cheb_degree=9))
+    x2, info2 = ctx.solve(ctx._rhs, SolveOptions())
+    assert info2["converged"]
+    c = get_case(name)
+    y_n = np.concatenate([c.v.ravel(), c.p])
+    y, yd, st, _ = ctx.time_step(y_n, np.zeros_like(y_n), rho=c.rho, mu=c.mu, dt=c.dt, rho_inf=c.rho_inf,
+                                 model={"Rp": c.R, "P": c.R * S.Q, "Q": S.Q},
+                                 newton=dict(tol_R=1e-30, tol_A=1e-300, l_max=2), opts=SolveOptions())
+    assert st["converged"] == 0 and st["iterations"] == 2 and len(st["res_hist"]) == 3
+    # the assembled tangent of the context was replaced by the time step's: restore it for later tests
+    _CTX.pop(name, None)
+
+
 def test_graph_replays_match_eager_launches(monkeypatch):
     """The captured Arnoldi-step graphs give bitwise the same solve as launching
     the same kernels one by one, on every replay, with eager work between."""

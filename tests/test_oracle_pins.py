@@ -706,3 +706,24 @@ def test_time_step_windkessel_derivative_gives_newton_convergence():
     assert info["converged"] and info["iterations"] <= 3
     assert h[-1] <= 1e-12 * h[0]
     assert np.all(h[2:] / h[1:-1] <= 1e-4)
+
+
+def test_time_step_exhausted_correctors_report_the_returned_state():
+    """With l_max solves used up, the last history entry is the residual of the
+    returned state (assembled here from its definition) and the step is not
+    converged."""
+    c, y_n, ydot_n, model = _step_inputs("channel2")
+    ph = dz.physics_of(c)
+    am, af, gam = ph.alphas
+    y, ydot, info, _ = nt.time_step(c, y_n, ydot_n, model, nt.NewtonOpts(tol_R=1e-30, tol_A=1e-300, l_max=1),
+                                    kr.SolveOpts())
+    assert not info["converged"] and info["iterations"] == 1 and len(info["res_hist"]) == 2
+    N = c.n_nodes
+    yaf = y_n + af * (y - y_n)
+    ydam = ydot_n + am * (ydot - ydot_n)
+    a_raw, _, _ = dz.outlet_vectors(c)
+    Q = np.array([np.sum(a_raw[k] * y[:3 * N].reshape(N, 3)) for k in range(c.n_outlets)])
+    S = dz.assemble(c, P_af=(1 - af) * model.P + af * c.R * Q, R=c.R, v=yaf[:3 * N].reshape(N, 3), p=yaf[3 * N:],
+                    vdot=ydam[:3 * N].reshape(N, 3))
+    assert np.isclose(info["res_hist"][-1], np.linalg.norm(S.rhs), rtol=1e-12)
+    assert info["res_hist"][-1] < info["res_hist"][0]
