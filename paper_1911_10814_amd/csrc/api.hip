@@ -266,9 +266,13 @@ void timed(ns_ctx* c, int cls, double bytes, hipStream_t st, F&& launch) {
         HIPCHK(hipEventCreate(&e));
         c->kt_ev.push_back(e);
     }
-    HIPCHK(hipEventRecord(c->kt_ev[2 * used], st));
+    // the launch itself records the pair at the kernel's start and end
+    set_launch_events(c->kt_ev[2 * used], c->kt_ev[2 * used + 1]);
     launch();
-    HIPCHK(hipEventRecord(c->kt_ev[2 * used + 1], st));
+    if (launch_events_pending()) {  // no timed kernel was launched: drop the sample
+        set_launch_events(nullptr, nullptr);
+        return;
+    }
     c->kt_pending.emplace_back(cls, bytes);
 }
 

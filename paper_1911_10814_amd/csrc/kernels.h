@@ -42,6 +42,13 @@ struct BlockOp {
     int xcd = 0;                // 1: each XCD takes one contiguous range of rows (xcd_block)
 };
 
+// Kernel timing: the next launch of the block-SpMV family (spmv, spmv_full,
+// cheb_step) records `start` and `stop` at its own start and end; returns to
+// plain launches after that one.  launch_events_pending() tells whether the
+// events are still unused.
+void set_launch_events(hipEvent_t start, hipEvent_t stop);
+bool launch_events_pending();
+
 // lanes per row for a pattern with nnz blocks over n rows: one pass over a
 // typical row, so consecutive rows give contiguous loads across the wavefront
 inline int lanes_for(int64_t nnz, int n) {
