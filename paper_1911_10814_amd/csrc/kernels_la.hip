@@ -100,6 +100,21 @@ __global__ __launch_bounds__(kBlock) void k_spmv(BlockOp<T> M, const T* __restri
     const int row = (int)(tid / W);
     const int lane = threadIdx.x % W;
     const bool valid = row < M.n;
+    // epilogue operands of the own row, loaded before the row loop (their
+    // latency overlaps the gathers)
+    const bool out_lane = valid && lane < BR;
+    const int64_t i = (int64_t)BR * row + lane;
+    T ext = 0, zi = 0, rsi = 1, fdi = 0, r1 = 0;
+    if (out_lane) {
+        if (M.dextra) ext = M.dextra[i] * x[i];
+        if (z) zi = z[i];
+        if (rscale) rsi = rscale[i];
+        if (fs.x) fdi = fs.coef[0] * fs.dinv[i];
+        if (ro.slot_of) {
+            const int sl = ro.slot_of[row];
+            if (sl >= 0) r1 = ro.s[ro.oid[sl]] * ro.aval[3 * (int64_t)sl + lane];
+        }
+    }
     T acc[BR];
 #pragma unroll
     for (int r = 0; r < BR; ++r) acc[r] = 0;
@@ -120,23 +135,19 @@ __global__ __launch_bounds__(kBlock) void k_spmv(BlockOp<T> M, const T* __restri
     for (int off = W / 2; off > 0; off >>= 1)
 #pragma unroll
         for (int r = 0; r < BR; ++r) acc[r] += __shfl_xor(acc[r], off, W);
-    if (!valid || lane >= BR) return;
+    if (!out_lane) return;
     T s = acc[0];
 #pragma unroll
     for (int r = 1; r < BR; ++r)
         if (lane == r) s = acc[r];
-    const int64_t i = (int64_t)BR * row + lane;
-    if (M.dextra) s += M.dextra[i] * x[i];
-    if (ro.slot_of) {
-        const int sl = ro.slot_of[row];
-        if (sl >= 0) s += ro.s[ro.oid[sl]] * ro.aval[3 * (int64_t)sl + lane];
-    }
+    if (M.dextra) s += ext;
+    if (ro.slot_of) s += r1;
     T out = alpha * s;
-    if (z) out += beta * z[i];
-    if (rscale) out *= rscale[i];
+    if (z) out += beta * zi;
+    if (rscale) out *= rsi;
     y[i] = out;
     if (fs.x) {
-        const T di = fs.coef[0] * fs.dinv[i] * out;
+        const T di = fdi * out;
         fs.x[i] = di;
         fs.d[i] = di;
     }
@@ -711,6 +722,19 @@ __global__ __launch_bounds__(kBlock) void k_cheb_step(BlockOp<T> M, const T* __r
     const int row = (int)(tid / W);
     const int lane = threadIdx.x % W;
     const bool valid = row < M.n;
+    // the epilogue's own-row operands are loaded before the row loop, so their
+    // latency overlaps the gathers instead of following the reduction
+    const bool out_lane = valid && lane < BS;
+    const int64_t i = (int64_t)BS * row + lane;
+    T xi = 0, ex = 0, bi = 0, dvi = 0, dprev = 0;
+    if (out_lane) {
+        xi = xin[i];
+        if (agg) xi += ec[(int64_t)BS * agg[row] + lane];
+        if (M.dextra) ex = M.dextra[i];
+        bi = b[i];
+        dvi = dinv[i];
+        if (step != 0) dprev = d[i];
+    }
     T acc[BS];
 #pragma unroll
     for (int r = 0; r < BS; ++r) acc[r] = 0;
@@ -737,20 +761,17 @@ __global__ __launch_bounds__(kBlock) void k_cheb_step(BlockOp<T> M, const T* __r
     for (int off = W / 2; off > 0; off >>= 1)
 #pragma unroll
         for (int r = 0; r < BS; ++r) acc[r] += __shfl_xor(acc[r], off, W);
-    if (!valid || lane >= BS) return;
+    if (!out_lane) return;
     T s = acc[0];
 #pragma unroll
     for (int r = 1; r < BS; ++r)
         if (lane == r) s = acc[r];
-    const int64_t i = (int64_t)BS * row + lane;
-    T xi = xin[i];
-    if (agg) xi += ec[(int64_t)BS * agg[row] + lane];
-    if (M.dextra) s += M.dextra[i] * xi;
+    if (M.dextra) s += ex * xi;
     T c1, c2;
     cheb_coef(coef, step, c1, c2);
-    const T ri = b[i] - s;
-    T di = c2 * dinv[i] * ri;
-    if (step != 0) di += c1 * d[i];
+    const T ri = bi - s;
+    T di = c2 * dvi * ri;
+    if (step != 0) di += c1 * dprev;
     d[i] = di;
     xout[i] = xi + di;
 }
