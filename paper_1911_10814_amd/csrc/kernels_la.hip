@@ -198,6 +198,16 @@ __global__ __launch_bounds__(kBlock) void k_spmv_full(int n, const int32_t* __re
     const int lane = threadIdx.x % W;
     const bool valid = row < n;
     const T* xp = x + 3 * (int64_t)n;
+    // own-row epilogue operands, loaded ahead of the row loop
+    const int64_t i = lane < 3 ? 3 * (int64_t)row + lane : 3 * (int64_t)n + row;
+    T zi = 0, r1 = 0;
+    if (valid && lane < 4) {
+        if (z) zi = z[i];
+        if (lane < 3 && ro.slot_of) {
+            const int sl = ro.slot_of[row];
+            if (sl >= 0) r1 = ro.s[ro.oid[sl]] * ro.aval[3 * (int64_t)sl + lane];
+        }
+    }
     T acc[4] = {0, 0, 0, 0};
     if (valid) {
         const int k1 = rp[row + 1];
@@ -219,13 +229,9 @@ __global__ __launch_bounds__(kBlock) void k_spmv_full(int n, const int32_t* __re
     if (lane == 1) s = acc[1];
     if (lane == 2) s = acc[2];
     if (lane == 3) s = acc[3];
-    const int64_t i = lane < 3 ? 3 * (int64_t)row + lane : 3 * (int64_t)n + row;
-    if (lane < 3 && ro.slot_of) {
-        const int sl = ro.slot_of[row];
-        if (sl >= 0) s += ro.s[ro.oid[sl]] * ro.aval[3 * (int64_t)sl + lane];
-    }
+    if (lane < 3 && ro.slot_of) s += r1;
     T out = alpha * s;
-    if (z) out += beta * z[i];
+    if (z) out += beta * zi;
     y[i] = out;
 }
 
@@ -821,6 +827,8 @@ __global__ __launch_bounds__(kBlock) void k_sfact_bt(int n, const int32_t* __res
     const int row = (int)(tid / W);
     const int lane = threadIdx.x % W;
     const bool valid = row < n;
+    const int64_t i = 3 * (int64_t)row + lane;
+    const T dai = (valid && lane < 3) ? dinvA[i] : T(0);  // loaded ahead of the row loop
     T acc[3] = {0, 0, 0};
     if (valid) {
         const int k1 = rp[row + 1];
@@ -838,8 +846,7 @@ __global__ __launch_bounds__(kBlock) void k_sfact_bt(int n, const int32_t* __res
         for (int r = 0; r < 3; ++r) acc[r] += __shfl_xor(acc[r], off, W);
     if (!valid || lane >= 3) return;
     const T s = lane == 0 ? acc[0] : (lane == 1 ? acc[1] : acc[2]);
-    const int64_t i = 3 * (int64_t)row + lane;
-    t[i] = dinvA[i] * s;
+    t[i] = dai * s;
 }
 
 template <typename T, int W>
@@ -855,6 +862,19 @@ __global__ __launch_bounds__(kBlock) void k_sfact_dc(int n, const int32_t* __res
     const int row = (int)(tid / W);
     const int lane = threadIdx.x % W;
     const bool valid = row < n;
+    // own-row epilogue operands, loaded ahead of the row loop
+    T zi = 0, xi = 0, bi = 0, dvi = 0, dprev = 0;
+    if (valid && lane == 0) {
+        if (!coef) {
+            if (z) zi = z[row];
+        } else {
+            xi = x[row];
+            if (agg) xi += ec[agg[row]];
+            bi = b[row];
+            dvi = dinv[row];
+            if (step != 0) dprev = d[row];
+        }
+    }
     T acc = 0;
     if (valid) {
         const int k1 = rp[row + 1];
@@ -872,16 +892,14 @@ __global__ __launch_bounds__(kBlock) void k_sfact_dc(int n, const int32_t* __res
     if (!valid || lane != 0) return;
     if (!coef) {
         T out = alpha * acc;
-        if (z) out += beta * z[row];
+        if (z) out += beta * zi;
         y[row] = out;
         return;
     }
-    T xi = x[row];
-    if (agg) xi += ec[agg[row]];
     T c1, c2;
     cheb_coef(coef, step, c1, c2);
-    T di = c2 * dinv[row] * (b[row] - acc);
-    if (step != 0) di += c1 * d[row];
+    T di = c2 * dvi * (bi - acc);
+    if (step != 0) di += c1 * dprev;
     d[row] = di;
     y[row] = xi + di;
 }
@@ -948,6 +966,8 @@ __global__ __launch_bounds__(kBlock) void k_resid_restrict(BlockOp<T> M, const T
     const int lane = threadIdx.x & 63;
     const int sub = lane / kRowLanes, l = lane % kRowLanes;
     const bool valid = I < nc;
+    const int64_t t = (int64_t)BS * I + lane;
+    const T fc = (valid && lane < BS && xc) ? coefc[0] * dinvc[t] : T(0);  // loaded ahead of the loops
     // acc = sum over the aggregate of (M x + dextra x - b): the negated residual
     T acc[BS];
 #pragma unroll
@@ -986,10 +1006,9 @@ __global__ __launch_bounds__(kBlock) void k_resid_restrict(BlockOp<T> M, const T
 #pragma unroll
     for (int r = 1; r < BS; ++r)
         if (lane == r) s = -acc[r];
-    const int64_t t = (int64_t)BS * I + lane;
     bc[t] = s;
     if (xc) {
-        const T di = coefc[0] * dinvc[t] * s;
+        const T di = fc * s;
         xc[t] = di;
         dc[t] = di;
     }
