@@ -1263,9 +1263,130 @@ __global__ void k_gj_extract(int n0, const double* w0, double* inv0, int n1, con
     }
 }
 
+// Blocked form: one launch per panel of kGjPanel pivot steps.  Each workgroup
+// owns kGjSlab columns of [M | I] (all rows) and keeps, redundantly, a copy of
+// the panel's columns: it repeats the panel's pivot choices and multipliers on
+// that copy (the same arithmetic in every workgroup) and applies them to its
+// columns in LDS.  Element by element the operations are those of k_gj_step,
+// so the result is the same.  LDS: n (kGjPanel + kGjSlab + 1) doubles.
+constexpr int kGjPanel = 8, kGjSlab = 8;
+constexpr int kGjPanelMaxN = 448;
+
+struct GjPanel {
+    int n[2];
+    const double* src[2];
+    double* dst[2];
+    int blocks0;   // workgroups of matrix 0; the rest belong to matrix 1
+};
+
+__global__ __launch_bounds__(kBlock) void k_gj_panel(GjPanel a, int k0) {
+    extern __shared__ double lds[];
+    __shared__ double sval[kBlock];
+    __shared__ int sidx[kBlock];
+    __shared__ double prow[kGjPanel + kGjSlab];  // scaled pivot row (old row p)
+    __shared__ double rowk[kGjPanel + kGjSlab];  // old row k
+    const int m = (int)blockIdx.x < a.blocks0 ? 0 : 1;
+    const int n = a.n[m];
+    const int b = m == 0 ? (int)blockIdx.x : (int)blockIdx.x - a.blocks0;
+    const double* src = a.src[m];
+    double* dst = a.dst[m];
+    const int64_t n2 = 2 * (int64_t)n;
+    const int c0 = b * kGjSlab;
+    const int nc = (int)min((int64_t)kGjSlab, n2 - c0);
+    const int P = min(kGjPanel, n - k0);   // pivot steps of this matrix in the panel (<= 0: carry over)
+    double* pan = lds;                     // [n][kGjPanel]
+    double* sl = pan + n * kGjPanel;       // [n][kGjSlab]
+    double* f = sl + n * kGjSlab;          // [n] multipliers
+    const int tid = threadIdx.x;
+    for (int e = tid; e < n * kGjSlab; e += kBlock) {
+        const int r = e / kGjSlab, c = e % kGjSlab;
+        sl[e] = c < nc ? src[r * n2 + c0 + c] : 0.0;
+    }
+    for (int e = tid; e < n * kGjPanel; e += kBlock) {
+        const int r = e / kGjPanel, t = e % kGjPanel;
+        pan[e] = t < P ? src[r * n2 + k0 + t] : 0.0;
+    }
+    __syncthreads();
+    for (int t = 0; t < P; ++t) {
+        const int k = k0 + t;
+        double best = -1.0;
+        int bi = k;
+        for (int q = k + tid; q < n; q += kBlock) {
+            const double v = fabs(pan[q * kGjPanel + t]);
+            if (v > best) {
+                best = v;
+                bi = q;
+            }
+        }
+        sval[tid] = best;
+        sidx[tid] = bi;
+        __syncthreads();
+        for (int s = kBlock / 2; s > 0; s >>= 1) {
+            if (tid < s) {
+                const double o = sval[tid + s];
+                const int oi = sidx[tid + s];
+                if (o > sval[tid] || (o == sval[tid] && oi < sidx[tid])) {
+                    sval[tid] = o;
+                    sidx[tid] = oi;
+                }
+            }
+            __syncthreads();
+        }
+        const int p = sidx[0];
+        const double inv_p = 1.0 / pan[p * kGjPanel + t];
+        if (tid < kGjPanel) {
+            prow[tid] = pan[p * kGjPanel + tid] * inv_p;
+            rowk[tid] = pan[k * kGjPanel + tid];
+        } else if (tid < kGjPanel + kGjSlab) {
+            prow[tid] = sl[p * kGjSlab + tid - kGjPanel] * inv_p;
+            rowk[tid] = sl[k * kGjSlab + tid - kGjPanel];
+        }
+        // after exchanging rows k and p, row r holds the old row (r == p ? k : r)
+        for (int r = tid; r < n; r += kBlock) f[r] = pan[(r == p ? k : r) * kGjPanel + t];
+        __syncthreads();
+        for (int e = tid; e < n * kGjPanel; e += kBlock) {
+            const int r = e / kGjPanel, c = e % kGjPanel;
+            if (r == k) pan[e] = prow[c];
+            else pan[e] = (r == p ? rowk[c] : pan[e]) - f[r] * prow[c];
+        }
+        for (int e = tid; e < n * kGjSlab; e += kBlock) {
+            const int r = e / kGjSlab, c = e % kGjSlab;
+            if (r == k) sl[e] = prow[kGjPanel + c];
+            else sl[e] = (r == p ? rowk[kGjPanel + c] : sl[e]) - f[r] * prow[kGjPanel + c];
+        }
+        __syncthreads();
+    }
+    for (int e = tid; e < n * kGjSlab; e += kBlock) {
+        const int r = e / kGjSlab, c = e % kGjSlab;
+        if (c < nc) dst[r * n2 + c0 + c] = sl[e];
+    }
+}
+
 void gauss_jordan_inverse2(int n0, double* work0, double* inv0, int n1, double* work1, double* inv1,
                            hipStream_t st) {
     const int steps = std::max(n0, n1);
+    if (std::max(n0, n1) <= kGjPanelMaxN) {
+        const int panels = (std::max(n0, n1) + kGjPanel - 1) / kGjPanel;
+        GjPanel a;
+        a.n[0] = n0;
+        a.n[1] = n1;
+        a.blocks0 = (int)((2 * (int64_t)n0 + kGjSlab - 1) / kGjSlab);
+        const int blocks = a.blocks0 + (int)((2 * (int64_t)n1 + kGjSlab - 1) / kGjSlab);
+        const size_t lds = (size_t)std::max(n0, n1) * (kGjPanel + kGjSlab + 1) * sizeof(double);
+        double* half0[2] = {work0, work0 + 2 * (int64_t)n0 * n0};
+        double* half1[2] = {work1, work1 + 2 * (int64_t)n1 * n1};
+        for (int i = 0; i < panels; ++i) {
+            a.src[0] = half0[i & 1];
+            a.dst[0] = half0[(i + 1) & 1];
+            a.src[1] = half1[i & 1];
+            a.dst[1] = half1[(i + 1) & 1];
+            hipLaunchKernelGGL(k_gj_panel, dim3(blocks), dim3(kBlock), lds, st, a, i * kGjPanel);
+        }
+        const int64_t tot = (int64_t)n0 * n0 + (int64_t)n1 * n1;
+        hipLaunchKernelGGL(k_gj_extract, dim3(grid_for(tot)), dim3(kBlock), 0, st, n0, half0[panels & 1], inv0, n1,
+                           half1[panels & 1], inv1);
+        return;
+    }
     GjStep a;
     a.n[0] = n0;
     a.n[1] = n1;
