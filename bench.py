@@ -195,7 +195,8 @@ def main():
                     ("fp32_inner_cheb2_ratio30", SolveOptions(precision="fp32_inner", cheb_ratio=30.0)),
                     ("fp32_inner_cheb3", SolveOptions(precision="fp32_inner", cheb_degree=3)),
                     ("fp32_inner_cheb3_S", SolveOptions(precision="fp32_inner", cheb_degree_S=3)),
-                    ("fp32_inner_simple", SolveOptions(precision="fp32_inner", pc="simple"))):
+                    ("fp32_inner_simple", SolveOptions(precision="fp32_inner", pc="simple")),
+                    ("fp32_inner_jacobi_inner", SolveOptions(precision="fp32_inner", pc_I="jacobi"))):
         runs = [solve_fresh(o)[1] for _ in range(args.steps)]
         variants[name] = {"solve_ms": round(statistics.median(r["wall_ms"] for r in runs), 3),
                           "outer_iters": runs[-1]["outer_iters"], "a_iters": runs[-1]["a_iters"],

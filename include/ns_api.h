@@ -139,6 +139,10 @@ typedef struct {
     int32_t pc;             /* ns_outer_pc: outer preconditioner      [SCR]   */
     int32_t cheb_degree_S;  /* Chebyshev degree on the S_hat hierarchy,
                              * 0..8; 0 = cheb_degree                  [0]     */
+    int32_t pc_I;           /* P of the inner A-solves of Algorithm 2
+                             * (Sec. 4 suggests a light one there):
+                             * 0 = as pc_A, 1 = AMG, 2 = Jacobi       [0]     */
+    int32_t reserved;       /* must be 0 */
     /* Iteration schedule.  If h_sched != NULL, the i-th Krylov call (calls
      * numbered in the order they start: FGMRES, then each GMRES on A or S)
      * runs exactly h_sched[i] iterations instead of testing its tolerance.

@@ -214,6 +214,7 @@ class SolveOpts:
     nmax_A: int = 200
     nmax_S: int = 200
     pc_A: str = "amg"        # "amg" or "jacobi"
+    pc_I: str | None = None  # P of the inner A-solves of Algorithm 2 (None: as pc_A)
     cheb_degree: int = 2
     cheb_degree_S: int = 0   # Chebyshev degree on the S_hat hierarchy (0: cheb_degree)
     cheb_ratio: float = 10.0
@@ -254,14 +255,15 @@ class NestedSolver:
             z = z + self.amgS.vcycle(r - self.Shat @ z)
         return z
 
-    def pA(self, r):
-        if self.o.pc_A == "jacobi":
+    def pA(self, r, pc=None):
+        if (pc or self.o.pc_A) == "jacobi":
             return r / self.dA
         return self.amgA.vcycle(r)
 
-    def solve_A(self, b, rtol, sched):
+    def solve_A(self, b, rtol, sched, inner=False):
         o = self.o
-        x, _ = gmres_left(self.S.apply_A, self.pA, b, rtol, o.m_A, o.nmax_A, sched, o.atol)
+        pc = (o.pc_I or o.pc_A) if inner else o.pc_A
+        x, _ = gmres_left(self.S.apply_A, lambda r: self.pA(r, pc), b, rtol, o.m_A, o.nmax_A, sched, o.atol)
         return x
 
     def schur_apply(self, xp, sched):
@@ -269,7 +271,7 @@ class NestedSolver:
         S = self.S
         xhat = S.D @ xp
         xbar = S.B @ xp
-        xt = self.solve_A(xbar, self.o.rtol_I, sched)
+        xt = self.solve_A(xbar, self.o.rtol_I, sched, inner=True)
         return xhat - S.C @ xt
 
     def scr_apply(self, s, sched):

@@ -357,7 +357,7 @@ void read_status(ns_ctx* c, const double* d_status, int n, hipStream_t st) {
 // [9 + kind] initial residual norm of a left GMRES call of that kind
 constexpr int kMapStatus = 0, kMapNorm = 8, kMapNorm0 = 9;
 // graph kinds of Arnoldi steps (one mapped initial-norm slot each)
-constexpr int kKindA = 0, kKindS = 1, kKindOuter = 2, kKindShat = 3;
+constexpr int kKindA = 0, kKindS = 1, kKindOuter = 2, kKindShat = 3, kKindInner = 4;
 
 template <typename T>
 double dev_norm(ns_ctx* c, int64_t n, const T* x, double* slot, hipStream_t st) {
@@ -380,8 +380,8 @@ void run_step(ns_ctx* c, const Ctl& K, int kind, int j, F&& body) {
     }
     const int sys = K.sy == &c->sys[0] ? 0 : 1;
     const int degA = dflt(K.o.cheb_degree, kDefaultChebDegree);
-    const auto key = std::make_tuple(kind, sys, K.o.precision, K.o.pc_A, degA, dflt(K.o.cheb_degree_S, degA),
-                                     dflt(K.o.cycles_S, kDefaultCyclesS), j);
+    const auto key = std::make_tuple(kind, sys, K.o.precision, K.o.pc_A, K.o.pc_I, degA,
+                                     dflt(K.o.cheb_degree_S, degA), dflt(K.o.cycles_S, kDefaultCyclesS), j);
     auto it = c->graphs.find(key);
     if (it == c->graphs.end()) {
         HIPCHK(hipStreamBeginCapture(K.st, hipStreamCaptureModeThreadLocal));
@@ -714,8 +714,11 @@ struct Nested {
             std::swap(a, bb);
         }
     }
-    void applyPA(const T* r, T* z) {
-        if (K.o.pc_A == NS_PC_JACOBI)
+    // P of an A-solve: pc_A for the intermediate ones, pc_I (if set) for the
+    // inner ones of Algorithm 2
+    int pc_of(bool inner) const { return inner && K.o.pc_I != 0 ? K.o.pc_I - 1 : K.o.pc_A; }
+    void applyPA(const T* r, T* z, int pc) {
+        if (pc == NS_PC_JACOBI)
             mul<T>(3 * (int64_t)N, Typed<T>::dinv(sy.A[0]), r, z, K.st);
         else
             vcycle(sy.A, 0, r, z);
@@ -736,9 +739,12 @@ struct Nested {
         }
     }
 
-    int solveA(const T* b, T* x, double rtol) {
+    int solveA(const T* b, T* x, double rtol, bool inner = false) {
+        const int pc = pc_of(inner);
+        // inner solves with a P of their own use graphs of their own
+        const int kind = pc == K.o.pc_A ? kKindA : kKindInner;
         std::function<void(const T*, T*)> sM, sP;
-        if (K.o.pc_A != NS_PC_JACOBI && fuse_first(sy.A)) {
+        if (pc != NS_PC_JACOBI && fuse_first(sy.A)) {
             sM = [this](const T* in, T* out) {
                 const FirstStep<T> f = first_step(sy.A);
                 applyA(in, out, &f);
@@ -747,15 +753,15 @@ struct Nested {
         }
         return gmres_left<T>(
             K, c->kw_A, 3 * (int64_t)N, [this](const T* in, T* out) { applyA(in, out); },
-            [this](const T* in, T* out) { applyPA(in, out); }, b, x, rtol, dflt(K.o.m_A, 200),
-            dflt(K.o.nmax_A, 200), kKindA, true, sM, sP);
+            [this, pc](const T* in, T* out) { applyPA(in, out, pc); }, b, x, rtol, dflt(K.o.m_A, 200),
+            dflt(K.o.nmax_A, 200), kind, true, sM, sP);
     }
     // Algorithm 2: y = D x - C A^{-1} (B x)
     void schur(const T* xp, T* y, const FirstStep<T>* fs = nullptr) {
         hipStream_t st = K.st;
         spmv<T>(1, 1, op(3, 3), xp, as<T>(c->t_xhat), T(1), nullptr, T(0), nullptr, nullptr, st);
         spmv<T>(3, 1, op(0, 3), xp, as<T>(c->t_xbar), T(1), nullptr, T(0), nullptr, nullptr, st);
-        const int it = solveA(as<T>(c->t_xbar), as<T>(c->t_xt), dfltd(K.o.rtol_I, 1e-3));
+        const int it = solveA(as<T>(c->t_xbar), as<T>(c->t_xt), dfltd(K.o.rtol_I, 1e-3), true);
         K.stats.inner_solves++;
         K.stats.inner_iters += it;
         spmv<T>(1, 3, op(3, 0), as<T>(c->t_xt), y, T(-1), as<T>(c->t_xhat), T(1), nullptr, nullptr, st, fs);
@@ -1128,6 +1134,8 @@ void check_solve_opts(const ns_solve_opts& o) {
     if (o.precision != NS_FP64 && o.precision != NS_FP32_INNER) throw Fail{NS_ERR_ARG, "unknown precision"};
     if (o.pc != NS_OUTER_SCR && o.pc != NS_OUTER_SIMPLE) throw Fail{NS_ERR_ARG, "unknown outer preconditioner"};
     if (o.pc_A != NS_PC_AMG && o.pc_A != NS_PC_JACOBI) throw Fail{NS_ERR_ARG, "unknown P_A"};
+    if (o.pc_I < 0 || o.pc_I > 2) throw Fail{NS_ERR_ARG, "unknown P of the inner A-solves"};
+    if (o.reserved != 0) throw Fail{NS_ERR_ARG, "reserved option field must be 0"};
     if (o.cheb_degree < 0 || o.cheb_degree > kMaxChebDegree || o.cheb_degree_S < 0 ||
         o.cheb_degree_S > kMaxChebDegree)
         throw Fail{NS_ERR_ARG, "Chebyshev degree out of range [1, 8]"};

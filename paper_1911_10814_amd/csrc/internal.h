@@ -208,6 +208,6 @@ struct ns_ctx {
     bool use_graphs = true;
     int xcd_mode = -1;           // XCD-contiguous row ranges: -1 by size, 0 off, 1 on
     // captured Arnoldi steps: (kind, system, precision, pc_A, degree, j) -> executable graph
-    std::map<std::tuple<int, int, int, int, int, int, int, int>, hipGraphExec_t> graphs;
+    std::map<std::tuple<int, int, int, int, int, int, int, int, int>, hipGraphExec_t> graphs;
     std::vector<double> ck_host;
 };

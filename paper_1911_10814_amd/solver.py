@@ -32,6 +32,7 @@ class SolveOptions:
     m_S: int = 200
     nmax_S: int = 200
     pc_A: str = "amg"            # "amg" | "jacobi"
+    pc_I: str | None = None      # P of the inner A-solves (Algorithm 2); None: as pc_A
     precision: str = "fp64"      # "fp64" | "fp32_inner"
     cheb_degree: int = 2
     cheb_degree_S: int = 0       # degree on the S_hat hierarchy (0: cheb_degree)
@@ -47,6 +48,7 @@ class SolveOptions:
                   "cheb_degree", "cheb_degree_S", "cheb_ratio", "cycles_S"):
             setattr(o, f, getattr(self, f))
         o.pc_A = {"amg": 0, "jacobi": 1}[self.pc_A]
+        o.pc_I = {None: 0, "amg": 1, "jacobi": 2}[self.pc_I]
         o.precision = {"fp64": 0, "fp32_inner": 1}[self.precision]
         o.pc = {"scr": 0, "simple": 1}[self.pc]
         keep = []

@@ -16,7 +16,8 @@
 * ``pa`` -- AMG against Jacobi for the A-solves: GMRES on A to delta_A = 1e-8
   with either preconditioner, and whole solves with the settings used for
   the patient-specific models (delta^r = 1e-2, delta_A = 1e-3,
-  delta_S = delta_I = 1e-2, m_A = m_S = n^max_A = n^max_S = 20).
+  delta_S = delta_I = 1e-2, m_A = m_S = n^max_A = n^max_S = 20), also with
+  AMG for the intermediate A-solves and Jacobi for the inner ones.
 * ``outlets`` -- many reduced-model outlets (the perforated plate: 784
   outlets, as many as the pulmonary model's): the Newton-step solve with all
   rank-one terms, and time steps of the predictor multi-corrector algorithm
@@ -134,10 +135,13 @@ def study_pa(a):
         print(json.dumps(dict(study="pa_solve_A", config=s.case.name, n_nodes=s.case.n_nodes,
                               precision=a.precision, pc_A=pc_A, rtol_A=1e-8, iterations=int(sched[0]),
                               wall_ms_incl_setup=round(best, 3))), flush=True)
-    for pc_A in ("jacobi", "amg"):
-        run(s, SolveOptions(precision=a.precision, pc_A=pc_A, rtol=1e-2, rtol_A=1e-3, rtol_S=1e-2, rtol_I=1e-2,
-                            m_A=20, m_S=20, nmax_A=20, nmax_S=20), a.repeat, study="pa_patient_settings")
-        run(s, SolveOptions(precision=a.precision, pc_A=pc_A), a.repeat, study="pa_default_settings")
+    # P_A for every A-solve, and AMG for the intermediate solves with Jacobi for the inner ones
+    for pc_A, pc_I in (("jacobi", None), ("amg", None), ("amg", "jacobi")):
+        run(s, SolveOptions(precision=a.precision, pc_A=pc_A, pc_I=pc_I, rtol=1e-2, rtol_A=1e-3, rtol_S=1e-2,
+                            rtol_I=1e-2, m_A=20, m_S=20, nmax_A=20, nmax_S=20), a.repeat,
+            study="pa_patient_settings", pc_I=pc_I)
+        run(s, SolveOptions(precision=a.precision, pc_A=pc_A, pc_I=pc_I), a.repeat, study="pa_default_settings",
+            pc_I=pc_I)
 
 
 def study_outlets(a):

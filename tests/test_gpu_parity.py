@@ -177,6 +177,20 @@ def test_separate_schur_smoother_degree_replay_matches_oracle(name):
     assert rel(xg.cpu().numpy(), xo) <= 1e-10
 
 
+@pytest.mark.parametrize("name", ["channel2", "pipe_tiny"])
+def test_jacobi_inner_solves_replay_matches_oracle(name):
+    """AMG for the intermediate A-solves, point Jacobi for the inner ones of
+    Algorithm 2 (the lighter inner preconditioner Sec. 4 recommends)."""
+    from paper_1911_10814_amd import SolveOptions
+    ctx = ctx_for(name)
+    S = get_assembled(name)
+    xo, info = oracle_solver(name, pc_I="jacobi").solve(S.rhs)
+    xg, gi = ctx.solve(ctx._rhs, SolveOptions(pc_I="jacobi", schedule=info["schedule"]))
+    assert rel(xg.cpu().numpy(), xo) <= 1e-10
+    xt, ti = ctx.solve(ctx._rhs, SolveOptions(pc_I="jacobi", precision="fp32_inner"))
+    assert ti["converged"] and rel(xt.cpu().numpy(), xo) <= 1e-6
+
+
 @pytest.mark.parametrize("name", CASES)
 def test_nested_solve_fp32_inner(name):
     from paper_1911_10814_amd import SolveOptions
