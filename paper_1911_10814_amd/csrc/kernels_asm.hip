@@ -26,23 +26,38 @@ inline unsigned grid_for(int64_t t) { return (unsigned)((t + kBlock - 1) / kBloc
 __device__ inline double nq(int q, int a) { return q == a ? QA : QB; }
 }  // namespace
 
+// One element per 16 lanes, one lane per (a, b) node pair: each lane
+// recomputes the element's geometry and quadrature-point state (cheap next to
+// a tangent block, and it keeps every array in registers with no
+// lane-dependent indexing), accumulates the (a, b) block over the four points
+// and, in lane (a, 0), the residual of node a.  The 16 lanes of an element
+// touch 16 distinct blocks and lanes (a, 0) four distinct residual rows, so the
+// colouring still makes every update race-free.
+constexpr int kPairs = 16;
+
+__device__ inline double pick(int a, double x0, double x1, double x2, double x3) {
+    return a == 0 ? x0 : a == 1 ? x1 : a == 2 ? x2 : x3;
+}
+
 __global__ __launch_bounds__(kBlock) void k_assemble_elements(AsmArgs g) {
-    const int s = g.E0 + blockIdx.x * kBlock + threadIdx.x;
-    if (s >= g.E0 + g.count) return;
+    const int64_t tid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (tid >= (int64_t)kPairs * g.count) return;
+    const int64_t s = g.E0 + tid / kPairs;
+    const int pair = (int)(tid % kPairs), a = pair >> 2, b = pair & 3;
     int t[4];
 #pragma unroll
-    for (int a = 0; a < 4; ++a) t[a] = g.tets[4 * (int64_t)s + a];
+    for (int c = 0; c < 4; ++c) t[c] = g.tets[4 * s + c];
     double X[4][3];
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int c = 0; c < 4; ++c)
 #pragma unroll
-        for (int i = 0; i < 3; ++i) X[a][i] = g.xyz[3 * (int64_t)t[a] + i];
+        for (int i = 0; i < 3; ++i) X[c][i] = g.xyz[3 * (int64_t)t[c] + i];
     double e[3][3];
 #pragma unroll
     for (int k = 0; k < 3; ++k)
 #pragma unroll
         for (int i = 0; i < 3; ++i) e[k][i] = X[k + 1][i] - X[0][i];
-    // rows of J^{-1} (J has columns e_k): (e1 x e2... ) / det
+    // rows of J^{-1} (J has columns e_k): cofactors / det
     double cr[3][3];
     cr[0][0] = e[1][1] * e[2][2] - e[1][2] * e[2][1];
     cr[0][1] = e[1][2] * e[2][0] - e[1][0] * e[2][2];
@@ -84,12 +99,12 @@ __global__ __launch_bounds__(kBlock) void k_assemble_elements(AsmArgs g) {
 
     double v[4][3], ac[4][3], p[4];
 #pragma unroll
-    for (int a = 0; a < 4; ++a) {
-        p[a] = g.p[t[a]];
+    for (int c = 0; c < 4; ++c) {
+        p[c] = g.p[t[c]];
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
-            v[a][i] = g.v[3 * (int64_t)t[a] + i];
-            ac[a][i] = g.vdot[3 * (int64_t)t[a] + i];
+            v[c][i] = g.v[3 * (int64_t)t[c] + i];
+            ac[c][i] = g.vdot[3 * (int64_t)t[c] + i];
         }
     }
     double gv[3][3], gp[3];
@@ -100,36 +115,48 @@ __global__ __launch_bounds__(kBlock) void k_assemble_elements(AsmArgs g) {
         for (int j = 0; j < 3; ++j) gv[i][j] = 0.0;
     }
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int c = 0; c < 4; ++c)
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
-            gp[j] += p[a] * gN[a][j];
+            gp[j] += p[c] * gN[c][j];
 #pragma unroll
-            for (int i = 0; i < 3; ++i) gv[i][j] += v[a][i] * gN[a][j];
+            for (int i = 0; i < 3; ++i) gv[i][j] += v[c][i] * gN[c][j];
         }
     const double div = gv[0][0] + gv[1][1] + gv[2][2];
     const double rho = g.rho, mu = g.mu, cm = g.c_m, cf = g.c_f;
     const double tconst = g.c_t / (g.dt * g.dt) + g.c_i * (mu / rho) * (mu / rho) * GG;
 
-    double Qv[4][3], Qvp[4][3], QtM[4], QtC[4];
-    double Rm[4][3], Rp[4];
+    // shape-function gradients of this lane's pair
+    double ga[3], gb[3];
 #pragma unroll
-    for (int a = 0; a < 4; ++a) {
-        Rp[a] = 0.0;
-#pragma unroll
-        for (int i = 0; i < 3; ++i) Rm[a][i] = 0.0;
+    for (int i = 0; i < 3; ++i) {
+        ga[i] = pick(a, gN[0][i], gN[1][i], gN[2][i], gN[3][i]);
+        gb[i] = pick(b, gN[0][i], gN[1][i], gN[2][i], gN[3][i]);
     }
-    // viscous term of the residual is constant per element
-    double visc[4][3];
+    // viscous term of the residual of node a (constant per element)
+    double visc[3];
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int i = 0; i < 3; ++i) {
+        double sum = 0.0;
 #pragma unroll
-        for (int i = 0; i < 3; ++i) {
-            double sum = 0.0;
+        for (int l = 0; l < 3; ++l) sum += ga[l] * (gv[i][l] + gv[l][i]);
+        visc[i] = mu * sum;
+    }
+    const double gNab = ga[0] * gb[0] + ga[1] * gb[1] + ga[2] * gb[2];
+    // (grad N_b . grad) v_i  = sum_l gN_b[l] gv[i][l]
+    double gbv[3];
 #pragma unroll
-            for (int l = 0; l < 3; ++l) sum += gN[a][l] * (gv[i][l] + gv[l][i]);
-            visc[a][i] = mu * sum;
-        }
+    for (int i = 0; i < 3; ++i) gbv[i] = gb[0] * gv[i][0] + gb[1] * gv[i][1] + gb[2] * gv[i][2];
+
+    double A[3][3], B[3], C[3], D = 0.0, Rm[3], Rp = 0.0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        B[i] = 0.0;
+        C[i] = 0.0;
+        Rm[i] = 0.0;
+#pragma unroll
+        for (int j = 0; j < 3; ++j) A[i][j] = 0.0;
+    }
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         double vq[3], aq[3], pq = 0.0;
@@ -139,13 +166,13 @@ __global__ __launch_bounds__(kBlock) void k_assemble_elements(AsmArgs g) {
             aq[i] = 0.0;
         }
 #pragma unroll
-        for (int a = 0; a < 4; ++a) {
-            const double N = nq(q, a);
-            pq += N * p[a];
+        for (int c = 0; c < 4; ++c) {
+            const double N = nq(q, c);
+            pq += N * p[c];
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
-                vq[i] += N * v[a][i];
-                aq[i] += N * ac[a][i];
+                vq[i] += N * v[c][i];
+                aq[i] += N * ac[c][i];
             }
         }
         double vGv = 0.0, conv[3];
@@ -164,108 +191,73 @@ __global__ __launch_bounds__(kBlock) void k_assemble_elements(AsmArgs g) {
         double vpgv[3];
 #pragma unroll
         for (int i = 0; i < 3; ++i) vpgv[i] = gv[i][0] * vp[0] + gv[i][1] * vp[1] + gv[i][2] * vp[2];
+
+        const double Na = nq(q, a), Nb = nq(q, b);
+        const double vgNa = vq[0] * ga[0] + vq[1] * ga[1] + vq[2] * ga[2];
+        const double vgNb = vq[0] * gb[0] + vq[1] * gb[1] + vq[2] * gb[2];
+        const double vpgNa = vp[0] * ga[0] + vp[1] * ga[1] + vp[2] * ga[2];
+        const double vpgNb = vp[0] * gb[0] + vp[1] * gb[1] + vp[2] * gb[2];
+        // residual of node a
 #pragma unroll
-        for (int a = 0; a < 4; ++a) {
-            const double N = nq(q, a);
-            const double vgN = vq[0] * gN[a][0] + vq[1] * gN[a][1] + vq[2] * gN[a][2];
-            const double vpgN = vp[0] * gN[a][0] + vp[1] * gN[a][1] + vp[2] * gN[a][2];
+        for (int i = 0; i < 3; ++i)
+            Rm[i] += w * (rho * Na * (aq[i] + conv[i]) - ga[i] * pq + visc[i] - rho * vp[i] * vgNa +
+                          rho * Na * vpgv[i] - rho * vp[i] * vpgNa - ga[i] * pp);
+        Rp += w * (Na * div - vpgNa);
+
+        // L_b (ij) = rho cm Nb d_ij + rho cf (d_ij v.gN_b + Nb d_j v_i): linearised rho(a + (v.grad)v)
+        double L[3][3];
 #pragma unroll
-            for (int i = 0; i < 3; ++i)
-                Rm[a][i] += w * (rho * N * (aq[i] + conv[i]) - gN[a][i] * pq + visc[a][i] - rho * vp[i] * vgN +
-                                 rho * N * vpgv[i] - rho * vp[i] * vpgN - gN[a][i] * pp);
-            Rp[a] += w * (N * div - vpgN);
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j)
+                L[i][j] = rho * cf * Nb * gv[i][j] + (i == j ? rho * (cm * Nb + cf * vgNb) : 0.0);
+        // column sums used by the fine-scale terms
+        double Lgv[3][3], LgNa[3];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            LgNa[j] = L[0][j] * ga[0] + L[1][j] * ga[1] + L[2][j] * ga[2];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) Lgv[i][j] = gv[i][0] * L[0][j] + gv[i][1] * L[1][j] + gv[i][2] * L[2][j];
         }
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
-            Qv[q][i] = vq[i];
-            Qvp[q][i] = vp[i];
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                const double dij = (i == j) ? 1.0 : 0.0;
+                double val = Na * L[i][j];                                   // rho N_a (a + (v.grad)v)
+                val += mu * cf * (dij * gNab + ga[j] * gb[i]);               // 2 mu eps(w):eps(v)
+                val += rho * tM * L[i][j] * vgNa - rho * cf * vp[i] * Nb * ga[j];  // -rho v'_i (v.gN_a)
+                val += rho * Na * (-tM * Lgv[i][j] + cf * dij * vpgNb);      // rho N_a (v'.grad) v_i
+                val += rho * tM * (L[i][j] * vpgNa + vp[i] * LgNa[j]);       // -rho v'_i (v'.gN_a)
+                val += tC * cf * ga[i] * gb[j];                              // -d_i N_a p'
+                A[i][j] += w * val;
+            }
+            B[i] += w * (-cf * ga[i] * Nb +
+                         cf * rho * tM * (vgNa * gb[i] - Na * gbv[i] + gb[i] * vpgNa + vp[i] * gNab));
+            C[i] += w * (cf * Na * gb[i] + tM * LgNa[i]);
         }
-        QtM[q] = tM;
-        QtC[q] = tC;
+        D += w * cf * tM * gNab;
     }
+    if (b == 0) {
+        const int ta = a == 0 ? t[0] : a == 1 ? t[1] : a == 2 ? t[2] : t[3];
 #pragma unroll
-    for (int a = 0; a < 4; ++a) {
-#pragma unroll
-        for (int i = 0; i < 3; ++i) g.res[3 * (int64_t)t[a] + i] += Rm[a][i];
-        g.res[3 * (int64_t)g.N + t[a]] += Rp[a];
+        for (int i = 0; i < 3; ++i) g.res[3 * (int64_t)ta + i] += Rm[i];
+        g.res[3 * (int64_t)g.N + ta] += Rp;
     }
-
-    // tangent blocks, pair by pair
-    for (int a = 0; a < 4; ++a) {
-        for (int b = 0; b < 4; ++b) {
-            double A[3][3], B[3], C[3], D = 0.0;
+    double* blk = g.aos + 16 * (int64_t)g.emap[16 * s + pair];
 #pragma unroll
-            for (int i = 0; i < 3; ++i) {
-                B[i] = 0.0;
-                C[i] = 0.0;
+    for (int i = 0; i < 3; ++i) {
 #pragma unroll
-                for (int j = 0; j < 3; ++j) A[i][j] = 0.0;
-            }
-            const double gNab = gN[a][0] * gN[b][0] + gN[a][1] * gN[b][1] + gN[a][2] * gN[b][2];
-            // (grad N_b . grad) v_i  = sum_l gN[b][l] gv[i][l]
-            double gbv[3];
-#pragma unroll
-            for (int i = 0; i < 3; ++i) gbv[i] = gN[b][0] * gv[i][0] + gN[b][1] * gv[i][1] + gN[b][2] * gv[i][2];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const double Na = nq(q, a), Nb = nq(q, b);
-                const double tM = QtM[q], tC = QtC[q];
-                const double* vq = Qv[q];
-                const double* vp = Qvp[q];
-                const double vgNa = vq[0] * gN[a][0] + vq[1] * gN[a][1] + vq[2] * gN[a][2];
-                const double vgNb = vq[0] * gN[b][0] + vq[1] * gN[b][1] + vq[2] * gN[b][2];
-                const double vpgNa = vp[0] * gN[a][0] + vp[1] * gN[a][1] + vp[2] * gN[a][2];
-                const double vpgNb = vp[0] * gN[b][0] + vp[1] * gN[b][1] + vp[2] * gN[b][2];
-                // L_b (ij) = rho cm Nb d_ij + rho cf (d_ij v.gN_b + Nb d_j v_i): linearised rho(a + (v.grad)v)
-                double L[3][3];
-#pragma unroll
-                for (int i = 0; i < 3; ++i)
-#pragma unroll
-                    for (int j = 0; j < 3; ++j)
-                        L[i][j] = rho * cf * Nb * gv[i][j] + (i == j ? rho * (cm * Nb + cf * vgNb) : 0.0);
-                // column sums used by the fine-scale terms
-                double Lgv[3][3], LgNa[3];
-#pragma unroll
-                for (int j = 0; j < 3; ++j) {
-                    LgNa[j] = L[0][j] * gN[a][0] + L[1][j] * gN[a][1] + L[2][j] * gN[a][2];
-#pragma unroll
-                    for (int i = 0; i < 3; ++i) Lgv[i][j] = gv[i][0] * L[0][j] + gv[i][1] * L[1][j] + gv[i][2] * L[2][j];
-                }
-#pragma unroll
-                for (int i = 0; i < 3; ++i) {
-#pragma unroll
-                    for (int j = 0; j < 3; ++j) {
-                        const double dij = (i == j) ? 1.0 : 0.0;
-                        double val = Na * L[i][j];                                   // rho N_a (a + (v.grad)v)
-                        val += mu * cf * (dij * gNab + gN[a][j] * gN[b][i]);         // 2 mu eps(w):eps(v)
-                        val += rho * tM * L[i][j] * vgNa - rho * cf * vp[i] * Nb * gN[a][j];  // -rho v'_i (v.gN_a)
-                        val += rho * Na * (-tM * Lgv[i][j] + cf * dij * vpgNb);      // rho N_a (v'.grad) v_i
-                        val += rho * tM * (L[i][j] * vpgNa + vp[i] * LgNa[j]);       // -rho v'_i (v'.gN_a)
-                        val += tC * cf * gN[a][i] * gN[b][j];                        // -d_i N_a p'
-                        A[i][j] += w * val;
-                    }
-                    B[i] += w * (-cf * gN[a][i] * Nb +
-                                 cf * rho * tM * (vgNa * gN[b][i] - Na * gbv[i] + gN[b][i] * vpgNa + vp[i] * gNab));
-                    C[i] += w * (cf * Na * gN[b][i] + tM * LgNa[i]);
-                }
-                D += w * cf * tM * gNab;
-            }
-            double* blk = g.aos + 16 * (int64_t)g.emap[16 * (int64_t)s + 4 * a + b];
-#pragma unroll
-            for (int i = 0; i < 3; ++i) {
-#pragma unroll
-                for (int j = 0; j < 3; ++j) blk[4 * i + j] += A[i][j];
-                blk[4 * i + 3] += B[i];
-                blk[12 + i] += C[i];
-            }
-            blk[15] += D;
-        }
+        for (int j = 0; j < 3; ++j) blk[4 * i + j] += A[i][j];
+        blk[4 * i + 3] += B[i];
+        blk[12 + i] += C[i];
     }
+    blk[15] += D;
 }
 
 void assemble_elements(const AsmArgs& a, hipStream_t st) {
     if (a.count <= 0) return;
-    hipLaunchKernelGGL(k_assemble_elements, dim3(grid_for(a.count)), dim3(kBlock), 0, st, a);
+    hipLaunchKernelGGL(k_assemble_elements, dim3(grid_for((int64_t)kPairs * a.count)), dim3(kBlock), 0, st, a);
 }
 
 // Backflow term -rho beta (v.n)_- N_a v_i on outlet triangles (3-point rule,
