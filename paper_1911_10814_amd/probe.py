@@ -32,10 +32,12 @@ def main():
     from paper_1911_10814_amd import NsContext, SolveOptions
 
     case = build(args.config)
+    print(f"[probe] {args.config}: {case.n_nodes} nodes built", file=sys.stderr, flush=True)
     ctx = NsContext(case).bind()
     Q = ctx.outlet_flow(case.v)
     ctx.assemble(case.v, case.p, case.vdot, rho=case.rho, mu=case.mu, dt=case.dt, rho_inf=case.rho_inf,
                  m=case.R, P_af=case.R * Q)
+    print("[probe] bound and assembled", file=sys.stderr, flush=True)
     o = SolveOptions(precision=args.precision)
     x3 = torch.as_tensor(np.random.default_rng(0).standard_normal(3 * case.n_nodes), device="cuda")
     for _ in range(args.reps):
