@@ -1080,29 +1080,31 @@ __global__ void k_galerkin(int64_t nq, int np_r, int np_c, const int32_t* gptr, 
                            const double* vf, int64_t frs, int64_t fcs, double* vc, int64_t crs, int64_t ccs,
                            const int32_t* qrow, const int32_t* ccol, const double* dextra, const int32_t* aptr,
                            const int32_t* anodes) {
-    const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (q >= nq) return;
+    // one thread per (plane, coarse value): the planes of a value are
+    // independent sums, so they run side by side (the coarsest levels have few
+    // values, each gathered from many fine ones)
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= nq * np_r * np_c) return;
+    const int plane = (int)(t / nq);
+    const int64_t q = t % nq;
+    const int r = plane / np_c, c = plane % np_c;
     const int t0 = gptr[q], t1 = gptr[q + 1];
-    const bool on_diag = dextra && qrow[q] == ccol[q];
-    for (int r = 0; r < np_r; ++r)
-        for (int c = 0; c < np_c; ++c) {
-            double s = 0.0;
-            const double* p = vf + r * frs + c * fcs;
-            for (int t = t0; t < t1; ++t) s += p[gidx[t]];
-            if (on_diag && r == c) {
-                const int I = qrow[q];
-                for (int a = aptr[I]; a < aptr[I + 1]; ++a) s += dextra[(int64_t)np_r * anodes[a] + r];
-            }
-            vc[r * crs + c * ccs + q] = s;
-        }
+    double s = 0.0;
+    const double* p = vf + r * frs + c * fcs;
+    for (int k = t0; k < t1; ++k) s += p[gidx[k]];
+    if (dextra && r == c && qrow[q] == ccol[q]) {
+        const int I = qrow[q];
+        for (int a = aptr[I]; a < aptr[I + 1]; ++a) s += dextra[(int64_t)np_r * anodes[a] + r];
+    }
+    vc[r * crs + c * ccs + q] = s;
 }
 void galerkin(int64_t nq, int np_r, int np_c, const int32_t* gptr, const int32_t* gidx, const double* vf,
               int64_t frs, int64_t fcs, double* vc, int64_t crs, int64_t ccs, const int32_t* qrow,
               const int32_t* ccol, const double* dextra, const int32_t* aptr, const int32_t* anodes,
               hipStream_t st) {
     if (nq <= 0) return;
-    hipLaunchKernelGGL(k_galerkin, dim3(grid_for(nq)), dim3(kBlock), 0, st, nq, np_r, np_c, gptr, gidx, vf, frs,
-                       fcs, vc, crs, ccs, qrow, ccol, dextra, aptr, anodes);
+    hipLaunchKernelGGL(k_galerkin, dim3(grid_for(nq * np_r * np_c)), dim3(kBlock), 0, st, nq, np_r, np_c, gptr,
+                       gidx, vf, frs, fcs, vc, crs, ccs, qrow, ccol, dextra, aptr, anodes);
 }
 
 __global__ void k_block_dinv(int n, int bs, const int32_t* rp, const int32_t* col, const double* v, int64_t rs,
@@ -1123,37 +1125,114 @@ void block_dinv(int n, int bs, const int32_t* rp, const int32_t* col, const doub
 }
 
 // S_hat_ij = D_ij - sum_{k in N(i)} sum_c C_{i,k,c} B_{k,j,c} / diag(A)_{3k+c}
-// one wavefront per row i, lanes over the entries of row i of S_hat.
+//
+// 16 lanes per row i.  The row's S_hat columns and accumulators sit in LDS;
+// lane t first loads neighbour k_t = col[r0 + t] (its row range, C_{i,k,:} and
+// diag(A)^{-1}_k) and seeds the entry j = k_t with D_ij.  Then, for the
+// neighbours in column order, the lanes take the blocks (k, j) of row k, find
+// j among the row's S_hat columns (binary search in LDS) and subtract the
+// three products.  The lanes of one step hold distinct j and the steps follow
+// the row's column order, so every entry sees the same operations in the
+// same order as a loop over k per entry; each step costs one round of
+// coalesced loads of row k instead of a binary search in global memory per
+// entry and neighbour.  Rows with more than kShatLds S_hat entries or more
+// than kShatW neighbours take that per-entry loop.
+constexpr int kShatW = 16;
+constexpr int kShatLds = 128;
+constexpr int kShatRows = kBlock / kShatW;
+
+__device__ inline int lds_lower_bound(const int32_t* a, int n, int key) {
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (a[mid] < key) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
 __global__ __launch_bounds__(kBlock) void k_shat(int n, const int32_t* __restrict__ rp,
                                                  const int32_t* __restrict__ col, const double* __restrict__ V,
                                                  int64_t nnzb, const double* __restrict__ dinvA,
                                                  const int32_t* __restrict__ srp, const int32_t* __restrict__ scol,
                                                  double* __restrict__ shat) {
-    const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int l = threadIdx.x & 63;
+    __shared__ int32_t lcol[kShatRows][kShatLds];
+    __shared__ double lacc[kShatRows][kShatLds];
+    const int g = threadIdx.x / kShatW, lane = threadIdx.x % kShatW;
+    const int row = blockIdx.x * kShatRows + g;
+    // whole 16-lane groups leave together; no barrier spans groups
     if (row >= n) return;
-    const int r0 = rp[row], r1 = rp[row + 1];
-    for (int e = srp[row] + l; e < srp[row + 1]; e += 64) {
-        const int j = scol[e];
-        double s = 0.0;
-        const int pd = lower_bound_dev(col, r0, r1, j);
-        if (pd < r1 && col[pd] == j) s = V[15 * nnzb + pd];
-        for (int q = r0; q < r1; ++q) {
-            const int k = col[q];
-            const int k0 = rp[k], k1 = rp[k + 1];
-            const int p2 = lower_bound_dev(col, k0, k1, j);
-            if (p2 < k1 && col[p2] == j) {
+    const int r0 = rp[row], r1 = rp[row + 1], nq = r1 - r0;
+    const int s0 = srp[row], ns = srp[row + 1] - s0;
+    if (ns > kShatLds || nq > kShatW) {
+        for (int e = s0 + lane; e < s0 + ns; e += kShatW) {
+            const int j = scol[e];
+            double s = 0.0;
+            const int pd = lower_bound_dev(col, r0, r1, j);
+            if (pd < r1 && col[pd] == j) s = V[15 * nnzb + pd];
+            for (int q = r0; q < r1; ++q) {
+                const int k = col[q];
+                const int k0 = rp[k], k1 = rp[k + 1];
+                const int p2 = lower_bound_dev(col, k0, k1, j);
+                if (p2 < k1 && col[p2] == j) {
 #pragma unroll
-                for (int c = 0; c < 3; ++c)
-                    s -= V[(12 + c) * nnzb + q] * V[(4 * c + 3) * nnzb + p2] * dinvA[3 * (int64_t)k + c];
+                    for (int c = 0; c < 3; ++c)
+                        s -= V[(12 + c) * nnzb + q] * V[(4 * c + 3) * nnzb + p2] * dinvA[3 * (int64_t)k + c];
+                }
+            }
+            shat[e] = s;
+        }
+        return;
+    }
+    int32_t* lc = lcol[g];
+    double* la = lacc[g];
+    for (int e = lane; e < ns; e += kShatW) {
+        lc[e] = scol[s0 + e];
+        la[e] = 0.0;
+    }
+    __builtin_amdgcn_wave_barrier();
+    int k0 = 0, k1 = 0;
+    double c0 = 0.0, c1 = 0.0, c2 = 0.0, d0 = 0.0, d1 = 0.0, d2 = 0.0;
+    if (lane < nq) {
+        const int q = r0 + lane;
+        const int k = col[q];
+        k0 = rp[k];
+        k1 = rp[k + 1];
+        c0 = V[12 * nnzb + q];
+        c1 = V[13 * nnzb + q];
+        c2 = V[14 * nnzb + q];
+        d0 = dinvA[3 * (int64_t)k];
+        d1 = dinvA[3 * (int64_t)k + 1];
+        d2 = dinvA[3 * (int64_t)k + 2];
+        const double dij = V[15 * nnzb + q];
+        const int e = lds_lower_bound(lc, ns, k);
+        if (e < ns && lc[e] == k) la[e] = dij;
+    }
+    __builtin_amdgcn_wave_barrier();
+    for (int t = 0; t < nq; ++t) {
+        const int kb = __shfl(k0, t, kShatW), ke = __shfl(k1, t, kShatW);
+        const double C0 = __shfl(c0, t, kShatW), C1 = __shfl(c1, t, kShatW), C2 = __shfl(c2, t, kShatW);
+        const double D0 = __shfl(d0, t, kShatW), D1 = __shfl(d1, t, kShatW), D2 = __shfl(d2, t, kShatW);
+        for (int p2 = kb + lane; p2 < ke; p2 += kShatW) {
+            const int j = col[p2];
+            const double b0 = V[3 * nnzb + p2], b1 = V[7 * nnzb + p2], b2 = V[11 * nnzb + p2];
+            const int e = lds_lower_bound(lc, ns, j);
+            if (e < ns && lc[e] == j) {
+                double s = la[e];
+                s -= C0 * b0 * D0;
+                s -= C1 * b1 * D1;
+                s -= C2 * b2 * D2;
+                la[e] = s;
             }
         }
-        shat[e] = s;
+        __builtin_amdgcn_wave_barrier();
     }
+    for (int e = lane; e < ns; e += kShatW) shat[s0 + e] = la[e];
 }
 void shat_numeric(int n, const int32_t* rp, const int32_t* col, const double* V, int64_t nnzb, const double* dinvA,
                   const int32_t* srp, const int32_t* scol, double* shat, hipStream_t st) {
-    hipLaunchKernelGGL(k_shat, dim3((n + 3) / 4), dim3(kBlock), 0, st, n, rp, col, V, nnzb, dinvA, srp, scol, shat);
+    hipLaunchKernelGGL(k_shat, dim3((n + kShatRows - 1) / kShatRows), dim3(kBlock), 0, st, n, rp, col, V, nnzb,
+                       dinvA, srp, scol, shat);
 }
 
 // Dense copy of a block-sparse matrix into the left half of work [n][2n]
@@ -1281,8 +1360,8 @@ struct GjPanel {
 
 __global__ __launch_bounds__(kBlock) void k_gj_panel(GjPanel a, int k0) {
     extern __shared__ double lds[];
-    __shared__ double sval[kBlock];
-    __shared__ int sidx[kBlock];
+    __shared__ double sval[kBlock / 64];
+    __shared__ int sidx[kBlock / 64];
     __shared__ double prow[kGjPanel + kGjSlab];  // scaled pivot row (old row p)
     __shared__ double rowk[kGjPanel + kGjSlab];  // old row k
     const int m = (int)blockIdx.x < a.blocks0 ? 0 : 1;
@@ -1318,21 +1397,29 @@ __global__ __launch_bounds__(kBlock) void k_gj_panel(GjPanel a, int k0) {
                 bi = q;
             }
         }
-        sval[tid] = best;
-        sidx[tid] = bi;
-        __syncthreads();
-        for (int s = kBlock / 2; s > 0; s >>= 1) {
-            if (tid < s) {
-                const double o = sval[tid + s];
-                const int oi = sidx[tid + s];
-                if (o > sval[tid] || (o == sval[tid] && oi < sidx[tid])) {
-                    sval[tid] = o;
-                    sidx[tid] = oi;
-                }
+        // pivot: the largest |value|, the smallest row among equal ones (a total
+        // order, so the wavefront butterflies and the 4-way merge find the
+        // same row as any reduction order)
+        for (int off = 32; off > 0; off >>= 1) {
+            const double o = __shfl_xor(best, off, 64);
+            const int oi = __shfl_xor(bi, off, 64);
+            if (o > best || (o == best && oi < bi)) {
+                best = o;
+                bi = oi;
             }
-            __syncthreads();
         }
-        const int p = sidx[0];
+        if ((tid & 63) == 0) {
+            sval[tid >> 6] = best;
+            sidx[tid >> 6] = bi;
+        }
+        __syncthreads();
+        double pb = sval[0];
+        int p = sidx[0];
+        for (int w = 1; w < kBlock / 64; ++w)
+            if (sval[w] > pb || (sval[w] == pb && sidx[w] < p)) {
+                pb = sval[w];
+                p = sidx[w];
+            }
         const double inv_p = 1.0 / pan[p * kGjPanel + t];
         if (tid < kGjPanel) {
             prow[tid] = pan[p * kGjPanel + tid] * inv_p;
