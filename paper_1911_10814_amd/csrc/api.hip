@@ -357,7 +357,9 @@ void read_status(ns_ctx* c, const double* d_status, int n, hipStream_t st) {
 // [9 + kind] initial residual norm of a left GMRES call of that kind
 constexpr int kMapStatus = 0, kMapNorm = 8, kMapNorm0 = 9;
 // graph kinds of Arnoldi steps (one mapped initial-norm slot each)
-constexpr int kKindA = 0, kKindS = 1, kKindOuter = 2, kKindShat = 3, kKindInner = 4;
+constexpr int kKindA = 0, kKindS = 1, kKindOuter = 2, kKindShat = 3, kKindInner = 4, kKindSetup = 5;
+// meshes up to this many nodes replay captured graphs by default
+constexpr int kGraphMaxNodes = 1024;
 
 template <typename T>
 double dev_norm(ns_ctx* c, int64_t n, const T* x, double* slot, hipStream_t st) {
@@ -365,6 +367,33 @@ double dev_norm(ns_ctx* c, int64_t n, const T* x, double* slot, hipStream_t st) 
     check_launch();
     HIPCHK(hipStreamSynchronize(st));
     return static_cast<volatile double*>(c->h_mapped)[kMapNorm];
+}
+
+// Launch the executable graph cached under `key` on `st`; the first time,
+// capture `body` on `st` into it (thread-local capture, so only this thread's
+// calls are restricted).  The bodies record no memset nodes.
+template <typename F>
+void launch_cached(ns_ctx* c, const ns_ctx::GraphKey& key, hipStream_t st, F&& body) {
+    auto it = c->graphs.find(key);
+    if (it == c->graphs.end()) {
+        HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        try {
+            body();
+        } catch (...) {
+            hipGraph_t g = nullptr;
+            (void)hipStreamEndCapture(st, &g);
+            if (g) (void)hipGraphDestroy(g);
+            throw;
+        }
+        hipGraph_t g = nullptr;
+        HIPCHK(hipStreamEndCapture(st, &g));
+        hipGraphExec_t ex = nullptr;
+        hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        HIPCHK(e);
+        it = c->graphs.emplace(key, ex).first;
+    }
+    HIPCHK(hipGraphLaunch(it->second, st));
 }
 
 // Run one Arnoldi-step body, captured once into a HIP graph per
@@ -380,28 +409,23 @@ void run_step(ns_ctx* c, const Ctl& K, int kind, int j, F&& body) {
     }
     const int sys = K.sy == &c->sys[0] ? 0 : 1;
     const int degA = dflt(K.o.cheb_degree, kDefaultChebDegree);
-    const auto key = std::make_tuple(kind, sys, K.o.precision, K.o.pc_A, K.o.pc_I, degA,
-                                     dflt(K.o.cheb_degree_S, degA), dflt(K.o.cycles_S, kDefaultCyclesS), j);
-    auto it = c->graphs.find(key);
-    if (it == c->graphs.end()) {
-        HIPCHK(hipStreamBeginCapture(K.st, hipStreamCaptureModeThreadLocal));
-        try {
-            body();
-        } catch (...) {
-            hipGraph_t g = nullptr;
-            (void)hipStreamEndCapture(K.st, &g);
-            if (g) (void)hipGraphDestroy(g);
-            throw;
-        }
-        hipGraph_t g = nullptr;
-        HIPCHK(hipStreamEndCapture(K.st, &g));
-        hipGraphExec_t ex = nullptr;
-        hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(g);
-        HIPCHK(e);
-        it = c->graphs.emplace(key, ex).first;
+    const ns_ctx::GraphKey key(kind, sys, K.o.precision, K.o.pc_A, K.o.pc_I, degA, dflt(K.o.cheb_degree_S, degA),
+                               dflt(K.o.cycles_S, kDefaultCyclesS), j);
+    launch_cached(c, key, K.st, body);
+}
+
+// Run one chain of the per-step set-up on stream `st`, captured once per
+// (system, chain) and replayed for every later tangent: queued kernel by
+// kernel, the set-up's ~300 launches keep the host busier than the device,
+// and a replayed chain costs one graph launch.  The chains' pointers and
+// sizes are fixed for the context and their inputs are in device memory.
+template <typename F>
+void run_chain(ns_ctx* c, int sys, int chain, hipStream_t st, F&& body) {
+    if (!c->use_graphs) {
+        body();
+        return;
     }
-    HIPCHK(hipGraphLaunch(it->second, K.st));
+    launch_cached(c, ns_ctx::GraphKey(kKindSetup, sys, 0, 0, 0, 0, 0, 0, chain), st, body);
 }
 
 template <typename T>
@@ -958,13 +982,13 @@ void smoother_bound_dev(ns_ctx* c, const BlockOp<double>& M, int bs, const doubl
 double smoother_bound_host(const double* v) { return std::min(v[2], kPowerSafety * (v[0] / v[1])); }
 
 // Numeric per-step set-up on the device: diag(A) with the lumped rank-one
-// diagonal, then two independent chains -- the A hierarchy (Galerkin levels,
-// then its coarsest inverse) on aux[0] and the S_hat hierarchy (S_hat, its
-// Galerkin levels, its coarsest inverse) on `st` -- and the smoother-bound
-// power iterations of each hierarchy on a stream of their own (aux[1] for A,
-// aux[2] for S_hat) once its operators exist.  Every chain works in buffers of
-// its own level (the power iterations: the level's x0, r and b as iterates and
-// reduction partials); all streams rejoin `st` at the end.
+// diagonal, then independent chains on four streams -- S_hat, its Galerkin
+// levels and coarsest inverse on `st`; the A hierarchy's Galerkin levels and
+// coarsest inverse on aux[0]; the smoother-bound power iterations of the A
+// levels on aux[1], of the finest S_hat level on aux[2] (as soon as S_hat
+// exists) and of the coarser S_hat levels on aux[3].  Every chain works in
+// buffers of its own level (the power iterations: the level's x0, r and b as
+// iterates and reduction partials); all streams rejoin `st` at the end.
 void setup_device(ns_ctx* c, SystemDev& y, hipStream_t st) {
     const Symbolic& S = c->sym;
     const int N = S.N;
@@ -974,7 +998,7 @@ void setup_device(ns_ctx* c, SystemDev& y, hipStream_t st) {
     rank_one_diag((int)S.onode.size(), c->d_onode, c->d_oid, c->d_a_msk, c->d_ck, y.dK64, st);
     block_dinv(N, 3, c->d_rp, c->d_col, y.V64, 4 * nnzb, nnzb, y.dK64, y.dinvA64, y.diagA64, st);
     double* bnd = c->d_bnd;
-    hipStream_t sA = c->aux[0], sAp = c->aux[1], sSp = c->aux[2];
+    hipStream_t sA = c->aux[0], sAp = c->aux[1], sSp = c->aux[2], sSc = c->aux[3];
     HIPCHK(hipEventRecord(c->fork_ev, st));
     HIPCHK(hipStreamWaitEvent(sA, c->fork_ev, 0));
     auto bounds = [&](int h, int l0, int l1, hipStream_t ps) {  // levels l0 <= l < l1, smoothed ones only
@@ -998,42 +1022,64 @@ void setup_device(ns_ctx* c, SystemDev& y, hipStream_t st) {
         dense_from_csr(d.n, d.bs, d.rp, d.col, d.v64, d.rstride, d.cstride, d.dextra64, d.work, cs);
         gauss_jordan_inverse2(d.n * d.bs, d.work, d.inv, 0, nullptr, nullptr, cs);
     };
-    // S_hat first: the longest kernel of the set-up, so it is queued before the A chain
+    // The chains are queued in the order in which they can start on the
+    // device: S_hat and the finest S_hat diagonal, the A Galerkin levels, then
+    // the finest S_hat level's power iterations (the longest chain), the A
+    // coarsest inverse, the A power iterations, and last the S_hat Galerkin
+    // levels with their power iterations and coarsest inverse.  A chain with
+    // no kernels (hierarchies of one or two levels) is skipped.
+    const int sys = &y == &c->sys[0] ? 0 : 1;
+    auto chain = [&](int id, bool nonempty, hipStream_t cs, auto&& body) {
+        if (nonempty) run_chain(c, sys, id, cs, body);
+    };
     shat_numeric(N, c->d_rp, c->d_col, y.V64, nnzb, y.dinvA64, c->d_srp, c->d_scol, y.shat64, st);
-    for (int l = 1; l < L; ++l) {
-        AmgLevelDev& f = y.A[l - 1];
-        AmgLevelDev& a = y.A[l];
-        galerkin(a.nnz, 3, 3, a.gptr, a.gidx, f.v64, f.rstride, f.cstride, a.v64, a.rstride, a.cstride, a.qrow,
-                 a.col, l == 1 ? y.dK64 : nullptr, f.aptr, f.anodes, sA);
-        block_dinv(a.n, 3, a.rp, a.col, a.v64, a.rstride, a.cstride, nullptr, a.dinv64, nullptr, sA);
-    }
-    HIPCHK(hipEventRecord(c->aux_ev[0], sA));
-    HIPCHK(hipStreamWaitEvent(sAp, c->aux_ev[0], 0));
-    bounds(0, 0, L, sAp);
-    coarsest(y.A, sA);
     block_dinv(N, 1, c->d_srp, c->d_scol, y.shat64, 0, 0, nullptr, y.S[0].dinv64, nullptr, st);
-    // the finest S_hat level's power iterations start as soon as S_hat exists
     HIPCHK(hipEventRecord(c->aux_ev[3], st));
     HIPCHK(hipStreamWaitEvent(sSp, c->aux_ev[3], 0));
-    bounds(1, 0, 1, sSp);
-    for (int l = 1; l < L; ++l) {
-        AmgLevelDev& fs = y.S[l - 1];
-        AmgLevelDev& s = y.S[l];
-        galerkin(s.nnz, 1, 1, s.gptr, s.gidx, fs.v64, 0, 0, s.v64, 0, 0, nullptr, s.col, nullptr, nullptr,
-                 nullptr, st);
-        block_dinv(s.n, 1, s.rp, s.col, s.v64, 0, 0, nullptr, s.dinv64, nullptr, st);
-    }
+    chain(0, L > 1, sA, [&] {
+        for (int l = 1; l < L; ++l) {
+            AmgLevelDev& f = y.A[l - 1];
+            AmgLevelDev& a = y.A[l];
+            galerkin(a.nnz, 3, 3, a.gptr, a.gidx, f.v64, f.rstride, f.cstride, a.v64, a.rstride, a.cstride,
+                     a.qrow, a.col, l == 1 ? y.dK64 : nullptr, f.aptr, f.anodes, sA);
+            block_dinv(a.n, 3, a.rp, a.col, a.v64, a.rstride, a.cstride, nullptr, a.dinv64, nullptr, sA);
+        }
+        check_launch();
+    });
+    HIPCHK(hipEventRecord(c->aux_ev[0], sA));
+    chain(1, L > 1, sSp, [&] { bounds(1, 0, 1, sSp); });
+    chain(2, true, sA, [&] {
+        coarsest(y.A, sA);
+        check_launch();
+    });
+    HIPCHK(hipStreamWaitEvent(sAp, c->aux_ev[0], 0));
+    chain(3, L > 1, sAp, [&] { bounds(0, 0, L, sAp); });
+    chain(4, L > 1, st, [&] {
+        for (int l = 1; l < L; ++l) {
+            AmgLevelDev& fs = y.S[l - 1];
+            AmgLevelDev& s = y.S[l];
+            galerkin(s.nnz, 1, 1, s.gptr, s.gidx, fs.v64, 0, 0, s.v64, 0, 0, nullptr, s.col, nullptr, nullptr,
+                     nullptr, st);
+            block_dinv(s.n, 1, s.rp, s.col, s.v64, 0, 0, nullptr, s.dinv64, nullptr, st);
+        }
+        check_launch();
+    });
     HIPCHK(hipEventRecord(c->aux_ev[1], st));
-    HIPCHK(hipStreamWaitEvent(sSp, c->aux_ev[1], 0));
-    bounds(1, 1, L, sSp);
-    coarsest(y.S, st);
+    HIPCHK(hipStreamWaitEvent(sSc, c->aux_ev[1], 0));
+    chain(5, L > 2, sSc, [&] { bounds(1, 1, L, sSc); });
+    chain(6, true, st, [&] {
+        coarsest(y.S, st);
+        check_launch();
+    });
     check_launch();
-    const hipStream_t joins[3] = {sA, sAp, sSp};
-    for (int k = 0; k < 3; ++k) {
+    const hipStream_t joins[4] = {sA, sAp, sSp, sSc};
+    for (int k = 0; k < 4; ++k) {
         HIPCHK(hipEventRecord(c->aux_ev[k], joins[k]));
         HIPCHK(hipStreamWaitEvent(st, c->aux_ev[k], 0));
     }
 }
+
+void convert32(ns_ctx* c, SystemDev& y, hipStream_t st);
 
 void setup_system(ns_ctx* c, SystemDev& y, bool need32, hipStream_t st) {
     const Symbolic& S = c->sym;
@@ -1041,8 +1087,8 @@ void setup_system(ns_ctx* c, SystemDev& y, bool need32, hipStream_t st) {
     const int64_t nnzb = S.g.nnz();
     const int L = (int)S.lv.size();
     if (!y.ready || y.version != c->version) {
-        // (captured into a graph, the ~700 launches replayed 1.4 ms slower than
-        // launched directly on the four streams)
+        // (one graph spanning all four streams replayed 1.4 ms slower than
+        // direct launches; a graph per stream's chain keeps the streams' overlap)
         setup_device(c, y, st);
         double* bnd = c->d_bnd;
         std::vector<double> hb(3 * 2 * (size_t)L);
@@ -1061,24 +1107,34 @@ void setup_system(ns_ctx* c, SystemDev& y, bool need32, hipStream_t st) {
         y.version = c->version;
     }
     if (need32 && !y.have32) {
-        convert<double, float>(nnzb * 16, y.V64, y.V32, st);
-        convert<double, float>(3 * (int64_t)N, y.dK64, y.dK32, st);
-        convert<double, float>(3 * (int64_t)N, y.dinvA64, y.dinvA32, st);
-        convert<double, float>(S.shat.nnz(), y.shat64, y.shat32, st);
-        for (int h = 0; h < 2; ++h) {
-            std::vector<AmgLevelDev>& H = h == 0 ? y.A : y.S;
-            for (int l = 0; l < L; ++l) {
-                AmgLevelDev& d = H[l];
-                if (l > 0) convert<double, float>(d.nnz * d.bs * d.bs, d.v64, d.v32, st);
-                if (!(h == 0 && l == 0)) convert<double, float>((int64_t)d.n * d.bs, d.dinv64, d.dinv32, st);
-            }
-        }
-        const int nslot = (int)S.onode.size();
-        convert<double, float>(3 * (int64_t)nslot, c->d_a_msk, c->d_a_msk32, st);
-        convert<double, float>(S.n_out, c->d_ck, c->d_ck32, st);
-        check_launch();
+        run_chain(c, &y == &c->sys[0] ? 0 : 1, 7, st, [&] { convert32(c, y, st); });
         y.have32 = true;
     }
+}
+
+// FP32 copies of the tangent planes, diagonals, S_hat, the AMG levels and
+// the rank-one data, for the FP32-inner solves
+void convert32(ns_ctx* c, SystemDev& y, hipStream_t st) {
+    const Symbolic& S = c->sym;
+    const int N = S.N;
+    const int64_t nnzb = S.g.nnz();
+    const int L = (int)S.lv.size();
+    convert<double, float>(nnzb * 16, y.V64, y.V32, st);
+    convert<double, float>(3 * (int64_t)N, y.dK64, y.dK32, st);
+    convert<double, float>(3 * (int64_t)N, y.dinvA64, y.dinvA32, st);
+    convert<double, float>(S.shat.nnz(), y.shat64, y.shat32, st);
+    for (int h = 0; h < 2; ++h) {
+        std::vector<AmgLevelDev>& H = h == 0 ? y.A : y.S;
+        for (int l = 0; l < L; ++l) {
+            AmgLevelDev& d = H[l];
+            if (l > 0) convert<double, float>(d.nnz * d.bs * d.bs, d.v64, d.v32, st);
+            if (!(h == 0 && l == 0)) convert<double, float>((int64_t)d.n * d.bs, d.dinv64, d.dinv32, st);
+        }
+    }
+    const int nslot = (int)S.onode.size();
+    convert<double, float>(3 * (int64_t)nslot, c->d_a_msk, c->d_a_msk32, st);
+    convert<double, float>(S.n_out, c->d_ck, c->d_ck32, st);
+    check_launch();
 }
 
 // Chebyshev coefficients of every smoothed level: interval
@@ -1265,6 +1321,9 @@ ns_status ns_ctx_bind(ns_ctx* c, void* ws, size_t bytes, hipStream_t st) {
         if (!ws || bytes < c->ws_bytes) throw Fail{NS_ERR_WORKSPACE, "workspace missing or too small"};
         if (reinterpret_cast<uintptr_t>(ws) % 256 != 0) throw Fail{NS_ERR_WORKSPACE, "workspace not 256-byte aligned"};
         HIPCHK(hipGetDevice(&c->device));
+        // captured graphs hold pointers into the previous workspace
+        for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+        c->graphs.clear();
         Arena A;
         A.base = static_cast<char*>(ws);
         layout(c, A);
@@ -1331,8 +1390,12 @@ ns_status ns_ctx_bind(ns_ctx* c, void* ws, size_t bytes, hipStream_t st) {
             if (!c->aux_ev[a]) HIPCHK(hipEventCreateWithFlags(&c->aux_ev[a], hipEventDisableTiming));
         }
         if (!c->fork_ev) HIPCHK(hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming));
-        const char* ng = getenv("NS_NO_GRAPHS");
-        c->use_graphs = !(ng && ng[0] == '1');
+        // Captured graphs pay off only where launches dominate: replayed, they
+        // ran 10-20 % faster than direct launches on meshes of ~700 nodes but
+        // 2-4 % slower from ~1600 nodes up (every measured mesh to 2e5 nodes).
+        // NS_GRAPHS=0/1 forces the choice.
+        const char* ng = getenv("NS_GRAPHS");
+        c->use_graphs = (ng && (ng[0] == '0' || ng[0] == '1')) ? ng[0] == '1' : S.N <= kGraphMaxNodes;
         const char* xr = getenv("NS_XCD_ROWS");
         c->xcd_mode = (xr && (xr[0] == '0' || xr[0] == '1')) ? xr[0] - '0' : -1;
         HIPCHK(hipStreamSynchronize(st));

@@ -207,7 +207,9 @@ struct ns_ctx {
     hipEvent_t fork_ev = nullptr;
     bool use_graphs = true;
     int xcd_mode = -1;           // XCD-contiguous row ranges: -1 by size, 0 off, 1 on
-    // captured Arnoldi steps: (kind, system, precision, pc_A, degree, j) -> executable graph
-    std::map<std::tuple<int, int, int, int, int, int, int, int, int>, hipGraphExec_t> graphs;
+    // captured Arnoldi steps, (kind, system, precision, pc_A, pc_I, degrees, cycles_S, j), and
+    // set-up chains, (set-up kind, system, 0 ..., chain) -> executable graph
+    using GraphKey = std::tuple<int, int, int, int, int, int, int, int, int>;
+    std::map<GraphKey, hipGraphExec_t> graphs;
     std::vector<double> ck_host;
 };

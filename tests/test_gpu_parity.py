@@ -304,27 +304,56 @@ def test_failure_statuses():
     _CTX.pop(name, None)
 
 
-def test_graph_replays_match_eager_launches(monkeypatch):
-    """The captured Arnoldi-step graphs give bitwise the same solve as launching
-    the same kernels one by one, on every replay, with eager work between."""
+@pytest.mark.parametrize("name", ["channel2", "plate_small"])
+def test_graph_replays_match_eager_launches(monkeypatch, name):
+    """The captured graphs (Arnoldi steps and set-up chains) give bitwise the
+    same solve as launching the same kernels one by one, on every replay, with
+    eager work between; both forms are forced, whichever the mesh size picks."""
     from paper_1911_10814_amd import NsContext, SolveOptions
-    name = "channel2"
     c = get_case(name)
     S = get_assembled(name)
-    monkeypatch.setenv("NS_NO_GRAPHS", "1")
+    monkeypatch.setenv("NS_GRAPHS", "0")
     eager = NsContext(c).bind()
-    monkeypatch.delenv("NS_NO_GRAPHS")
-    graph = ctx_for(name)
+    monkeypatch.setenv("NS_GRAPHS", "1")
+    graph = NsContext(c).bind()
+    monkeypatch.delenv("NS_GRAPHS")
     kw = dict(rho=c.rho, mu=c.mu, dt=c.dt, rho_inf=c.rho_inf, m=c.R, P_af=c.R * S.Q)
     r_e = eager.assemble(c.v, c.p, c.vdot, **kw)
     for prec in ("fp64", "fp32_inner"):
         xe, ie = eager.solve(r_e, SolveOptions(precision=prec))
         for rep in range(3):
-            graph._rhs = graph.assemble(c.v, c.p, c.vdot, **kw)
-            xg, ig = graph.solve(graph._rhs, SolveOptions(precision=prec))
+            r_g = graph.assemble(c.v, c.p, c.vdot, **kw)
+            xg, ig = graph.solve(r_g, SolveOptions(precision=prec))
             torch.cuda.synchronize()
             assert ig["schedule"] == ie["schedule"]
             assert torch.equal(xg, xe), (prec, rep)
     le, _ = eager.adjoint(r_e, SolveOptions())
-    lg, _ = graph.adjoint(graph._rhs, SolveOptions())
+    lg, _ = graph.adjoint(r_g, SolveOptions())
     assert torch.equal(le, lg)
+
+
+def test_rebind_to_a_new_workspace(monkeypatch):
+    """Binding a context to a new workspace drops the graphs captured against
+    the old one: after the rebind (the old workspace zeroed but still
+    allocated) the same tangent solves to bitwise the same result."""
+    from paper_1911_10814_amd import NsContext, SolveOptions
+    from paper_1911_10814_amd.solver import _ptr, _stream_handle
+    name = "channel2"
+    c = get_case(name)
+    S = get_assembled(name)
+    monkeypatch.setenv("NS_GRAPHS", "1")
+    ctx = NsContext(c).bind()
+    kw = dict(rho=c.rho, mu=c.mu, dt=c.dt, rho_inf=c.rho_inf, m=c.R, P_af=c.R * S.Q)
+    x1, i1 = ctx.solve(ctx.assemble(c.v, c.p, c.vdot, **kw), SolveOptions())
+    old = ctx.ws
+    ws2 = torch.empty_like(old)
+    ctx._check(ctx.lib.ns_ctx_bind(ctx.h, _ptr(ws2), ctx.workspace_bytes, _stream_handle(ctx.device)))
+    ctx.ws = ws2
+    monkeypatch.delenv("NS_GRAPHS")
+    old.zero_()
+    torch.cuda.synchronize()
+    x2, i2 = ctx.solve(ctx.assemble(c.v, c.p, c.vdot, **kw), SolveOptions())
+    torch.cuda.synchronize()
+    assert i2["schedule"] == i1["schedule"]
+    assert torch.equal(x1, x2)
+    del old
