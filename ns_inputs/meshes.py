@@ -67,6 +67,35 @@ def kuhn_box(nx: int, ny: int, nz: int, lx: float = 1.0, ly: float = 1.0, lz: fl
     return xyz, _orient(xyz, tets)
 
 
+def delaunay_box(nx: int, ny: int, nz: int, lx: float = 1.0, ly: float = 1.0, lz: float = 1.0,
+                 jitter: float = 0.3, seed: int = 0):
+    """Unstructured mesh of a box: the Delaunay tetrahedralisation of an
+    (nx+1)(ny+1)(nz+1) lattice whose points move by up to ``jitter`` lattice
+    spacings (boundary points only within their faces, so the boundary stays
+    the box surface).  Node degrees spread well beyond the Kuhn lattice's
+    (up to ~30 neighbours).  Flat tetrahedra that the triangulation leaves on
+    the planar faces are dropped; every lattice point stays a vertex."""
+    from scipy.spatial import Delaunay
+    L = np.array([lx, ly, lz])
+    h = L / np.array([nx, ny, nz])
+    xs = [np.linspace(0.0, L[a], n + 1) for a, n in enumerate((nx, ny, nz))]
+    Z, Y, X = np.meshgrid(xs[2], xs[1], xs[0], indexing="ij")
+    xyz = np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1).astype(np.float64)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    d = rng.uniform(-jitter, jitter, size=xyz.shape) * h
+    tol = 1e-12
+    on_face = (xyz < tol) | (xyz > L - tol)
+    d[on_face] = 0.0
+    xyz = xyz + d
+    tets = Delaunay(xyz).simplices.astype(np.int64)
+    p = xyz[tets]
+    vol = np.einsum("ei,ei->e", np.cross(p[:, 1] - p[:, 0], p[:, 2] - p[:, 0]), p[:, 3] - p[:, 0]) / 6.0
+    tets = tets[np.abs(vol) > 1e-9 * float(np.prod(h))]
+    if np.unique(tets).size != len(xyz):
+        raise ValueError("a lattice point is not a vertex of the triangulation")
+    return xyz, _orient(xyz, tets)
+
+
 # ----------------------------------------------------------------------------
 # Boundary faces
 # ----------------------------------------------------------------------------

@@ -18,7 +18,7 @@ from oracle import krylov as kr
 
 pytestmark = pytest.mark.gpu
 
-CASES = ["cube", "channel2", "pipe_tiny", "ybif_small", "conexp_small", "plate_small"]
+CASES = ["cube", "channel2", "pipe_tiny", "ybif_small", "conexp_small", "plate_small", "unstr_channel"]
 _CTX = {}
 _NS = {}
 

@@ -7,7 +7,7 @@ import pytest
 
 from ns_inputs import build, meshes
 
-SMALL = ["cube", "channel2", "pipe_tiny", "ybif_small", "conexp_small", "plate_small"]
+SMALL = ["cube", "channel2", "pipe_tiny", "ybif_small", "conexp_small", "plate_small", "unstr_channel"]
 
 
 def _faces(tets):
@@ -27,7 +27,8 @@ def test_mesh_conforming_and_oriented(name):
     assert len(np.unique(c.tets)) == c.n_nodes
 
 
-@pytest.mark.parametrize("name", ["channel2", "pipe_tiny", "ybif_small", "conexp_small", "plate_small"])
+@pytest.mark.parametrize("name", ["channel2", "pipe_tiny", "ybif_small", "conexp_small", "plate_small",
+                                  "unstr_channel"])
 def test_outlets_planar_outward_disjoint(name):
     c = build(name)
     bf = {tuple(f) for f in np.sort(meshes.boundary_faces(c.xyz, c.tets), axis=1)}
@@ -105,3 +106,30 @@ def test_plate_outlet_patches():
                                     axis=1).sum()
         n_quads = npch * (q + 1) + 1
         assert np.isclose(area, (q / n_quads) ** 2)
+
+
+def test_unstructured_channel_is_irregular_and_fills_the_box():
+    """The Delaunay channel fills [0,2]x[0,1]x[0,1] exactly, its boundary is
+    the box surface, and its node degrees exceed the Kuhn lattice's (so rows
+    longer than 16 blocks and S_hat rows of irregular length occur)."""
+    c = build("unstr_channel")
+    p = c.xyz[c.tets]
+    vol = np.einsum("ei,ei->e", np.cross(p[:, 1] - p[:, 0], p[:, 2] - p[:, 0]), p[:, 3] - p[:, 0]) / 6.0
+    assert abs(vol.sum() - 2.0) < 1e-12
+    fx = c.xyz[meshes.boundary_faces(c.xyz, c.tets)]
+    on = np.zeros(len(fx), bool)
+    for a, L in enumerate((2.0, 1.0, 1.0)):
+        on |= np.all(np.abs(fx[:, :, a]) < 1e-12, axis=1) | np.all(np.abs(fx[:, :, a] - L) < 1e-12, axis=1)
+    assert on.all()
+    nbr = [set() for _ in range(c.n_nodes)]
+    for t in c.tets:
+        for a in t:
+            nbr[a].update(t.tolist())
+    deg = np.array([len(s) for s in nbr])
+    assert deg.max() > 16 and deg.min() < 10
+    # the wall (every boundary node off the outlet interior) is no-slip
+    x, y, z = c.xyz.T
+    outlet_interior = (np.abs(x - 2.0) < 1e-12) & (y > 1e-12) & (y < 1 - 1e-12) & (z > 1e-12) & (z < 1 - 1e-12)
+    bnd = np.unique(meshes.boundary_faces(c.xyz, c.tets))
+    wall = np.setdiff1d(bnd, np.nonzero(outlet_interior)[0])
+    assert c.mask[wall, :3].all() and not c.mask[outlet_interior, :3].any()
