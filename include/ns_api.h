@@ -181,7 +181,12 @@ ns_status ns_ctx_create(const ns_mesh* mesh, const ns_ctx_opts* opts, ns_ctx** o
 /* ns_ctx_bind: lay out the caller-owned device workspace d_workspace
  * (>= workspace_bytes, 256-byte aligned) and upload the mesh, pattern and
  * maps on `stream`; computes the outlet vectors a^k_{Ai} = int N_A n_i
- * (Sec. 2.5).  The workspace must stay allocated until ns_ctx_destroy.
+ * (Sec. 2.5).  The workspace must stay allocated until ns_ctx_destroy or
+ * the next ns_ctx_bind (binding again moves the context to the new
+ * workspace; a tangent must then be assembled again before a solve).
+ * Meshes of up to 1024 nodes replay each Krylov step and set-up chain from
+ * a HIP graph captured on first use; larger ones launch directly (the
+ * environment variable NS_GRAPHS=0 or 1, read here, forces either form).
  * Errors: NS_ERR_WORKSPACE, NS_ERR_HIP. */
 ns_status ns_ctx_bind(ns_ctx* ctx, void* d_workspace, size_t bytes, hipStream_t stream);
 

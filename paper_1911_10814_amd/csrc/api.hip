@@ -1321,9 +1321,16 @@ ns_status ns_ctx_bind(ns_ctx* c, void* ws, size_t bytes, hipStream_t st) {
         if (!ws || bytes < c->ws_bytes) throw Fail{NS_ERR_WORKSPACE, "workspace missing or too small"};
         if (reinterpret_cast<uintptr_t>(ws) % 256 != 0) throw Fail{NS_ERR_WORKSPACE, "workspace not 256-byte aligned"};
         HIPCHK(hipGetDevice(&c->device));
-        // captured graphs hold pointers into the previous workspace
+        // a new workspace holds no tangent yet, and captured graphs hold
+        // pointers into the previous one
         for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
         c->graphs.clear();
+        c->assembled = false;
+        for (SystemDev& y : c->sys) {
+            y.ready = false;
+            y.have32 = false;
+            y.coef_deg = 0;
+        }
         Arena A;
         A.base = static_cast<char*>(ws);
         layout(c, A);

@@ -334,9 +334,10 @@ def test_graph_replays_match_eager_launches(monkeypatch, name):
 
 def test_rebind_to_a_new_workspace(monkeypatch):
     """Binding a context to a new workspace drops the graphs captured against
-    the old one: after the rebind (the old workspace zeroed but still
-    allocated) the same tangent solves to bitwise the same result."""
-    from paper_1911_10814_amd import NsContext, SolveOptions
+    the old one and the assembled tangent: a solve before the next assembly
+    is refused, and after it (the old workspace zeroed but still allocated)
+    the same tangent solves to bitwise the same result."""
+    from paper_1911_10814_amd import NsContext, NsError, SolveOptions
     from paper_1911_10814_amd.solver import _ptr, _stream_handle
     name = "channel2"
     c = get_case(name)
@@ -352,6 +353,9 @@ def test_rebind_to_a_new_workspace(monkeypatch):
     monkeypatch.delenv("NS_GRAPHS")
     old.zero_()
     torch.cuda.synchronize()
+    # the new workspace holds no tangent until one is assembled into it
+    with pytest.raises(NsError, match="NS_ERR_STATE"):
+        ctx.solve(torch.zeros_like(x1), SolveOptions())
     x2, i2 = ctx.solve(ctx.assemble(c.v, c.p, c.vdot, **kw), SolveOptions())
     torch.cuda.synchronize()
     assert i2["schedule"] == i1["schedule"]
