@@ -206,7 +206,7 @@ def test_nested_solve_fp32_inner(name):
     assert rel(x[:n3], xo[:n3]) <= 1e-6 and rel(x[n3:], xo[n3:]) <= 1e-6
 
 
-@pytest.mark.parametrize("name", ["channel2", "pipe_tiny"])
+@pytest.mark.parametrize("name", ["channel2", "pipe_tiny", "unstr_channel"])
 def test_adjoint_matches_oracle_and_dense(name):
     from paper_1911_10814_amd import SolveOptions
     ctx = ctx_for(name)

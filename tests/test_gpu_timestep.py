@@ -53,7 +53,7 @@ def inputs(name, rcr, seed=3):
 
 
 @pytest.mark.parametrize("name,rcr", [("cube", False), ("channel2", False), ("channel2", True),
-                                      ("pipe_tiny", False), ("plate_small", "meta")])
+                                      ("pipe_tiny", False), ("plate_small", "meta"), ("unstr_channel", True)])
 def test_time_step_matches_oracle(name, rcr):
     from paper_1911_10814_amd import SolveOptions
     c, y_n, ydot_n, model = inputs(name, rcr)
