@@ -100,36 +100,41 @@ __global__ __launch_bounds__(kBlock) void k_spmv(BlockOp<T> M, const T* __restri
     const int row = (int)(tid / W);
     const int lane = threadIdx.x % W;
     const bool valid = row < M.n;
-    // epilogue operands of the own row, loaded before the row loop (their
-    // latency overlaps the gathers)
+    // The row bounds, then the epilogue's own-row operands: loads only (no
+    // arithmetic or branch on a loaded value before the row loop), so they
+    // are all in flight together and the loop waits once; the rank-one
+    // term's dependent loads follow the loop.
+    int kb = 0, ke = 0;
+    if (valid) {
+        kb = M.rp[row];
+        ke = M.rp[row + 1];
+    }
     const bool out_lane = valid && lane < BR;
     const int64_t i = (int64_t)BR * row + lane;
-    T ext = 0, zi = 0, rsi = 1, fdi = 0, r1 = 0;
+    T dxi = 0, xii = 0, zi = 0, rsi = 1, fdv = 0;
+    int sl = -1;
     if (out_lane) {
-        if (M.dextra) ext = M.dextra[i] * x[i];
+        if (M.dextra) {
+            dxi = M.dextra[i];
+            xii = x[i];
+        }
         if (z) zi = z[i];
         if (rscale) rsi = rscale[i];
-        if (fs.x) fdi = fs.coef[0] * fs.dinv[i];
-        if (ro.slot_of) {
-            const int sl = ro.slot_of[row];
-            if (sl >= 0) r1 = ro.s[ro.oid[sl]] * ro.aval[3 * (int64_t)sl + lane];
-        }
+        if (fs.x) fdv = fs.dinv[i];
+        if (ro.slot_of) sl = ro.slot_of[row];
     }
     T acc[BR];
 #pragma unroll
     for (int r = 0; r < BR; ++r) acc[r] = 0;
-    if (valid) {
-        const int k1 = M.rp[row + 1];
-        for (int k = M.rp[row] + lane; k < k1; k += W) {
-            const int j = M.col[k];
-            T xj[BC];
+    for (int k = kb + lane; k < ke; k += W) {
+        const int j = M.col[k];
+        T xj[BC];
 #pragma unroll
-            for (int c = 0; c < BC; ++c) xj[c] = x[(int64_t)BC * j + c];
+        for (int c = 0; c < BC; ++c) xj[c] = x[(int64_t)BC * j + c];
 #pragma unroll
-            for (int r = 0; r < BR; ++r)
+        for (int r = 0; r < BR; ++r)
 #pragma unroll
-                for (int c = 0; c < BC; ++c) acc[r] += M.v[r * M.rs + c * M.cs + k] * xj[c];
-        }
+            for (int c = 0; c < BC; ++c) acc[r] += M.v[r * M.rs + c * M.cs + k] * xj[c];
     }
 #pragma unroll
     for (int off = W / 2; off > 0; off >>= 1)
@@ -140,14 +145,22 @@ __global__ __launch_bounds__(kBlock) void k_spmv(BlockOp<T> M, const T* __restri
 #pragma unroll
     for (int r = 1; r < BR; ++r)
         if (lane == r) s = acc[r];
-    if (M.dextra) s += ext;
-    if (ro.slot_of) s += r1;
+    {
+        // each extra term is rounded before it is added
+#pragma clang fp contract(off)
+        if (M.dextra) s += dxi * xii;
+        if (ro.slot_of) {
+            T r1 = 0;
+            if (sl >= 0) r1 = ro.s[ro.oid[sl]] * ro.aval[3 * (int64_t)sl + lane];
+            s += r1;
+        }
+    }
     T out = alpha * s;
     if (z) out += beta * zi;
     if (rscale) out *= rsi;
     y[i] = out;
     if (fs.x) {
-        const T di = fdi * out;
+        const T di = (fs.coef[0] * fdv) * out;
         fs.x[i] = di;
         fs.d[i] = di;
     }
@@ -728,25 +741,33 @@ __global__ __launch_bounds__(kBlock) void k_cheb_step(BlockOp<T> M, const T* __r
     const int row = (int)(tid / W);
     const int lane = threadIdx.x % W;
     const bool valid = row < M.n;
-    // the epilogue's own-row operands are loaded before the row loop, so their
-    // latency overlaps the gathers instead of following the reduction
+    // The epilogue's own-row operands are loaded before the row loop, so their
+    // latency overlaps the gathers instead of following the reduction: the
+    // aggregate of the row first (its coarse correction is one more load),
+    // then the row bounds and the rest, with no arithmetic on loaded values
+    // before the loop.
     const bool out_lane = valid && lane < BS;
     const int64_t i = (int64_t)BS * row + lane;
-    T xi = 0, ex = 0, bi = 0, dvi = 0, dprev = 0;
+    int ag = 0, kb = 0, ke = 0;
+    if (out_lane && agg) ag = agg[row];
+    if (valid) {
+        kb = M.rp[row];
+        ke = M.rp[row + 1];
+    }
+    T xi = 0, eci = 0, ex = 0, bi = 0, dvi = 0, dprev = 0;
     if (out_lane) {
         xi = xin[i];
-        if (agg) xi += ec[(int64_t)BS * agg[row] + lane];
         if (M.dextra) ex = M.dextra[i];
         bi = b[i];
         dvi = dinv[i];
         if (step != 0) dprev = d[i];
+        if (agg) eci = ec[(int64_t)BS * ag + lane];
     }
     T acc[BS];
 #pragma unroll
     for (int r = 0; r < BS; ++r) acc[r] = 0;
-    if (valid) {
-        const int k1 = M.rp[row + 1];
-        for (int k = M.rp[row] + lane; k < k1; k += W) {
+    {
+        for (int k = kb + lane; k < ke; k += W) {
             const int j = M.col[k];
             T xj[BS];
             if (agg) {
@@ -768,6 +789,7 @@ __global__ __launch_bounds__(kBlock) void k_cheb_step(BlockOp<T> M, const T* __r
 #pragma unroll
         for (int r = 0; r < BS; ++r) acc[r] += __shfl_xor(acc[r], off, W);
     if (!out_lane) return;
+    if (agg) xi += eci;
     T s = acc[0];
 #pragma unroll
     for (int r = 1; r < BS; ++r)
