@@ -360,6 +360,8 @@ constexpr int kMapStatus = 0, kMapNorm = 8, kMapNorm0 = 9;
 constexpr int kKindA = 0, kKindS = 1, kKindOuter = 2, kKindShat = 3, kKindInner = 4, kKindSetup = 5;
 // meshes up to this many nodes replay captured graphs by default
 constexpr int kGraphMaxNodes = 1024;
+// finest A levels from this many rows add the prolongated correction in a pass of its own
+constexpr int kProlongPassRows = 500000;
 
 template <typename T>
 double dev_norm(ns_ctx* c, int64_t n, const T* x, double* slot, hipStream_t st) {
@@ -730,8 +732,17 @@ struct Nested {
                               coefc, st);
         }
         vcycle(H, l + 1, as<T>(C.b), as<T>(C.x1));
-        // post-smoothing; the first step applies the prolongated correction
-        cheb(a, bb, 0, L.agg, as<T>(C.x1));
+        // post-smoothing; the first step applies the prolongated correction.
+        // On a large finest A level, where the step streams from HBM, the
+        // correction is added by a pass of its own instead: the fused step's
+        // per-block aggregate gather costs more than that pass there (the
+        // same addition either way).
+        if (tme && L.n >= kProlongPassRows) {
+            prolong_add<T>(L.n, bs, L.agg, as<T>(C.x1), a, st);
+            cheb(a, bb, 0, nullptr, nullptr);
+        } else {
+            cheb(a, bb, 0, L.agg, as<T>(C.x1));
+        }
         std::swap(a, bb);
         for (int s = 1; s < deg; ++s) {
             cheb(a, bb, s, nullptr, nullptr);
