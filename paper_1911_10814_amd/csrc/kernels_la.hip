@@ -850,11 +850,15 @@ __global__ __launch_bounds__(kBlock) void k_sfact_bt(int n, const int32_t* __res
     const int lane = threadIdx.x % W;
     const bool valid = row < n;
     const int64_t i = 3 * (int64_t)row + lane;
+    int kb = 0, ke = 0;
+    if (valid) {
+        kb = rp[row];
+        ke = rp[row + 1];
+    }
     const T dai = (valid && lane < 3) ? dinvA[i] : T(0);  // loaded ahead of the row loop
     T acc[3] = {0, 0, 0};
-    if (valid) {
-        const int k1 = rp[row + 1];
-        for (int k = rp[row] + lane; k < k1; k += W) {
+    {
+        for (int k = kb + lane; k < ke; k += W) {
             const int j = col[k];
             T xj = x[j];
             if (agg) xj += ec[agg[j]];
@@ -884,23 +888,28 @@ __global__ __launch_bounds__(kBlock) void k_sfact_dc(int n, const int32_t* __res
     const int row = (int)(tid / W);
     const int lane = threadIdx.x % W;
     const bool valid = row < n;
-    // own-row epilogue operands, loaded ahead of the row loop
-    T zi = 0, xi = 0, bi = 0, dvi = 0, dprev = 0;
-    if (valid && lane == 0) {
-        if (!coef) {
-            if (z) zi = z[row];
-        } else {
-            xi = x[row];
-            if (agg) xi += ec[agg[row]];
-            bi = b[row];
-            dvi = dinv[row];
-            if (step != 0) dprev = d[row];
-        }
+    // own-row epilogue operands, loaded ahead of the row loop with no use of a
+    // loaded value before it: the row's aggregate first (its coarse
+    // correction is one more load), then the row bounds and the rest
+    const bool smooth_lane = valid && lane == 0 && coef;
+    int ag = 0, kb = 0, ke = 0;
+    if (smooth_lane && agg) ag = agg[row];
+    if (valid) {
+        kb = rp[row];
+        ke = rp[row + 1];
+    }
+    T zi = 0, xi = 0, eci = 0, bi = 0, dvi = 0, dprev = 0;
+    if (valid && lane == 0 && !coef && z) zi = z[row];
+    if (smooth_lane) {
+        xi = x[row];
+        bi = b[row];
+        dvi = dinv[row];
+        if (step != 0) dprev = d[row];
+        if (agg) eci = ec[ag];
     }
     T acc = 0;
-    if (valid) {
-        const int k1 = rp[row + 1];
-        for (int k = rp[row] + lane; k < k1; k += W) {
+    {
+        for (int k = kb + lane; k < ke; k += W) {
             const int j = col[k];
             T xj = x[j];
             if (agg) xj += ec[agg[j]];
@@ -918,6 +927,7 @@ __global__ __launch_bounds__(kBlock) void k_sfact_dc(int n, const int32_t* __res
         y[row] = out;
         return;
     }
+    if (agg) xi += eci;
     T c1, c2;
     cheb_coef(coef, step, c1, c2);
     T di = c2 * dvi * (bi - acc);
@@ -1064,16 +1074,18 @@ void restrict_agg(int nc, int bs, const int32_t* aptr, const int32_t* anodes, co
                        r, bc);
 }
 
+// x += P ec: one thread per node (its aggregate loaded once for the node's
+// bs entries)
 template <typename T>
 __global__ void k_prolong(int n, int bs, const int32_t* agg, const T* ec, T* x) {
-    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (t >= (int64_t)n * bs) return;
-    const int i = (int)(t / bs), c = (int)(t % bs);
-    x[t] += ec[(int64_t)bs * agg[i] + c];
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const int64_t a = agg[i];
+    for (int c = 0; c < bs; ++c) x[bs * i + c] += ec[bs * a + c];
 }
 template <typename T>
 void prolong_add(int n, int bs, const int32_t* agg, const T* ec, T* x, hipStream_t st) {
-    hipLaunchKernelGGL((k_prolong<T>), dim3(grid_for((int64_t)n * bs)), dim3(kBlock), 0, st, n, bs, agg, ec, x);
+    hipLaunchKernelGGL((k_prolong<T>), dim3(grid_for(n)), dim3(kBlock), 0, st, n, bs, agg, ec, x);
 }
 
 // x = Minv b (FP64 arithmetic), one wavefront per row
