@@ -277,7 +277,7 @@ def test_outlet_vectors_closed_form():
 # --------------------------------------------------------------------------- tangent
 
 
-@pytest.mark.parametrize("name", ["cube", "channel2"])
+@pytest.mark.parametrize("name", ["cube", "channel2", "unstr_channel"])
 def test_tangent_matches_central_differences(name):
     c = get_case(name)
     S = get_assembled(name)
@@ -382,7 +382,7 @@ def test_matrix_free_schur_matches_dense_schur():
     assert np.linalg.norm(y - Sd @ x) <= 1e-10 * np.linalg.norm(Sd @ x)
 
 
-@pytest.mark.parametrize("name", ["cube", "channel2"])
+@pytest.mark.parametrize("name", ["cube", "channel2", "unstr_channel"])
 def test_exact_subsolves_make_scr_exact(name):
     """With delta_A = delta_S = delta_I -> 0 the SCR preconditioner is the block
     LDU factorisation of the tangent, so FGMRES needs one iteration."""
@@ -396,7 +396,7 @@ def test_exact_subsolves_make_scr_exact(name):
     assert np.linalg.norm(x - xs) <= 1e-7 * np.linalg.norm(xs)
 
 
-@pytest.mark.parametrize("name", ["cube", "channel2"])
+@pytest.mark.parametrize("name", ["cube", "channel2", "unstr_channel"])
 def test_nested_solve_matches_dense_lu(name):
     S = get_assembled(name)
     c = get_case(name)
@@ -501,7 +501,7 @@ def test_gershgorin_bound_brute_force():
     assert amg.gershgorin_bound(sp.csr_matrix(A), d) == pytest.approx(want, rel=1e-15)
 
 
-@pytest.mark.parametrize("name", ["cube", "channel2", "pipe_tiny"])
+@pytest.mark.parametrize("name", ["cube", "channel2", "pipe_tiny", "unstr_channel"])
 def test_smoother_bound_covers_spectrum(name):
     """The smoother interval's upper end bounds the spectral radius of
     D^{-1} M on every smoothed level (dense eigenvalues), for both
