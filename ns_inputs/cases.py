@@ -132,13 +132,20 @@ def channel2(nx: int = 8, ny: int = 4, nz: int = 4, seed: int = 2, R=(1.5e3, 3.0
                    {"seed": seed, "pressure": "p = 0 everywhere"})
 
 
-def unstructured_channel(nx: int = 16, ny: int = 8, nz: int = 8, seed: int = 7, R: float = 2.0e3,
+UNSTR_SIZES = {
+    "unstr_channel": (16, 8, 8),    # 1 377 nodes (parity tests)
+    "unstr_200k": (96, 48, 48),     # 232 897 nodes, 1.48M tets (the Delaunay step takes ~1 min)
+}
+
+
+def unstructured_channel(size: str = "unstr_channel", seed: int = 7, R: float = 2.0e3,
                          umax: float = 10.0, noise: float = 0.01, jitter: float = 0.3) -> Case:
     """Box [0,2]x[0,1]x[0,1] meshed by ``meshes.delaunay_box`` (unstructured:
     irregular node degrees and row lengths); inlet x=0 with u = umax*16
     y(1-y) z(1-z); outlet the face x=2; every other boundary point (and the
     outlet rim) is no-slip.  State: the inlet profile continued along x plus
     seeded Gaussian noise (``noise`` * umax) on free components; p = 0."""
+    nx, ny, nz = UNSTR_SIZES[size]
     lx, ly, lz = 2.0, 1.0, 1.0
     xyz, tets = meshes.delaunay_box(nx, ny, nz, lx, ly, lz, jitter=jitter, seed=seed)
     N = len(xyz)
@@ -159,7 +166,7 @@ def unstructured_channel(nx: int = 16, ny: int = 8, nz: int = 8, seed: int = 7, 
     inlet = np.abs(x) < tol
     v[dir_nodes] = 0.0
     v[inlet, 0] = prof[inlet]
-    return _finish("unstr_channel", xyz, tets, mask, [bfaces[out]], v, np.zeros(N), 1.06, 0.04, 1e-3, 0.5,
+    return _finish(size, xyz, tets, mask, [bfaces[out]], v, np.zeros(N), 1.06, 0.04, 1e-3, 0.5,
                    np.asarray([R], float), {"seed": seed, "jitter": jitter, "pressure": "p = 0 everywhere"})
 
 
@@ -435,8 +442,8 @@ def build(name: str, **kw) -> Case:
         return cube_lid(**kw)
     if name == "channel2":
         return channel2(**kw)
-    if name == "unstr_channel":
-        return unstructured_channel(**kw)
+    if name in UNSTR_SIZES:
+        return unstructured_channel(name, **kw)
     if name in PIPE_SIZES:
         return pipe(name, **kw)
     if name in YBIF_SIZES:
