@@ -176,6 +176,88 @@ def test_pressure_and_reynolds_stress_terms():
     assert np.abs(R[3 * N:] - Rp).max() <= 1e-13 * np.abs(Rp).max()
 
 
+def _tau_M_closed(X, ph, U=np.zeros(3)):
+    """tau_M of one element for a velocity U that is uniform over it (Sec. 2.3):
+    rho^-1 (C_T/dt^2 + U.G.U + C_I (mu/rho)^2 G:G)^(-1/2), G from the simplex matrix."""
+    Mq = (2 ** (1 / 3) / 2) * np.array([[2, 1, 1], [1, 2, 1], [1, 1, 2]])
+    Jinv = np.linalg.inv(np.stack([X[1] - X[0], X[2] - X[0], X[3] - X[0]], 1))
+    G = Jinv.T @ Mq @ Jinv
+    return (1 / ph.rho) / np.sqrt(4.0 / ph.dt ** 2 + U @ G @ U + 36.0 * (ph.mu / ph.rho) ** 2 * np.sum(G * G))
+
+
+def test_supg_term_uniform_velocity():
+    """SUPG term of B_m^vol: v = U uniform, p linear, vdot = 0, tau on.  Then
+    grad v = 0, r_M = grad p and v' = -tau_M grad p (tau_M constant per element,
+    with the U.G.U term), so per element
+      R_m[a,i] = -V p(centroid) dN_a/dx_i + rho V tau_M d_i p (U . grad N_a)
+                 - rho V tau_M^2 d_i p (grad p . grad N_a),
+      R_p[a]   = V tau_M grad N_a . grad p.
+    The second term is -rho v'_i (v.grad N_a); its sign, and the v.grad N_a
+    contraction, are what this pins (the cross-stress term is zero here)."""
+    U = np.array([0.8, -0.5, 1.3])
+    gp = np.array([0.4, -1.2, 2.0])
+    c = _box_case(2, v=lambda X: np.broadcast_to(U, X.shape).copy(), p=lambda X: 0.2 + X @ gp)
+    ph = dz.Physics(1.06, 0.004, 0.5, 0.5)  # a long step: tau_M ~ h / |U|, so the SUPG term is O(1)
+    R = _res(c, ph, tau_off=False)
+    N = c.n_nodes
+    Rm = np.zeros((N, 3))
+    Rp = np.zeros(N)
+    supg = np.zeros((N, 3))
+    for t in c.tets:
+        X = c.xyz[t]
+        g, V = _grads(X)
+        tM = _tau_M_closed(X, ph, U)
+        pc = c.p[t].mean()
+        for a in range(4):
+            s = ph.rho * V * tM * gp * (U @ g[a])
+            supg[t[a]] += s
+            Rm[t[a]] += -V * pc * g[a] + s - ph.rho * V * tM ** 2 * gp * (gp @ g[a])
+            Rp[t[a]] += V * tM * (g[a] @ gp)
+    # the SUPG contribution is a sizeable part of the row, so a flipped or dropped term shows
+    assert np.abs(supg).max() > 0.05 * np.abs(Rm).max()
+    assert np.abs(R[:3 * N] - Rm.ravel()).max() <= 1e-13 * np.abs(Rm).max()
+    assert np.abs(R[3 * N:] - Rp).max() <= 1e-13 * np.abs(Rp).max()
+
+
+def test_cross_stress_term_shear_flow():
+    """Cross-stress term of B_m^vol: the shear v = (y, 0, 0), p linear, vdot = 0,
+    with tau_M = t and tau_C held fixed (the frozen-tau residual).  Then
+    (v.grad)v = 0, div v = 0, r_M = grad p, v' = -t grad p, and
+    (v'.grad)v_i = v'_y delta_ix, so with the exact integrals int N_a = V/4 and
+    int y = V y_c (centroid) per element
+      R_m[a,i] = -V p_c d_iN_a + mu V (d_yN_a delta_ix + d_xN_a delta_iy)
+                 + rho t V y_c d_i p d_xN_a          (SUPG,  -rho v'_i (v.grad N_a))
+                 - rho t (V/4) d_y p delta_ix        (cross, +rho N_a (v'.grad) v_i)
+                 - rho t^2 V d_i p (grad p . grad N_a)  (Reynolds stress),
+      R_p[a]   = V t grad N_a . grad p.
+    A transposed cross term (v'_l d_i v_l) would put -rho t (V/4) d_x p in the
+    y rows instead."""
+    gp = np.array([0.7, -1.1, 0.5])
+    c = _box_case(2, v=lambda X: np.stack([X[:, 1], 0 * X[:, 0], 0 * X[:, 0]], 1), p=lambda X: -0.3 + X @ gp)
+    ph = dz.Physics(1.3, 0.02, 1e-3, 0.5)
+    E, N = c.n_elems, c.n_nodes
+    t = 0.37
+    R = dz.residual_only(c, c.v, c.p, c.vdot, np.zeros(0), ph, tau_fixed=(np.full((E, 4), t), np.full((E, 4), 2.9)))
+    Rm = np.zeros((N, 3))
+    Rp = np.zeros(N)
+    cross = np.zeros((N, 3))
+    ex, ey = np.eye(3)[0], np.eye(3)[1]
+    for tt in c.tets:
+        X = c.xyz[tt]
+        g, V = _grads(X)
+        pc = c.p[tt].mean()
+        yc = X[:, 1].mean()
+        for a in range(4):
+            cr = -ph.rho * t * (V / 4) * gp[1] * ex
+            cross[tt[a]] += cr
+            Rm[tt[a]] += (-V * pc * g[a] + ph.mu * V * (g[a][1] * ex + g[a][0] * ey)
+                          + ph.rho * t * V * yc * gp * g[a][0] + cr - ph.rho * t ** 2 * V * gp * (gp @ g[a]))
+            Rp[tt[a]] += V * t * (g[a] @ gp)
+    assert np.abs(cross).max() > 0.05 * np.abs(Rm).max()
+    assert np.abs(R[:3 * N] - Rm.ravel()).max() <= 1e-13 * np.abs(Rm).max()
+    assert np.abs(R[3 * N:] - Rp).max() <= 1e-13 * np.abs(Rp).max()
+
+
 def test_grad_div_term_tau_C():
     """rho -> 0, mu > 0, v = (x, 0, 0): v' -> 0 and p' = -tau_C div v with
     tau_C = 1/(tau_M tr G), tau_M -> 1/(mu sqrt(C_I G:G))."""
