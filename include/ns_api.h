@@ -127,6 +127,9 @@ typedef struct {
     double rtol_I;          /* delta^r_I, inner A-solve of Alg. 2     [1e-3]  */
     double cheb_ratio;      /* AMG smoother interval [lambda/cheb_ratio, lambda],
                              * lambda >= spectral radius of D^-1 M     [10]    */
+    double cc_scale_A;      /* AMG coarse-grid correction x += c P e_c, c in
+                             * (0, 2], on the A hierarchy              [1]     */
+    double cc_scale_S;      /* the same on the S_hat hierarchy         [1]     */
     int32_t m, nmax;        /* FGMRES restart length / max iterations [200]   */
     int32_t m_A, nmax_A;    /* GMRES on A                             [200]   */
     int32_t m_S, nmax_S;    /* GMRES on S                             [200]   */
@@ -187,6 +190,13 @@ ns_status ns_ctx_create(const ns_mesh* mesh, const ns_ctx_opts* opts, ns_ctx** o
  * Meshes of up to 1024 nodes replay each Krylov step and set-up chain from
  * a HIP graph captured on first use; larger ones launch directly (the
  * environment variable NS_GRAPHS=0 or 1, read here, forces either form).
+ * Two more kernel-path choices are made by size and can be forced here the
+ * same way (both compute the same sums; used to test every path on small
+ * meshes): NS_XCD_ROWS=0/1, block-SpMV rows mapped to one contiguous range
+ * per XCD (default: when the gathered vector is <= 8 MB), and
+ * NS_PROLONG_PASS=0/1, the finest A level's coarse correction added by a
+ * pass of its own instead of inside the first post-smoothing step (default:
+ * from 5e5 rows).
  * Errors: NS_ERR_WORKSPACE, NS_ERR_HIP. */
 ns_status ns_ctx_bind(ns_ctx* ctx, void* d_workspace, size_t bytes, hipStream_t stream);
 

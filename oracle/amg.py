@@ -30,6 +30,12 @@ written definition, which the GPU library implements independently:
   vector x_i = 0.5 + ((i * 2654435761) mod 2^32)/2^32 (power iteration
   approaches the spectral radius from below); one pre- and one
   post-smoothing application (zero initial guess before pre-smoothing);
+* coarse-grid correction scaled by ``cc_scale`` (default 1): x += c P e_c at
+  every level, where e_c is the coarse level's cycle applied to P^T r.  The
+  piecewise-constant prolongation represents a smooth error only by its
+  aggregate means, so the Galerkin correction (the M-orthogonal projection on
+  range(P)) falls short of the smooth error; an over-correction c in (1, 2)
+  compensates.  The cycle stays a fixed linear operator for any c;
 * coarsest level: dense LU solve in FP64.
 """
 from __future__ import annotations
@@ -152,10 +158,12 @@ def chebyshev(M, dinv, b, x, degree, lmin, lmax):
 class AMG:
     """V-cycle for M (scipy CSR) with block size ``bs`` on the node aggregates."""
 
-    def __init__(self, M, bs: int, aggs, cheb_degree: int = 2, extra_diag=None, cheb_ratio: float = 10.0):
+    def __init__(self, M, bs: int, aggs, cheb_degree: int = 2, extra_diag=None, cheb_ratio: float = 10.0,
+                 cc_scale: float = 1.0):
         self.bs = bs
         self.deg = cheb_degree
         self.ratio = cheb_ratio
+        self.cc_scale = cc_scale
         M = sp.csr_matrix(M, dtype=np.float64)
         if extra_diag is not None:
             M = (M + sp.diags(extra_diag)).tocsr()
@@ -183,5 +191,5 @@ class AMG:
         x = chebyshev(M, dinv, b, None, self.deg, lmax / self.ratio, lmax)
         r = b - M @ x
         P = self.P[level]
-        x = x + P @ self.vcycle(P.T @ r, level + 1)
+        x = x + self.cc_scale * (P @ self.vcycle(P.T @ r, level + 1))
         return chebyshev(M, dinv, b, x, self.deg, lmax / self.ratio, lmax)

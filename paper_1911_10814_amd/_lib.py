@@ -38,7 +38,8 @@ class NsPhys(C.Structure):
 
 class NsSolveOpts(C.Structure):
     _fields_ = [("rtol", C.c_double), ("atol", C.c_double), ("rtol_A", C.c_double), ("rtol_S", C.c_double),
-                ("rtol_I", C.c_double), ("cheb_ratio", C.c_double), ("m", C.c_int32), ("nmax", C.c_int32), ("m_A", C.c_int32),
+                ("rtol_I", C.c_double), ("cheb_ratio", C.c_double), ("cc_scale_A", C.c_double),
+                ("cc_scale_S", C.c_double), ("m", C.c_int32), ("nmax", C.c_int32), ("m_A", C.c_int32),
                 ("nmax_A", C.c_int32), ("m_S", C.c_int32), ("nmax_S", C.c_int32), ("pc_A", C.c_int32),
                 ("precision", C.c_int32), ("cheb_degree", C.c_int32), ("cycles_S", C.c_int32),
                 ("pc", C.c_int32), ("cheb_degree_S", C.c_int32), ("pc_I", C.c_int32), ("reserved", C.c_int32),

@@ -55,6 +55,10 @@ constexpr double kDefaultChebRatio = 10.0;
 // meshes but the stationary V-cycle iteration on S_hat can diverge (observed
 // on the 1e6-node Y-bifurcation), so the default is a single V-cycle.
 constexpr int kDefaultCyclesS = 1;
+// Scaling of the coarse-grid correction of each hierarchy (1: the plain
+// Galerkin correction).
+constexpr double kDefaultCcScaleA = 1.0;
+constexpr double kDefaultCcScaleS = 1.0;
 constexpr double kXcdMaxXBytes = 8.0e6;
 
 // ---------------------------------------------------------------------------
@@ -360,7 +364,8 @@ constexpr int kMapStatus = 0, kMapNorm = 8, kMapNorm0 = 9;
 constexpr int kKindA = 0, kKindS = 1, kKindOuter = 2, kKindShat = 3, kKindInner = 4, kKindSetup = 5;
 // meshes up to this many nodes replay captured graphs by default
 constexpr int kGraphMaxNodes = 1024;
-// finest A levels from this many rows add the prolongated correction in a pass of its own
+// finest A levels from this many rows add the prolongated correction in a pass
+// of its own (NS_PROLONG_PASS=0/1, read at bind, forces the fused step or the pass)
 constexpr int kProlongPassRows = 500000;
 
 template <typename T>
@@ -726,10 +731,10 @@ struct Nested {
                 spmv<T>(bs, bs, M, a, as<T>(L.r), T(-1), b, T(1), nullptr, nullptr, st);
             }
             restrict_first<T>(C.n, bs, L.aptr, L.anodes, as<T>(L.r), as<T>(C.b), xc, as<T>(C.d), Typed<T>::dinv(C),
-                              coefc, st);
+                              coefc, coef + kCoefScale, st);
         } else {
             resid_restrict<T>(bs, M, a, b, C.n, L.aptr, L.anodes, as<T>(C.b), xc, as<T>(C.d), Typed<T>::dinv(C),
-                              coefc, st);
+                              coefc, coef + kCoefScale, st);
         }
         vcycle(H, l + 1, as<T>(C.b), as<T>(C.x1));
         // post-smoothing; the first step applies the prolongated correction.
@@ -737,7 +742,8 @@ struct Nested {
         // correction is added by a pass of its own instead: the fused step's
         // per-block aggregate gather costs more than that pass there (the
         // same addition either way).
-        if (tme && L.n >= kProlongPassRows) {
+        const bool pass = c->prolong_mode >= 0 ? c->prolong_mode == 1 : L.n >= kProlongPassRows;
+        if (tme && pass) {
             prolong_add<T>(L.n, bs, L.agg, as<T>(C.x1), a, st);
             cheb(a, bb, 0, nullptr, nullptr);
         } else {
@@ -1153,11 +1159,12 @@ void convert32(ns_ctx* c, SystemDev& y, hipStream_t st) {
 // Step coefficients of the Chebyshev recurrence for every step up to the
 // largest degree (a step's coefficients do not depend on the degree in use,
 // so both hierarchies can run different degrees from one table).
-void upload_coef(ns_ctx* c, SystemDev& y, int deg, double ratio, hipStream_t st) {
+void upload_coef(ns_ctx* c, SystemDev& y, int deg, double ratio, const double scale[2], hipStream_t st) {
     if (deg < 1 || deg > kMaxChebDegree) throw Fail{NS_ERR_ARG, "Chebyshev degree out of range [1, 8]"};
     if (!(ratio > 1.0) || !std::isfinite(ratio)) throw Fail{NS_ERR_ARG, "cheb_ratio must be finite and > 1"};
     deg = kMaxChebDegree;
-    if (y.coef_deg == deg && y.coef_ratio == ratio) return;
+    if (y.coef_deg == deg && y.coef_ratio == ratio && y.coef_scale[0] == scale[0] && y.coef_scale[1] == scale[1])
+        return;
     std::vector<double> host;
     std::vector<AmgLevelDev*> lv;
     for (int h = 0; h < 2; ++h) {
@@ -1174,6 +1181,7 @@ void upload_coef(ns_ctx* c, SystemDev& y, int deg, double ratio, hipStream_t st)
                 cf[2 * s] = 2.0 * rn / delta;
                 rho = rn;
             }
+            cf[kCoefScale] = scale[h];
             host.insert(host.end(), cf.begin(), cf.end());
             lv.push_back(&H[l]);
         }
@@ -1187,6 +1195,13 @@ void upload_coef(ns_ctx* c, SystemDev& y, int deg, double ratio, hipStream_t st)
     HIPCHK(hipStreamSynchronize(st));  // the host buffer goes out of scope
     y.coef_deg = deg;
     y.coef_ratio = ratio;
+    y.coef_scale[0] = scale[0];
+    y.coef_scale[1] = scale[1];
+}
+
+void upload_coef(ns_ctx* c, SystemDev& y, const ns_solve_opts& o, hipStream_t st) {
+    const double scale[2] = {dfltd(o.cc_scale_A, kDefaultCcScaleA), dfltd(o.cc_scale_S, kDefaultCcScaleS)};
+    upload_coef(c, y, dflt(o.cheb_degree, kDefaultChebDegree), dfltd(o.cheb_ratio, kDefaultChebRatio), scale, st);
 }
 
 void ensure_transposed(ns_ctx* c, hipStream_t st) {
@@ -1206,6 +1221,8 @@ void check_solve_opts(const ns_solve_opts& o) {
     if (o.cheb_degree < 0 || o.cheb_degree > kMaxChebDegree || o.cheb_degree_S < 0 ||
         o.cheb_degree_S > kMaxChebDegree)
         throw Fail{NS_ERR_ARG, "Chebyshev degree out of range [1, 8]"};
+    for (double sc : {o.cc_scale_A, o.cc_scale_S})
+        if (!(sc >= 0.0 && sc <= 2.0)) throw Fail{NS_ERR_ARG, "coarse-grid correction scale out of range [0, 2]"};
 }
 
 ns_status run_solve(ns_ctx* c, int which, const ns_solve_opts* opts, const double* b, double* x, ns_stats* hs,
@@ -1231,7 +1248,7 @@ ns_status run_solve(ns_ctx* c, int which, const ns_solve_opts* opts, const doubl
     if (which == 1) ensure_transposed(c, st);
     K.sy = &c->sys[which];
     setup_system(c, *K.sy, K.o.precision == NS_FP32_INNER, st);
-    upload_coef(c, *K.sy, dflt(K.o.cheb_degree, kDefaultChebDegree), dfltd(K.o.cheb_ratio, kDefaultChebRatio), st);
+    upload_coef(c, *K.sy, K.o, st);
     HIPCHK(hipStreamSynchronize(st));
     auto t1 = std::chrono::steady_clock::now();
     ns_status rs = K.o.precision == NS_FP32_INNER ? fgmres<float>(K, b, x) : fgmres<double>(K, b, x);
@@ -1416,6 +1433,8 @@ ns_status ns_ctx_bind(ns_ctx* c, void* ws, size_t bytes, hipStream_t st) {
         c->use_graphs = (ng && (ng[0] == '0' || ng[0] == '1')) ? ng[0] == '1' : S.N <= kGraphMaxNodes;
         const char* xr = getenv("NS_XCD_ROWS");
         c->xcd_mode = (xr && (xr[0] == '0' || xr[0] == '1')) ? xr[0] - '0' : -1;
+        const char* pp = getenv("NS_PROLONG_PASS");
+        c->prolong_mode = (pp && (pp[0] == '0' || pp[0] == '1')) ? pp[0] - '0' : -1;
         HIPCHK(hipStreamSynchronize(st));
         c->bound = true;
         return NS_OK;
@@ -1807,7 +1826,7 @@ ns_status ns_apply(ns_ctx* c, int32_t op, const ns_solve_opts* opts, const doubl
         K.sy = &c->sys[0];
         const bool f32 = K.o.precision == NS_FP32_INNER;
         setup_system(c, c->sys[0], f32, st);
-        upload_coef(c, c->sys[0], dflt(K.o.cheb_degree, kDefaultChebDegree), dfltd(K.o.cheb_ratio, kDefaultChebRatio), st);
+        upload_coef(c, c->sys[0], K.o, st);
         const int N = c->sym.N;
         const int64_t nin[] = {4L * N, 3L * N, N, 3L * N, N, N, 3L * N, N, N, 4L * N, 3L * N, 4L * N};
         const int64_t nout[] = {4L * N, 3L * N, 3L * N, N, N, N, 3L * N, N, N, 4L * N, 3L * N, 4L * N};

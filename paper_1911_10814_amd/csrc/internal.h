@@ -125,6 +125,7 @@ struct SystemDev {
     std::vector<AmgLevelDev> A, S;   // hierarchies
     int coef_deg = 0;                // number of Chebyshev steps the device coefficients cover
     double coef_ratio = 0.0;         // and the interval ratio
+    double coef_scale[2] = {0.0, 0.0};  // and the coarse-grid correction scales (A, S_hat)
     bool ready = false;              // per-step set-up done for the current tangent
     bool have32 = false;
     uint64_t version = 0;            // tangent version the set-up belongs to
@@ -207,6 +208,7 @@ struct ns_ctx {
     hipEvent_t fork_ev = nullptr;
     bool use_graphs = true;
     int xcd_mode = -1;           // XCD-contiguous row ranges: -1 by size, 0 off, 1 on
+    int prolong_mode = -1;       // finest A prolongation: -1 by size, 0 fused into smoothing, 1 separate pass
     // captured Arnoldi steps, (kind, system, precision, pc_A, pc_I, degrees, cycles_S, j), and
     // set-up chains, (set-up kind, system, 0 ..., chain) -> executable graph
     using GraphKey = std::tuple<int, int, int, int, int, int, int, int, int>;

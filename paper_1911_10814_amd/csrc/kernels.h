@@ -116,14 +116,20 @@ void scale_by(int64_t n, const T* x, const double* s, bool inverse, T* y, hipStr
 // uses (c1, c2) = (coef[2s-1], coef[2s]).
 constexpr int kMaxChebDegree = 8;
 constexpr int kCoefLen = 2 * kMaxChebDegree;
+// the last slot of a level's coefficient array holds the scaling of the
+// coarse-grid correction that level receives from the next one
+constexpr int kCoefScale = kCoefLen - 1;
+static_assert(2 * (kMaxChebDegree - 1) < kCoefScale, "Chebyshev step coefficients overlap the scale slot");
 template <typename T>
 void cheb_first(int64_t n, const T* b, const T* dinv, const T* coef, T* x, T* d, hipStream_t st);
 template <typename T>
 void cheb_step(int bs, const BlockOp<T>& M, const T* xin, T* xout, T* d, const T* b, const T* dinv, const T* coef,
                int step, const int32_t* agg, const T* ec, hipStream_t st);
+// scale (device scalar, or nullptr for 1) multiplies the restricted right-hand
+// side, i.e. the coarse-grid correction the coarse cycle returns
 template <typename T>
 void restrict_first(int nc, int bs, const int32_t* aptr, const int32_t* anodes, const T* r, T* bc, T* xc, T* dc,
-                    const T* dinvc, const T* coefc, hipStream_t st);
+                    const T* dinvc, const T* coefc, const T* scale, hipStream_t st);
 // Factored S_hat = D - C diag(A)^{-1} B on the node pattern (V: the 16 value
 // planes; t: [3n] scratch).  With coef == nullptr: y = alpha S_hat xx + beta z;
 // else one Chebyshev step y = xx + d, d = c1 d + c2 dinv (b - S_hat xx), where
@@ -136,7 +142,8 @@ void shat_factored(int n, const int32_t* rp, const int32_t* col, const T* V, int
 // the coarse first Chebyshev step when xc != nullptr (as restrict_first)
 template <typename T>
 void resid_restrict(int bs, const BlockOp<T>& M, const T* x, const T* b, int nc, const int32_t* aptr,
-                    const int32_t* anodes, T* bc, T* xc, T* dc, const T* dinvc, const T* coefc, hipStream_t st);
+                    const int32_t* anodes, T* bc, T* xc, T* dc, const T* dinvc, const T* coefc, const T* scale,
+                    hipStream_t st);
 template <typename T>
 void restrict_agg(int nc, int bs, const int32_t* aptr, const int32_t* anodes, const T* r, T* bc, hipStream_t st);
 template <typename T>

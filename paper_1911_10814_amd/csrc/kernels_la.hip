@@ -955,12 +955,13 @@ template <typename T>
 __global__ void k_restrict_first(int nc, int bs, const int32_t* __restrict__ aptr,
                                  const int32_t* __restrict__ anodes, const T* __restrict__ r, T* __restrict__ bc,
                                  T* __restrict__ xc, T* __restrict__ dc, const T* __restrict__ dinvc,
-                                 const T* __restrict__ coefc) {
+                                 const T* __restrict__ coefc, const T* __restrict__ scale) {
     const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (t >= (int64_t)nc * bs) return;
     const int I = (int)(t / bs), c = (int)(t % bs);
     T s = 0;
     for (int q = aptr[I]; q < aptr[I + 1]; ++q) s += r[(int64_t)bs * anodes[q] + c];
+    if (scale) s *= scale[0];
     bc[t] = s;
     if (xc) {
         const T di = coefc[0] * dinvc[t] * s;
@@ -971,9 +972,9 @@ __global__ void k_restrict_first(int nc, int bs, const int32_t* __restrict__ apt
 
 template <typename T>
 void restrict_first(int nc, int bs, const int32_t* aptr, const int32_t* anodes, const T* r, T* bc, T* xc, T* dc,
-                    const T* dinvc, const T* coefc, hipStream_t st) {
+                    const T* dinvc, const T* coefc, const T* scale, hipStream_t st) {
     hipLaunchKernelGGL((k_restrict_first<T>), dim3(grid_for((int64_t)nc * bs)), dim3(kBlock), 0, st, nc, bs, aptr,
-                       anodes, r, bc, xc, dc, dinvc, coefc);
+                       anodes, r, bc, xc, dc, dinvc, coefc, scale);
 }
 
 // Residual fused with the restriction, for the coarser levels: one wavefront
@@ -992,7 +993,8 @@ __global__ __launch_bounds__(kBlock) void k_resid_restrict(BlockOp<T> M, const T
                                                            const int32_t* __restrict__ aptr,
                                                            const int32_t* __restrict__ anodes, T* __restrict__ bc,
                                                            T* __restrict__ xc, T* __restrict__ dc,
-                                                           const T* __restrict__ dinvc, const T* __restrict__ coefc) {
+                                                           const T* __restrict__ dinvc, const T* __restrict__ coefc,
+                                                           const T* __restrict__ scale) {
     const int64_t tid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const int I = (int)(tid >> 6);
     const int lane = threadIdx.x & 63;
@@ -1000,6 +1002,7 @@ __global__ __launch_bounds__(kBlock) void k_resid_restrict(BlockOp<T> M, const T
     const bool valid = I < nc;
     const int64_t t = (int64_t)BS * I + lane;
     const T fc = (valid && lane < BS && xc) ? coefc[0] * dinvc[t] : T(0);  // loaded ahead of the loops
+    const T sc = scale ? scale[0] : T(1);
     // acc = sum over the aggregate of (M x + dextra x - b): the negated residual
     T acc[BS];
 #pragma unroll
@@ -1038,6 +1041,7 @@ __global__ __launch_bounds__(kBlock) void k_resid_restrict(BlockOp<T> M, const T
 #pragma unroll
     for (int r = 1; r < BS; ++r)
         if (lane == r) s = -acc[r];
+    s *= sc;
     bc[t] = s;
     if (xc) {
         const T di = fc * s;
@@ -1048,15 +1052,16 @@ __global__ __launch_bounds__(kBlock) void k_resid_restrict(BlockOp<T> M, const T
 
 template <typename T>
 void resid_restrict(int bs, const BlockOp<T>& M, const T* x, const T* b, int nc, const int32_t* aptr,
-                    const int32_t* anodes, T* bc, T* xc, T* dc, const T* dinvc, const T* coefc, hipStream_t st) {
+                    const int32_t* anodes, T* bc, T* xc, T* dc, const T* dinvc, const T* coefc, const T* scale,
+                    hipStream_t st) {
     if (nc <= 0) return;
     const dim3 grid(grid_for((int64_t)nc * 64));
     if (bs == 3)
         hipLaunchKernelGGL((k_resid_restrict<T, 3>), grid, dim3(kBlock), 0, st, M, x, b, nc, aptr, anodes, bc, xc, dc,
-                           dinvc, coefc);
+                           dinvc, coefc, scale);
     else
         hipLaunchKernelGGL((k_resid_restrict<T, 1>), grid, dim3(kBlock), 0, st, M, x, b, nc, aptr, anodes, bc, xc, dc,
-                           dinvc, coefc);
+                           dinvc, coefc, scale);
 }
 
 template <typename T>
@@ -1691,13 +1696,13 @@ void newton_update(int64_t n, double gdt, const double* dx, double* y, double* y
     template void cheb_step<T>(int, const BlockOp<T>&, const T*, T*, T*, const T*, const T*, const T*, int,           \
                                const int32_t*, const T*, hipStream_t);                                               \
     template void restrict_first<T>(int, int, const int32_t*, const int32_t*, const T*, T*, T*, T*, const T*,         \
-                                    const T*, hipStream_t);                                                           \
+                                    const T*, const T*, hipStream_t);                                                 \
     template void restrict_agg<T>(int, int, const int32_t*, const int32_t*, const T*, T*, hipStream_t);              \
     template void shat_factored<T>(int, const int32_t*, const int32_t*, const T*, int64_t, const T*, const T*,       \
                                    const int32_t*, const T*, T*, T*, T, const T*, T, const T*, const T*, const T*,   \
                                    int, T*, int, hipStream_t);                                                       \
     template void resid_restrict<T>(int, const BlockOp<T>&, const T*, const T*, int, const int32_t*, const int32_t*, \
-                                    T*, T*, T*, const T*, const T*, hipStream_t);                                    \
+                                    T*, T*, T*, const T*, const T*, const T*, hipStream_t);                          \
     template void prolong_add<T>(int, int, const int32_t*, const T*, T*, hipStream_t);                               \
     template void dense_gemv<T>(int, const double*, const T*, T*, hipStream_t);
 

@@ -36,6 +36,38 @@ def ctx_for(name):
     return _CTX[name]
 
 
+# The kernel paths the large meshes take by size (the finest A level's coarse
+# correction in a pass of its own from 5e5 rows, the block SpMV family without
+# XCD row ranges once the gathered vector exceeds 8 MB), forced on the small
+# meshes through the switches the library reads at bind.
+LARGE_PATHS = {"NS_PROLONG_PASS": "1", "NS_XCD_ROWS": "0"}
+_CTX_FORCED = {}
+
+
+def ctx_forced(name, env):
+    import os
+    from paper_1911_10814_amd import NsContext
+    key = (name, tuple(sorted(env.items())))
+    if key not in _CTX_FORCED:
+        c = get_case(name)
+        S = get_assembled(name)
+        old = {k: os.environ.get(k) for k in env}
+        os.environ.update(env)
+        try:
+            ctx = NsContext(c).bind()
+        finally:
+            for k, v in old.items():
+                if v is None:
+                    os.environ.pop(k, None)
+                else:
+                    os.environ[k] = v
+        ctx._rhs = ctx.assemble(c.v, c.p, c.vdot, rho=c.rho, mu=c.mu, dt=c.dt, rho_inf=c.rho_inf, m=c.R,
+                                P_af=c.R * S.Q)
+        torch.cuda.synchronize()
+        _CTX_FORCED[key] = ctx
+    return _CTX_FORCED[key]
+
+
 def oracle_solver(name, **kw):
     key = (name, tuple(sorted(kw.items())))
     if key not in _NS:
@@ -98,16 +130,20 @@ def test_shat_matches_oracle(name):
 
 
 @pytest.mark.parametrize("name", CASES)
-def test_vcycles_match_oracle(name):
-    ctx = ctx_for(name)
-    ns = oracle_solver(name)
+@pytest.mark.parametrize("paths", ["by_size", "large_mesh_paths"])
+@pytest.mark.parametrize("scale", [(1.0, 1.0), (1.6, 1.8)])
+def test_vcycles_match_oracle(name, paths, scale):
+    from paper_1911_10814_amd import SolveOptions
+    ctx = ctx_for(name) if paths == "by_size" else ctx_forced(name, LARGE_PATHS)
+    ns = oracle_solver(name, cc_scale_A=scale[0], cc_scale_S=scale[1])
+    o = SolveOptions(cc_scale_A=scale[0], cc_scale_S=scale[1])
     rng = np.random.default_rng(5)
     x3 = rng.standard_normal(3 * ctx.N)
     x1 = rng.standard_normal(ctx.N)
-    ya, _ = ctx.apply("vcycle_A", x3)
-    ys, _ = ctx.apply("vcycle_S", x1)
+    ya, _ = ctx.apply("vcycle_A", x3, o)
+    ys, _ = ctx.apply("vcycle_S", x1, o)
     ea, es = rel(ya.cpu().numpy(), ns.amgA.vcycle(x3)), rel(ys.cpu().numpy(), ns.amgS.vcycle(x1))
-    print(name, "vcycle A", ea, "S", es, flush=True)
+    print(name, paths, scale, "vcycle A", ea, "S", es, flush=True)
     assert ea <= 1e-11 and es <= 1e-11
 
 
@@ -148,6 +184,35 @@ def test_nested_solve_fp64_replay_and_tolerance(name):
     assert np.linalg.norm(S.rhs - Ad @ xt.cpu().numpy()) <= 1e-8 * np.linalg.norm(S.rhs) * (1 + 1e-6)
     if ti["schedule"] == info["schedule"]:
         assert rel(xt.cpu().numpy(), xo) <= 1e-10
+
+
+@pytest.mark.parametrize("name", ["pipe_tiny", "ybif_small", "conexp_small", "unstr_channel"])
+def test_nested_solve_replay_on_large_mesh_paths(name):
+    """The whole FP64 nested solve through the kernel paths the large meshes
+    take (separate prolongation pass on the finest A level, block SpMVs without
+    XCD row ranges), replayed on the oracle's iteration path."""
+    from paper_1911_10814_amd import SolveOptions
+    ctx = ctx_forced(name, LARGE_PATHS)
+    S = get_assembled(name)
+    xo, info = oracle_solver(name).solve(S.rhs)
+    xg, gi = ctx.solve(ctx._rhs, SolveOptions(schedule=info["schedule"]))
+    n3 = 3 * ctx.N
+    xg = xg.cpu().numpy()
+    ev, ep = rel(xg[:n3], xo[:n3]), rel(xg[n3:], xo[n3:])
+    print(name, "large-mesh paths replay err v", ev, "p", ep, flush=True)
+    assert ev <= 1e-10 and ep <= 1e-10
+
+
+@pytest.mark.parametrize("name", ["channel2", "ybif_small"])
+def test_scaled_coarse_correction_replay_matches_oracle(name):
+    """Over-scaled coarse-grid corrections on both hierarchies."""
+    from paper_1911_10814_amd import SolveOptions
+    kw = dict(cc_scale_A=1.5, cc_scale_S=1.8)
+    ctx = ctx_for(name)
+    S = get_assembled(name)
+    xo, info = oracle_solver(name, **kw).solve(S.rhs)
+    xg, _ = ctx.solve(ctx._rhs, SolveOptions(schedule=info["schedule"], **kw))
+    assert rel(xg.cpu().numpy(), xo) <= 1e-10
 
 
 @pytest.mark.parametrize("name,pc_A", [("channel2", "amg"), ("pipe_tiny", "jacobi"), ("ybif_small", "amg")])

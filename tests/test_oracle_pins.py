@@ -633,6 +633,33 @@ def test_amg_two_level_galerkin_and_exact_coarse():
     assert np.bincount(aggs[0]).max() <= 4
 
 
+@pytest.mark.parametrize("cc", [1.0, 1.7])
+def test_amg_two_level_cycle_dense_formula(cc):
+    """Two levels, degree-1 smoothing (x += D^-1 r / theta), exact coarse
+    solve and the coarse-grid correction scaled by cc: the cycle is the dense
+    matrix B = X + T (I - M X) with X = T + cc P (P^T M P)^-1 P^T (I - M T),
+    T = D^-1 / theta, theta the centre of [lambda/10, lambda]."""
+    S = get_assembled("channel2")
+    c = get_case("channel2")
+    adj = amg.node_adjacency(c.n_nodes, c.tets)
+    aggs = amg.build_aggregates(adj, coarse_nodes=60)[:1]
+    h = amg.AMG(S.A_F, 3, aggs, cheb_degree=1, cc_scale=cc)
+    M = S.A_F.toarray()
+    n = M.shape[0]
+    Pn = np.zeros((c.n_nodes, int(aggs[0].max()) + 1))
+    Pn[np.arange(c.n_nodes), aggs[0]] = 1
+    P = np.kron(Pn, np.eye(3))
+    lam = h.lmax[0]
+    T = np.diag(1.0 / np.diag(M)) / (0.5 * (lam + lam / 10.0))
+    I = np.eye(n)
+    Cc = cc * P @ np.linalg.solve(P.T @ M @ P, P.T)
+    pre = T                                   # x1 = T b
+    mid = pre + Cc @ (I - M @ pre)            # x2 = x1 + cc P Mc^-1 P^T (b - M x1)
+    B = mid + T @ (I - M @ mid)               # x3 = x2 + T (b - M x2)
+    b = np.random.default_rng(4).standard_normal(n)
+    assert np.abs(h.vcycle(b) - B @ b).max() <= 1e-10 * np.abs(B @ b).max()
+
+
 # --------------------------------------------------------------------------- adjoint
 
 
