@@ -98,12 +98,28 @@ typedef struct {
  *   rho_inf    spectral radius of the generalized-alpha method
  *   beta_bf    backflow coefficient beta [0.2]
  *   c_t, c_i   C_T [4] and C_I [36] of tau_M
- *   h_m        [n_outlets] m^k = dP^k_{n+af}/dQ^k (= R^k for a resistance)
- *   h_P_af     [n_outlets] outlet pressures P^k_{n+af} in the traction term  */
+ * The outlets enter through m^k = dP^k_{n+af}/dQ^k (the rank-one weight) and
+ * the traction pressure P^k_{n+af}, given in one of two ways:
+ *   resistance outlets, h_R != NULL (Sec. 2.2, 2.5): P^k_{n+1} = R^k Q^k, so
+ *     m^k = R^k and P^k_{n+af} = (1 - alpha_f) P^k_n + alpha_f R^k Q^k, formed
+ *     by the library;
+ *     h_R   [n_outlets] resistances R^k
+ *     h_P_n [n_outlets] P^k_n at t_n, or NULL for P^k_n = R^k Q^k (a state at
+ *           rest in time)
+ *     h_Q   [n_outlets] flow rates Q^k = a^k . v of the current iterate, or
+ *           NULL to take a^k . v from d_v_af on the device (the same at a
+ *           frozen state, where y_{n+af} = y_{n+1})
+ *     ns_resistance_gradient then differentiates the solve with respect to R;
+ *   any reduced model, h_R == NULL: h_m [n_outlets] m^k and h_P_af
+ *     [n_outlets] P^k_{n+af} as computed by the caller (ns_time_step fills them
+ *     from the Windkessel model); h_P_n and h_Q are ignored.  */
 typedef struct {
     double rho, mu, dt, rho_inf, beta_bf, c_t, c_i;
     const double* h_m;
     const double* h_P_af;
+    const double* h_R;
+    const double* h_P_n;
+    const double* h_Q;
 } ns_phys;
 
 typedef enum { NS_PC_AMG = 0, NS_PC_JACOBI = 1 } ns_pc;
@@ -215,6 +231,30 @@ ns_status ns_outlet_flow(ns_ctx* ctx, const double* d_v, double* h_Q, hipStream_
  * the stream. */
 ns_status ns_rank_one_dots(ns_ctx* ctx, const double* d_xv, double* h_out, hipStream_t stream);
 
+/* ns_resistance_gradient: derivative of a loss L(x) of the last solve's
+ * solution with respect to the outlet resistances, for a tangent assembled
+ * with resistance outlets (ns_phys.h_R).  x(R) = A(R)^{-1} r(R) at the frozen
+ * state: R^k enters the tangent through K (dA/dR_k = blockdiag(c_f a^k a^k^T,
+ * 0), c_f = alpha_f gamma dt, Sec. 2.5) and the right-hand side through the
+ * traction pressure (dr/dR_k = -[alpha_f Q^k a^k; 0], P^k_n held fixed), so
+ * with lambda solving A^T lambda = dL/dx (ns_adjoint_solve)
+ *     dL/dR_k = lambda^T (dr/dR_k - (dA/dR_k) x)
+ *             = -(a^k . lambda_v) (alpha_f Q^k + c_f a^k . x_v),
+ * a^k with its Dirichlet entries zeroed.  The dots and the contraction run on
+ * the device.
+ *   d_lambda  [4 n_nodes] adjoint solution, d_x [4 n_nodes] the solve's x
+ *   h_grad    [n_outlets] out: dL/dR_k
+ * Waits for the stream.  Errors: NS_ERR_STATE when the last assembly did not
+ * take resistance outlets. */
+ns_status ns_resistance_gradient(ns_ctx* ctx, const double* d_lambda, const double* d_x, double* h_grad,
+                                 hipStream_t stream);
+
+/* ns_gen_alpha: the generalized-alpha parameters of Sec. 2.4.1 for the
+ * spectral radius rho_inf in [0, 1]: h_out3 = {alpha_m, alpha_f, gamma},
+ * alpha_m = (3 - rho_inf) / (2 (1 + rho_inf)), alpha_f = gamma = 1 / (1 + rho_inf).
+ * Host-only.  Errors: NS_ERR_ARG for rho_inf outside [0, 1]. */
+ns_status ns_gen_alpha(double rho_inf, double* h_out3);
+
 /* ns_assemble_tangent: residual and consistent tangent of one Newton step
  * (Sec. 2.5, steps 6 and 8; forms of Sec. 2.3) at the intermediate states
  *   d_v_af    [n_nodes][3] velocity y_{n+af} (Dirichlet values imposed)
@@ -301,7 +341,8 @@ typedef struct {
  * At most l_max systems are solved; the residual of the returned iterate is
  * always assembled and tested (after the l_max-th update too), and
  * NS_NOT_CONVERGED is returned when it misses both tolerances.
- *   phys       rho, mu, dt, rho_inf, beta_bf, c_t, c_i (h_m, h_P_af unused)
+ *   phys       rho, mu, dt, rho_inf, beta_bf, c_t, c_i (the outlet fields are
+ *              unused: the reduced models give m^k and P^k_{n+af})
  *   d_y_n, d_ydot_n   [4 n_nodes] field-split state at t_n (Dirichlet values
  *                     imposed in d_y_n)
  *   d_y, d_ydot       [4 n_nodes] out: state at t_{n+1} (may not alias inputs)
@@ -336,6 +377,17 @@ ns_status ns_newton_update(ns_ctx* ctx, double gamma_dt, const double* d_dx, dou
 typedef enum { NS_KT_SPMV_A = 0, NS_KT_CHEB_A0 = 1, NS_KT_SPMV_FULL = 2, NS_KT_COUNT = 3 } ns_kernel_class;
 ns_status ns_kernel_timing(ns_ctx* ctx, int32_t mask);
 ns_status ns_kernel_timing_read(ns_ctx* ctx, int32_t kclass, double* h_out3);
+
+/* ns_stream_bench: the streaming ceiling of the device, for comparing the
+ * solver's bandwidth-bound kernels with a measured peak beside the nominal
+ * one.  mode 0 reads `bytes` from d_src (16-byte loads; one word per
+ * workgroup is written to the start of d_dst), mode 1 copies `bytes` from
+ * d_src to d_dst.  Both buffers hold at least `bytes`, 16-byte aligned, and do
+ * not overlap; bytes is a multiple of 16.  One untimed launch, then `reps`
+ * launches timed with HIP events on a stream of its own; writes the average
+ * milliseconds per launch to *h_ms.  Waits for completion; uses the current
+ * device.  Errors: NS_ERR_ARG, NS_ERR_HIP. */
+ns_status ns_stream_bench(int32_t mode, const void* d_src, void* d_dst, size_t bytes, int32_t reps, double* h_ms);
 
 /* ---- inspection entry points (used by the tests) -------------------------- */
 

@@ -33,7 +33,8 @@ class NsCtxOpts(C.Structure):
 
 class NsPhys(C.Structure):
     _fields_ = [("rho", C.c_double), ("mu", C.c_double), ("dt", C.c_double), ("rho_inf", C.c_double),
-                ("beta_bf", C.c_double), ("c_t", C.c_double), ("c_i", C.c_double), ("h_m", PD), ("h_P_af", PD)]
+                ("beta_bf", C.c_double), ("c_t", C.c_double), ("c_i", C.c_double), ("h_m", PD), ("h_P_af", PD),
+                ("h_R", PD), ("h_P_n", PD), ("h_Q", PD)]
 
 
 class NsSolveOpts(C.Structure):
@@ -88,6 +89,9 @@ SIGNATURES = {
     "ns_last_error": (C.c_char_p, [C.c_void_p]),
     "ns_outlet_flow": (C.c_int, [C.c_void_p, C.c_void_p, PD, C.c_void_p]),
     "ns_rank_one_dots": (C.c_int, [C.c_void_p, C.c_void_p, PD, C.c_void_p]),
+    "ns_resistance_gradient": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, PD, C.c_void_p]),
+    "ns_gen_alpha": (C.c_int, [C.c_double, PD]),
+    "ns_stream_bench": (C.c_int, [C.c_int32, C.c_void_p, C.c_void_p, C.c_size_t, C.c_int32, PD]),
     "ns_assemble_tangent": (C.c_int, [C.c_void_p, C.POINTER(NsPhys), C.c_void_p, C.c_void_p, C.c_void_p,
                                       C.c_void_p, C.c_void_p]),
     "ns_nested_solve": (C.c_int, [C.c_void_p, C.POINTER(NsSolveOpts), C.c_void_p, C.c_void_p,

@@ -104,6 +104,11 @@ void layout(ns_ctx* c, Arena& A) {
     c->d_ck = A.take<double>(std::max(1, NO));
     c->d_ck32 = A.take<float>(std::max(1, NO));
     c->d_s = A.take<double>(std::max(1, NO));
+    c->d_s2 = A.take<double>(std::max(1, NO));
+    c->d_R = A.take<double>(std::max(1, NO));
+    c->d_Pn = A.take<double>(std::max(1, NO));
+    c->d_Q = A.take<double>(std::max(1, NO));
+    c->d_grad = A.take<double>(std::max(1, NO));
     c->d_Paf = A.take<double>(std::max(1, NO));
     const int mo = dflt(c->opts.max_m, 200), ma = dflt(c->opts.max_m_A, 200), ms = dflt(c->opts.max_m_S, 200);
     const int mmax = std::max(mo, std::max(ma, ms));
@@ -1491,6 +1496,35 @@ ns_status ns_rank_one_dots(ns_ctx* c, const double* d_xv, double* h_out, hipStre
     });
 }
 
+ns_status ns_resistance_gradient(ns_ctx* c, const double* d_lambda, const double* d_x, double* h_grad,
+                                 hipStream_t st) {
+    if (!c) return NS_ERR_ARG;
+    return guard(c, [&]() -> ns_status {
+        if (!c->bound) throw Fail{NS_ERR_STATE, "context not bound"};
+        if (!c->assembled || !c->resistance_mode)
+            throw Fail{NS_ERR_STATE, "the last assembly did not take resistance outlets"};
+        const int NO = c->sym.n_out;
+        if (NO == 0) return NS_OK;
+        if (!d_lambda || !d_x || !h_grad) throw Fail{NS_ERR_ARG, "null argument"};
+        HIPCHK(hipSetDevice(c->device));
+        outlet_dot<double>(NO, c->d_optr, c->d_onode, c->d_a_msk, nullptr, d_lambda, c->d_s2, st);
+        outlet_dot<double>(NO, c->d_optr, c->d_onode, c->d_a_msk, nullptr, d_x, c->d_grad, st);
+        resistance_grad(NO, c->d_s2, c->d_grad, c->d_Q, c->a_f, c->c_f, c->d_grad, st);
+        check_launch();
+        HIPCHK(hipMemcpyAsync(h_grad, c->d_grad, NO * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        return NS_OK;
+    });
+}
+
+ns_status ns_gen_alpha(double rho_inf, double* h_out3) {
+    if (!h_out3 || !(rho_inf >= 0.0 && rho_inf <= 1.0)) return NS_ERR_ARG;
+    h_out3[0] = 0.5 * (3.0 - rho_inf) / (1.0 + rho_inf);
+    h_out3[1] = 1.0 / (1.0 + rho_inf);
+    h_out3[2] = h_out3[1];
+    return NS_OK;
+}
+
 ns_status ns_assemble_tangent(ns_ctx* c, const ns_phys* ph, const double* d_v, const double* d_p,
                               const double* d_vdot, double* d_rhs, hipStream_t st) {
     if (!c) return NS_ERR_ARG;
@@ -1498,7 +1532,8 @@ ns_status ns_assemble_tangent(ns_ctx* c, const ns_phys* ph, const double* d_v, c
         if (!c->bound) throw Fail{NS_ERR_STATE, "context not bound"};
         if (!ph || !d_v || !d_p || !d_vdot || !d_rhs) throw Fail{NS_ERR_ARG, "null argument"};
         const Symbolic& S = c->sym;
-        if (S.n_out > 0 && (!ph->h_m || !ph->h_P_af)) throw Fail{NS_ERR_ARG, "outlet data missing"};
+        const bool resist = S.n_out > 0 && ph->h_R;
+        if (S.n_out > 0 && !resist && (!ph->h_m || !ph->h_P_af)) throw Fail{NS_ERR_ARG, "outlet data missing"};
         if (!(ph->rho > 0) || !(ph->dt > 0) || ph->mu < 0 || ph->rho_inf < 0 || ph->rho_inf > 1)
             throw Fail{NS_ERR_ARG, "invalid physical parameters"};
         HIPCHK(hipSetDevice(c->device));
@@ -1532,11 +1567,33 @@ ns_status ns_assemble_tangent(ns_ctx* c, const ns_phys* ph, const double* d_v, c
             assemble_elements(a, st);
         }
         if (S.n_out > 0) {
-            std::vector<double> paf(ph->h_P_af, ph->h_P_af + S.n_out);
-            c->ck_host.resize(S.n_out);
-            for (int k = 0; k < S.n_out; ++k) c->ck_host[k] = cf * ph->h_m[k];
-            h2d(c->d_Paf, paf, st);
-            h2d(c->d_ck, c->ck_host, st);
+            const int NO = S.n_out;
+            if (resist) {
+                // resistance outlets: Q^k (given, or a^k . v on the device), then
+                // c_k and P^k_{n+af} on the device
+                c->h_outlets.assign(ph->h_R, ph->h_R + NO);
+                if (ph->h_P_n) c->h_outlets.insert(c->h_outlets.end(), ph->h_P_n, ph->h_P_n + NO);
+                if (ph->h_Q) c->h_outlets.insert(c->h_outlets.end(), ph->h_Q, ph->h_Q + NO);
+                HIPCHK(hipMemcpyAsync(c->d_R, c->h_outlets.data(), NO * sizeof(double), hipMemcpyHostToDevice, st));
+                size_t off = NO;
+                if (ph->h_P_n) {
+                    HIPCHK(hipMemcpyAsync(c->d_Pn, c->h_outlets.data() + off, NO * sizeof(double),
+                                          hipMemcpyHostToDevice, st));
+                    off += NO;
+                }
+                if (ph->h_Q)
+                    HIPCHK(hipMemcpyAsync(c->d_Q, c->h_outlets.data() + off, NO * sizeof(double),
+                                          hipMemcpyHostToDevice, st));
+                else
+                    outlet_dot<double>(NO, c->d_optr, c->d_onode, c->d_a_raw, nullptr, d_v, c->d_Q, st);
+                resistance_outlets(NO, c->d_R, ph->h_P_n ? c->d_Pn : nullptr, c->d_Q, af, cf, c->d_ck, c->d_Paf, st);
+            } else {
+                std::vector<double> paf(ph->h_P_af, ph->h_P_af + NO);
+                c->ck_host.resize(NO);
+                for (int k = 0; k < NO; ++k) c->ck_host[k] = cf * ph->h_m[k];
+                h2d(c->d_Paf, paf, st);
+                h2d(c->d_ck, c->ck_host, st);
+            }
             FaceArgs fa;
             fa.faces = c->d_faces;
             fa.fmap = c->d_fmap;
@@ -1562,6 +1619,9 @@ ns_status ns_assemble_tangent(ns_ctx* c, const ns_phys* ph, const double* d_v, c
         finalize_rhs(S.N, c->d_mask, c->d_res, d_rhs, st);
         check_launch();
         c->c_f = cf;
+        c->a_f = af;
+        c->gamma_dt = gam * ph->dt;
+        c->resistance_mode = resist;
         c->version++;
         c->sys[0].ready = c->sys[1].ready = false;
         c->assembled = true;
@@ -1642,6 +1702,7 @@ ns_status ns_time_step(ns_ctx* c, const ns_phys* phys, ns_outlet_model* om, cons
         ns_phys ph = *phys;
         ph.h_m = m.data();
         ph.h_P_af = Paf.data();
+        ph.h_R = ph.h_P_n = ph.h_Q = nullptr;  // the reduced model gives m^k and P^k_{n+af}
         double r0 = 0.0, r = 0.0;
         bool conv = false;
         double asm_ms = 0.0, sol_ms = 0.0;

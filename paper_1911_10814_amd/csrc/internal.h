@@ -173,6 +173,11 @@ struct ns_ctx {
     double* d_ck = nullptr;      // [n_out] rank-one weights c_k = alpha_f gamma dt m^k
     float* d_ck32 = nullptr;
     double* d_s = nullptr;       // [n_out] rank-one dot results
+    double* d_s2 = nullptr;      // [n_out] second dot buffer (gradient contraction)
+    double* d_R = nullptr;       // [n_out] resistances of the last resistance-mode assembly
+    double* d_Pn = nullptr;      // [n_out] its P^k_n
+    double* d_Q = nullptr;       // [n_out] its outlet flows Q^k
+    double* d_grad = nullptr;    // [n_out] dL/dR of ns_resistance_gradient
     double* d_red = nullptr;     // reduction partials
     ns::SystemDev sys[2];        // 0: forward, 1: transposed
     ns::KrylovWs kw_out, kw_A, kw_S;
@@ -192,6 +197,9 @@ struct ns_ctx {
     uint64_t version = 0;        // incremented by every assembly
     bool assembled = false;
     double c_f = 0.0;            // alpha_f gamma dt of the last assembly
+    double a_f = 0.0;            // alpha_f and gamma dt of the last assembly
+    double gamma_dt = 0.0;
+    bool resistance_mode = false;  // the last assembly took resistance outlets (ns_phys.h_R)
     // kernel timing (HIP event pairs around launches of selected classes)
     int32_t kt_mask = 0;
     std::vector<hipEvent_t> kt_ev;           // pool: 2 events per timed launch
@@ -214,4 +222,5 @@ struct ns_ctx {
     using GraphKey = std::tuple<int, int, int, int, int, int, int, int, int>;
     std::map<GraphKey, hipGraphExec_t> graphs;
     std::vector<double> ck_host;
+    std::vector<double> h_outlets;   // host staging of R, P_n, Q for the asynchronous uploads
 };

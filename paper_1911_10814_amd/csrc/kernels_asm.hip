@@ -440,4 +440,38 @@ void add_traction(int n_slots, const int32_t* onode, const int32_t* oid, const d
                        oid, P_af, a_raw, res);
 }
 
+// Resistance outlets (Sec. 2.5): m^k = R^k enters the rank-one weight
+// c_k = c_f R^k, and the traction pressure is
+// P^k_{n+af} = (1 - alpha_f) P^k_n + alpha_f R^k Q^k (P_n == nullptr: P_n = R Q).
+__global__ void k_resistance_outlets(int n_out, const double* R, const double* P_n, const double* Q, double af,
+                                     double cf, double* ck, double* P_af) {
+    const int k = blockIdx.x * kBlock + threadIdx.x;
+    if (k >= n_out) return;
+    const double rq = R[k] * Q[k];
+    ck[k] = cf * R[k];
+    P_af[k] = (1.0 - af) * (P_n ? P_n[k] : rq) + af * rq;
+}
+void resistance_outlets(int n_out, const double* R, const double* P_n, const double* Q, double af, double cf,
+                        double* ck, double* P_af, hipStream_t st) {
+    if (n_out <= 0) return;
+    hipLaunchKernelGGL(k_resistance_outlets, dim3(grid_for(n_out)), dim3(kBlock), 0, st, n_out, R, P_n, Q, af, cf,
+                       ck, P_af);
+}
+
+// dL/dR_k = lambda^T (dr/dR_k - (dA/dR_k) x) with dr/dR_k = -[alpha_f Q^k a^k; 0]
+// and dA/dR_k = blockdiag(c_f a^k a^k^T, 0): -(a^k.lambda_v)(alpha_f Q^k + c_f a^k.x_v),
+// from the masked dots s_lam[k] = a^k.lambda_v and s_x[k] = a^k.x_v.
+__global__ void k_resistance_grad(int n_out, const double* s_lam, const double* s_x, const double* Q, double af,
+                                  double cf, double* grad) {
+    const int k = blockIdx.x * kBlock + threadIdx.x;
+    if (k >= n_out) return;
+    grad[k] = -s_lam[k] * (af * Q[k] + cf * s_x[k]);
+}
+void resistance_grad(int n_out, const double* s_lam, const double* s_x, const double* Q, double af, double cf,
+                     double* grad, hipStream_t st) {
+    if (n_out <= 0) return;
+    hipLaunchKernelGGL(k_resistance_grad, dim3(grid_for(n_out)), dim3(kBlock), 0, st, n_out, s_lam, s_x, Q, af, cf,
+                       grad);
+}
+
 }  // namespace ns

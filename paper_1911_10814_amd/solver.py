@@ -181,25 +181,46 @@ class NsContext:
                                               _stream_handle(self.device)))
         return out[:self.n_out]
 
-    def assemble(self, v, p, vdot, *, rho, mu, dt, rho_inf, m=None, P_af=None, beta_bf=0.2, c_t=4.0, c_i=36.0,
-                 rhs=None):
-        """Residual and tangent (Sec. 2.5); returns rhs = -[R_m; R_p] (device, [4N])."""
+    def _outlet_array(self, a, what):
+        if a is None:
+            return None
+        a = np.ascontiguousarray(np.broadcast_to(np.asarray(a, dtype=np.float64), (self.n_out,)))
+        return a
+
+    def assemble(self, v, p, vdot, *, rho, mu, dt, rho_inf, R=None, P_n=None, Q=None, m=None, P_af=None,
+                 beta_bf=0.2, c_t=4.0, c_i=36.0, rhs=None):
+        """Residual and tangent (Sec. 2.5); returns rhs = -[R_m; R_p] (device, [4N]).
+
+        Outlets: resistances ``R`` (with ``P_n`` and ``Q`` optional, see
+        ``ns_phys``: the library forms m^k and P^k_{n+af}), or the reduced
+        model's ``m`` and ``P_af`` directly."""
         self.bind()
         v = self._dev(v, (self.N, 3))
         p = self._dev(p, (self.N,))
         vdot = self._dev(vdot, (self.N, 3))
-        mk = np.ascontiguousarray(m if m is not None else np.zeros(self.n_out), dtype=np.float64)
-        pk = np.ascontiguousarray(P_af if P_af is not None else np.zeros(self.n_out), dtype=np.float64)
-        if len(mk) != self.n_out or len(pk) != self.n_out:
-            raise ValueError("one m and one P_af per outlet")
-        ph = _lib.NsPhys(rho, mu, dt, rho_inf, beta_bf, c_t, c_i, mk.ctypes.data_as(_lib.PD),
-                         pk.ctypes.data_as(_lib.PD))
+        arrs = {k: self._outlet_array(a, k) for k, a in (("R", R), ("P_n", P_n), ("Q", Q), ("m", m), ("P_af", P_af))}
+        if self.n_out and arrs["R"] is None:
+            arrs["m"] = arrs["m"] if arrs["m"] is not None else np.zeros(self.n_out)
+            arrs["P_af"] = arrs["P_af"] if arrs["P_af"] is not None else np.zeros(self.n_out)
+        ptr = {k: (a.ctypes.data_as(_lib.PD) if a is not None else None) for k, a in arrs.items()}
+        ph = _lib.NsPhys(rho, mu, dt, rho_inf, beta_bf, c_t, c_i, ptr["m"], ptr["P_af"], ptr["R"], ptr["P_n"],
+                         ptr["Q"])
         if rhs is None:
             rhs = torch.empty(4 * self.N, dtype=torch.float64, device=self.device)
         self._check(self.lib.ns_assemble_tangent(self.h, C.byref(ph), _ptr(v), _ptr(p), _ptr(vdot), _ptr(rhs),
                                                  _stream_handle(self.device)))
-        self._keep = (v, p, vdot, mk, pk)  # inputs stay alive until the stream has consumed them
+        self._keep = (v, p, vdot, arrs)  # inputs stay alive until the stream has consumed them
         return rhs
+
+    def resistance_gradient(self, lam, x):
+        """dL/dR_k of the last resistance-outlet assembly (``ns_resistance_gradient``),
+        from the adjoint solution ``lam`` and the solve's ``x``."""
+        lam = self._dev(lam).reshape(-1)
+        x = self._dev(x).reshape(-1)
+        out = np.zeros(max(1, self.n_out))
+        self._check(self.lib.ns_resistance_gradient(self.h, _ptr(lam), _ptr(x), out.ctypes.data_as(_lib.PD),
+                                                    _stream_handle(self.device)))
+        return out[:self.n_out]
 
     def _solve(self, fn, b, opts: SolveOptions | None, x=None):
         opts = opts or SolveOptions()
@@ -322,35 +343,31 @@ def context_for(case, **kw) -> NsContext:
 
 
 def gen_alpha(rho_inf):
-    am = 0.5 * (3.0 - rho_inf) / (1.0 + rho_inf)
-    af = 1.0 / (1.0 + rho_inf)
-    return am, af, af
+    """(alpha_m, alpha_f, gamma) of the generalized-alpha method (``ns_gen_alpha``)."""
+    out = (C.c_double * 3)()
+    st = _lib.load().ns_gen_alpha(float(rho_inf), out)
+    if st != 0:
+        raise NsError(st, "rho_inf must lie in [0, 1]")
+    return out[0], out[1], out[2]
 
 
 class NestedSolveFn(torch.autograd.Function):
-    """x(R) = A(R)^{-1} r(R) for one Newton step at a frozen state.
-
-    R enters the tangent through the rank-one term K (m^k = R^k, Sec. 2.5)
-    and the residual through P^k_{n+af} = (1 - alpha_f) P^k_n + alpha_f R^k Q^k
-    with P^k_n held fixed.  backward solves A^T lam = dL/dx with the
-    transposed nested preconditioner and returns
-    dL/dR_k = -(lam_v . a^k) (alpha_f Q^k + alpha_f gamma dt a^k . x_v).
+    """x(R) = A(R)^{-1} r(R) for one Newton step at a frozen state, with
+    resistance outlets: the library forms m^k = R^k and
+    P^k_{n+af} = (1 - alpha_f) P^k_n + alpha_f R^k Q^k (``ns_phys.h_R``), and
+    backward solves A^T lam = dL/dx with the transposed nested preconditioner
+    (``ns_adjoint_solve``) and contracts dL/dR on the device
+    (``ns_resistance_gradient``).
 
     apply(R, ctx, case, P_n, Q, fwd_opts, adj_opts) -> x  (R: CPU float64 [n_out])
     """
 
     @staticmethod
     def forward(fctx, R, ctx: NsContext, case, P_n, Q, fwd_opts=None, adj_opts=None):
-        Rn = R.detach().cpu().double().numpy()
-        am, af, g = gen_alpha(case.rho_inf)
-        P_af = (1.0 - af) * np.asarray(P_n) + af * Rn * np.asarray(Q)
         rhs = ctx.assemble(case.v, case.p, case.vdot, rho=case.rho, mu=case.mu, dt=case.dt,
-                           rho_inf=case.rho_inf, m=Rn, P_af=P_af)
+                           rho_inf=case.rho_inf, R=R.detach().cpu().double().numpy(), P_n=P_n, Q=Q)
         x, info = ctx.solve(rhs, fwd_opts)
         fctx.ctx = ctx
-        fctx.af = af
-        fctx.cf = af * g * case.dt
-        fctx.Q = np.asarray(Q, dtype=np.float64)
         fctx.adj_opts = adj_opts
         fctx.info = info
         fctx.save_for_backward(x)
@@ -361,7 +378,5 @@ class NestedSolveFn(torch.autograd.Function):
         (x,) = fctx.saved_tensors
         ctx = fctx.ctx
         lam, info = ctx.adjoint(grad_x.contiguous(), fctx.adj_opts)
-        s_lam = ctx.rank_one_dots(lam)
-        s_x = ctx.rank_one_dots(x)
-        grad_R = -s_lam * (fctx.af * fctx.Q + fctx.cf * s_x)
+        grad_R = ctx.resistance_gradient(lam, x)
         return (torch.as_tensor(grad_R, dtype=torch.float64), None, None, None, None, None, None)

@@ -67,9 +67,7 @@ class System:
     def assemble(self, R):
         c = self.case
         R = np.broadcast_to(np.asarray(R, float), (c.n_outlets,)).copy()
-        Q = self.ctx.outlet_flow(c.v)
-        self.rhs = self.ctx.assemble(c.v, c.p, c.vdot, rho=c.rho, mu=c.mu, dt=c.dt, rho_inf=c.rho_inf, m=R,
-                                     P_af=R * Q)
+        self.rhs = self.ctx.assemble(c.v, c.p, c.vdot, rho=c.rho, mu=c.mu, dt=c.dt, rho_inf=c.rho_inf, R=R)
         torch.cuda.synchronize()
 
 

@@ -88,8 +88,7 @@ class Full:
     def set_R(self, R):
         c = self.case
         self.R = np.asarray(R, float)
-        self.rhs = self.ctx.assemble(c.v, c.p, c.vdot, rho=c.rho, mu=c.mu, dt=c.dt, rho_inf=c.rho_inf, m=self.R,
-                                     P_af=self.R * self.Q)
+        self.rhs = self.ctx.assemble(c.v, c.p, c.vdot, rho=c.rho, mu=c.mu, dt=c.dt, rho_inf=c.rho_inf, R=self.R)
         self.S = patch_oracle(c, self.nodes, self.R, self.R * self.Q)
 
     def residual_rows(self, b, x, transposed=False):
@@ -163,40 +162,53 @@ def _rel(a, b):
     return np.linalg.norm(a - b) / np.linalg.norm(b)
 
 
+# Configurations where an FP64 solve stopped at rtol 1e-8 lands within 1e-7 of
+# the tight reference, so rtol 1e-8 determines x to 1e-6 with a 10x margin
+# (measured before these bounds were set): the FP32-inner 1e-6 target is
+# asserted at rtol 1e-8 there.  Elsewhere rtol 1e-8 does not determine x to
+# 1e-6 for either precision (conditioning), the rtol-1e-8 errors are reported,
+# and the precision claim is asserted at rtol 1e-12.
+ASSERT_AT_1E8 = {"pipe_200k", "pipe_2m", "ybif_1m"}
+TIGHT = dict(rtol=1e-12, pc_A="jacobi")
+
+
+def _errors(x, xr, n3):
+    return _rel(x[:n3], xr[:n3]), _rel(x[n3:], xr[n3:])
+
+
 def test_solves_fp64_and_fp32_inner(full):
-    """FP64 and FP32-inner solves at rtol 1e-8.  Their solutions agree to
-    1e-6 when the tangent is well conditioned.  Otherwise the error of either
-    solve is bounded only by its final true relative residual times the
-    conditioning, so both are compared with an FP64 reference at rtol 1e-10
-    per unit of their own final residual.  That ratio depends on the direction
-    of the final residual (the FP64 solve's ratio is only a lower bound on the
-    condition number, and FP32 rounding in the preconditioner turns the
-    residual), so the FP32-inner error per unit residual must stay within 10x
-    the FP64 solve's."""
+    """FP64 and FP32-inner solves at rtol 1e-8 (default options) against an
+    FP64 reference at rtol 1e-12: the FP32-inner error is <= 1e-6 where rtol
+    1e-8 determines x to that accuracy (ASSERT_AT_1E8), reported elsewhere;
+    the FP32-inner solve at rtol 1e-12 is within 1e-6 of the reference on
+    every configuration."""
     from paper_1911_10814_amd import SolveOptions
+    name = full.case.name
     n3 = 3 * full.case.n_nodes
     x64, i64 = _solve_and_check(full, SolveOptions(precision="fp64"), "fp64", with_info=True)
     x32, i32 = _solve_and_check(full, SolveOptions(precision="fp32_inner"), "fp32_inner", with_info=True)
-    ev, ep = _rel(x32[:n3], x64[:n3]), _rel(x32[n3:], x64[n3:])
-    print(full.case.name, "fp32_inner vs fp64: v %.2e p %.2e" % (ev, ep), flush=True)
-    if ev <= 1e-6 and ep <= 1e-6:
-        return
-    xr = _solve_and_check(full, SolveOptions(precision="fp64", rtol=1e-10), "fp64 reference")
-    r64, r32 = i64["true_rel_res"], i32["true_rel_res"]
-    for part in (slice(0, n3), slice(n3, None)):
-        e64, e32 = _rel(x64[part], xr[part]), _rel(x32[part], xr[part])
-        print(full.case.name, f"error vs reference: fp64 {e64:.2e} (res {r64:.2e}) fp32_inner {e32:.2e} "
-              f"(res {r32:.2e})", flush=True)
-        assert e32 <= max(1e-6, 10 * (e64 / r64) * r32)
+    xr = _solve_and_check(full, SolveOptions(precision="fp64", **TIGHT), "fp64 reference rtol 1e-12")
+    x32t = _solve_and_check(full, SolveOptions(precision="fp32_inner", **TIGHT), "fp32_inner rtol 1e-12")
+    e64, e32, e32t = _errors(x64, xr, n3), _errors(x32, xr, n3), _errors(x32t, xr, n3)
+    print(name, "error vs the rtol-1e-12 reference (v, p): fp64@1e-8 %.2e %.2e (res %.2e), fp32_inner@1e-8 %.2e %.2e "
+          "(res %.2e), fp32_inner@1e-12 %.2e %.2e" % (*e64, i64["true_rel_res"], *e32, i32["true_rel_res"], *e32t),
+          flush=True)
+    if name in ASSERT_AT_1E8:
+        assert max(e32) <= 1e-6
+    elif max(e32) > 1e-6:
+        print(name, "fp32_inner at rtol 1e-8 misses 1e-6 (conditioning: fp64 at rtol 1e-8 is %.2e off)" % max(e64),
+              flush=True)
+    assert max(e32t) <= 1e-6
 
 
 def test_resistance_sweep(full):
     """Outlet resistance sweep on the 2e6-node pipe (the Schur complement
     stiffens with R), intermediate and Schur tolerances 1e-4, inner 1e-2.
-    The tangent's conditioning grows with R, so at rtol 1e-8 even the FP64
-    solution is only as close to the exact one as its residual allows; both
-    solves are compared with an FP64 reference at rtol 1e-12, and the
-    FP32-inner error must stay within 1e-6 or within 10x the FP64 solve's."""
+    Errors against an FP64 reference at rtol 1e-12: the FP32-inner solve at
+    rtol 1e-8 is within 1e-6 at R = 1e2 (where the FP64 solve at rtol 1e-8 is
+    within 1e-7); at R = 1e4 and 1e6 rtol 1e-8 does not determine x to 1e-6
+    and the errors are reported; at every R the FP32-inner solve at rtol 1e-12
+    is within 1e-6 of the reference."""
     if full.case.name != "pipe_2m":
         pytest.skip("the resistance sweep runs on the 2e6-node pipe")
     from paper_1911_10814_amd import SolveOptions
@@ -209,12 +221,43 @@ def test_resistance_sweep(full):
             xr = _solve_and_check(full, SolveOptions(precision="fp64", rtol=1e-12, **kw), f"R={R:g} fp64 reference")
             x64 = _solve_and_check(full, SolveOptions(precision="fp64", **kw), f"R={R:g} fp64")
             x32 = _solve_and_check(full, SolveOptions(precision="fp32_inner", **kw), f"R={R:g} fp32_inner")
-            for part in (slice(0, n3), slice(n3, None)):
-                e64, e32 = _rel(x64[part], xr[part]), _rel(x32[part], xr[part])
-                print(f"R={R:g} error vs reference: fp64 {e64:.2e} fp32_inner {e32:.2e}", flush=True)
-                assert e32 <= max(1e-6, 10 * e64)
+            x32t = _solve_and_check(full, SolveOptions(precision="fp32_inner", rtol=1e-12, **kw),
+                                    f"R={R:g} fp32_inner rtol 1e-12")
+            e64, e32, e32t = _errors(x64, xr, n3), _errors(x32, xr, n3), _errors(x32t, xr, n3)
+            print(f"R={R:g} error vs reference (v, p): fp64@1e-8 {e64[0]:.2e} {e64[1]:.2e}, fp32_inner@1e-8 "
+                  f"{e32[0]:.2e} {e32[1]:.2e}, fp32_inner@1e-12 {e32t[0]:.2e} {e32t[1]:.2e}", flush=True)
+            if R == 1e2:
+                assert max(e32) <= 1e-6
+            assert max(e32t) <= 1e-6
     finally:
         full.set_R(base)
+
+
+def test_fp64_replay_matches_oracle_on_the_benchmark_pipe(full):
+    """FP64 nested solve of the 2e5-node pipe on the oracle's iteration path
+    (its per-call iteration counts, stored with its solution's norms and
+    sampled entries by tests/golden/make_pipe_200k_replay.py): within 1e-10
+    relative, velocity and pressure blocks separately."""
+    if full.case.name != "pipe_200k":
+        pytest.skip("the stored oracle solve is of the 2e5-node pipe")
+    import json
+    import os
+    from paper_1911_10814_amd import SolveOptions
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "pipe_200k_fp64_replay.json")))
+    n3 = 3 * full.case.n_nodes
+    assert abs(float(torch.linalg.norm(full.rhs)) - g["norm_rhs"]) <= 1e-13 * g["norm_rhs"]
+    x, info = full.ctx.solve(full.rhs, SolveOptions(schedule=g["schedule"]))
+    assert info["schedule"] == g["schedule"]
+    x = x.cpu().numpy()
+    idx = np.array(g["idx"])
+    xo = np.array(g["x"])
+    v, p = idx < n3, idx >= n3
+    ev = np.linalg.norm(x[idx[v]] - xo[v]) / np.linalg.norm(xo[v])
+    ep = np.linalg.norm(x[idx[p]] - xo[p]) / np.linalg.norm(xo[p])
+    nv = abs(np.linalg.norm(x[:n3]) - g["norm_v"]) / g["norm_v"]
+    np_ = abs(np.linalg.norm(x[n3:]) - g["norm_p"]) / g["norm_p"]
+    print("pipe_200k fp64 replay: sampled error v %.2e p %.2e, norms %.2e %.2e" % (ev, ep, nv, np_), flush=True)
+    assert max(ev, ep, nv, np_) <= 1e-10
 
 
 def test_adjoint_sampled_rows(full):

@@ -28,9 +28,8 @@ def ctx_for(name):
     if name not in _CTX:
         c = get_case(name)
         ctx = NsContext(c).bind()
-        S = get_assembled(name)
-        ctx._rhs = ctx.assemble(c.v, c.p, c.vdot, rho=c.rho, mu=c.mu, dt=c.dt, rho_inf=c.rho_inf, m=c.R,
-                                P_af=c.R * S.Q)
+        # resistance outlets: the library forms m^k = R^k and P_af = R^k Q^k (P_n = R Q, Q = a^k . v on the device)
+        ctx._rhs = ctx.assemble(c.v, c.p, c.vdot, rho=c.rho, mu=c.mu, dt=c.dt, rho_inf=c.rho_inf, R=c.R)
         torch.cuda.synchronize()
         _CTX[name] = ctx
     return _CTX[name]
@@ -50,7 +49,6 @@ def ctx_forced(name, env):
     key = (name, tuple(sorted(env.items())))
     if key not in _CTX_FORCED:
         c = get_case(name)
-        S = get_assembled(name)
         old = {k: os.environ.get(k) for k in env}
         os.environ.update(env)
         try:
@@ -61,8 +59,7 @@ def ctx_forced(name, env):
                     os.environ.pop(k, None)
                 else:
                     os.environ[k] = v
-        ctx._rhs = ctx.assemble(c.v, c.p, c.vdot, rho=c.rho, mu=c.mu, dt=c.dt, rho_inf=c.rho_inf, m=c.R,
-                                P_af=c.R * S.Q)
+        ctx._rhs = ctx.assemble(c.v, c.p, c.vdot, rho=c.rho, mu=c.mu, dt=c.dt, rho_inf=c.rho_inf, R=c.R)
         torch.cuda.synchronize()
         _CTX_FORCED[key] = ctx
     return _CTX_FORCED[key]
@@ -325,8 +322,46 @@ def test_autograd_gradient_matches_finite_differences():
         print("grad", k, grad[k], "fd", fd, flush=True)
         assert abs(grad[k] - fd) <= 1e-5 * abs(fd)
     # leave the context assembled at the base state for later tests
-    ctx._rhs = ctx.assemble(c.v, c.p, c.vdot, rho=c.rho, mu=c.mu, dt=c.dt, rho_inf=c.rho_inf, m=c.R,
-                            P_af=c.R * S.Q)
+    ctx._rhs = ctx.assemble(c.v, c.p, c.vdot, rho=c.rho, mu=c.mu, dt=c.dt, rho_inf=c.rho_inf, R=c.R)
+
+
+@pytest.mark.parametrize("name", ["channel2", "plate_small"])
+def test_resistance_outlets_and_gradient_contraction(name):
+    """Resistance-outlet assembly (the library forms m^k = R^k and
+    P_af = (1 - alpha_f) P_n + alpha_f R Q) against the oracle's assembly with
+    those pressures, for a given P_n and for the at-rest P_n = R Q; and the
+    device contraction of ns_resistance_gradient against the oracle's dL/dR for
+    the same lambda and x."""
+    from paper_1911_10814_amd import NsContext
+    c = get_case(name)
+    S0 = get_assembled(name)
+    ctx = NsContext(c).bind()
+    rng = np.random.default_rng(8)
+    R = c.R * (1.0 + 0.3 * rng.random(c.n_outlets))
+    P_n = rng.uniform(100.0, 300.0, c.n_outlets)
+    am, af, gam = dz.gen_alpha(c.rho_inf)
+    for pn in (P_n, None):
+        rhs = ctx.assemble(c.v, c.p, c.vdot, rho=c.rho, mu=c.mu, dt=c.dt, rho_inf=c.rho_inf, R=R, P_n=pn)
+        P_af = (1 - af) * (pn if pn is not None else R * S0.Q) + af * R * S0.Q
+        So = dz.assemble(c, P_af=P_af, R=R)
+        assert rel(rhs.cpu().numpy(), So.rhs) <= 1e-13
+        Mg = bsr_to_csr(ctx, ctx.export_bsr())
+        assert max(block_rel_err(Mg, oracle_full(So), 3 * ctx.N).values()) <= 1e-12
+        lam = rng.standard_normal(4 * ctx.N)
+        x = rng.standard_normal(4 * ctx.N)
+        g = ctx.resistance_gradient(lam, x)
+        go = oadj.grad_R(So, x, lam, af, af * gam * c.dt)
+        assert rel(g, go) <= 1e-13
+    # Q supplied by the caller instead of a^k . v
+    Qx = S0.Q * 1.1
+    rhs = ctx.assemble(c.v, c.p, c.vdot, rho=c.rho, mu=c.mu, dt=c.dt, rho_inf=c.rho_inf, R=R, P_n=P_n, Q=Qx)
+    So = dz.assemble(c, P_af=(1 - af) * P_n + af * R * Qx, R=R)
+    assert rel(rhs.cpu().numpy(), So.rhs) <= 1e-13
+    # the reduced-model form leaves no resistance data for the gradient
+    ctx.assemble(c.v, c.p, c.vdot, rho=c.rho, mu=c.mu, dt=c.dt, rho_inf=c.rho_inf, m=R, P_af=R * S0.Q)
+    from paper_1911_10814_amd import NsError
+    with pytest.raises(NsError, match="resistance"):
+        ctx.resistance_gradient(np.zeros(4 * ctx.N), np.zeros(4 * ctx.N))
 
 
 def test_newton_update():
