@@ -367,22 +367,32 @@ ns_status ns_newton_update(ns_ctx* ctx, double gamma_dt, const double* d_dx, dou
  *   NS_KT_CHEB_A0   the fused residual + Chebyshev step on the finest level of
  *                   the A hierarchy
  *   NS_KT_SPMV_FULL the 4x4 field-split SpMV of the outer FGMRES
+ *   NS_KT_SFACT     the factored S_hat = D - C diag(A)^-1 B on the finest
+ *                   S_hat level (two launches timed as one: the B pass and the
+ *                   D, C pass with the smoothing or residual epilogue)
+ *   NS_KT_CGS2      one CGS2 orthogonalisation step, any Krylov level (four
+ *                   launches timed as one; bytes with k = j + 1 basis vectors
+ *                   of length n: (4k + 8) n values)
+ *   NS_KT_CHEB_S1   a Chebyshev step on level 1 of the S_hat hierarchy
  * ns_kernel_timing(ctx, mask) enables timing of the classes in `mask` (bit
  * 1 << class) for later solves (0 disables); every timed launch is bracketed
- * by two events from a pool of 16384 pairs (launches beyond it are not
+ * by two events from a pool of 65536 pairs per solve (launches beyond it are not
  * timed).  ns_kernel_timing_read(ctx, class, out3) returns and clears
  * out3 = {launches, total milliseconds, algorithmic bytes moved}; the bytes
  * count one read of the matrix values, column indices and row pointers, one
  * read of every input vector entry and one write of every output entry. */
-typedef enum { NS_KT_SPMV_A = 0, NS_KT_CHEB_A0 = 1, NS_KT_SPMV_FULL = 2, NS_KT_COUNT = 3 } ns_kernel_class;
+typedef enum {
+    NS_KT_SPMV_A = 0, NS_KT_CHEB_A0 = 1, NS_KT_SPMV_FULL = 2, NS_KT_SFACT = 3, NS_KT_CGS2 = 4, NS_KT_CHEB_S1 = 5,
+    NS_KT_COUNT = 6
+} ns_kernel_class;
 ns_status ns_kernel_timing(ns_ctx* ctx, int32_t mask);
 ns_status ns_kernel_timing_read(ns_ctx* ctx, int32_t kclass, double* h_out3);
 
 /* ns_stream_bench: the streaming ceiling of the device, for comparing the
  * solver's bandwidth-bound kernels with a measured peak beside the nominal
- * one.  mode 0 reads `bytes` from d_src (16-byte loads; one word per
- * workgroup is written to the start of d_dst), mode 1 copies `bytes` from
- * d_src to d_dst.  Both buffers hold at least `bytes`, 16-byte aligned, and do
+ * one.  mode 0 reads `bytes` from d_src (16-byte loads; the first 4 KiB of
+ * d_dst may be written), mode 1 copies `bytes` from d_src to d_dst.  Both
+ * buffers hold at least `bytes` (>= 4 KiB in mode 0), 16-byte aligned, and do
  * not overlap; bytes is a multiple of 16.  One untimed launch, then `reps`
  * launches timed with HIP events on a stream of its own; writes the average
  * milliseconds per launch to *h_ms.  Waits for completion; uses the current

@@ -304,7 +304,7 @@ def ybif(size: str = "ybif_1m", seed: int = 4, R=(1.5e3, 3.0e3), umax: float = 3
 CONEXP_SIZES = {
     # name: (m, nr, annulus rings, cone layers, throat layers, expansion layers)
     "conexp_small": (6, 3, 4, 6, 10, 16),
-    "conexp_23k": (5, 3, 4, 18, 36, 100),     # a CPU-sized sample of the same recipe (22 960 nodes)
+    "conexp_60k": (8, 4, 6, 20, 40, 120),     # a CPU-sized sample of the same recipe (61 061 nodes)
     "conexp_150k": (10, 5, 8, 30, 60, 180),   # the size of the paper's nozzle mesh (~1.4e5 vertices)
     "conexp_4m": (24, 10, 20, 100, 200, 1000),
 }

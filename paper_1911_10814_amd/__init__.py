@@ -5,5 +5,5 @@ The computation lives in the HIP library ``libns_hip.so`` (C ABI in
 ``include/ns_api.h``); this package only marshals arguments and uses PyTorch
 for device memory and streams.
 """
-from .solver import NestedSolveFn, NsContext, SolveOptions, context_for, gen_alpha  # noqa: F401
+from .solver import NestedSolveFn, NsContext, SolveOptions, context_for, gen_alpha, stream_bench  # noqa: F401
 from ._lib import NsError, load  # noqa: F401

@@ -11,7 +11,7 @@ NS_OK, NS_NOT_CONVERGED = 0, 1
 STATUS_NAMES = {0: "NS_OK", 1: "NS_NOT_CONVERGED", -1: "NS_ERR_ARG", -2: "NS_ERR_HIP", -3: "NS_ERR_NAN",
                 -4: "NS_ERR_BREAKDOWN", -5: "NS_ERR_WORKSPACE", -6: "NS_ERR_STATE"}
 
-KERNEL_CLASSES = {"spmv_A": 0, "cheb_A0": 1, "spmv_full": 2}
+KERNEL_CLASSES = {"spmv_A": 0, "cheb_A0": 1, "spmv_full": 2, "sfact": 3, "cgs2": 4, "cheb_S1": 5}
 
 OPS = {"full": 0, "A": 1, "B": 2, "C": 3, "D": 4, "shat": 5, "vcycle_A": 6, "vcycle_S": 7, "schur": 8,
        "pscr": 9, "solve_A": 10, "psimple": 11}

@@ -261,7 +261,7 @@ void h2d(T* d, const std::vector<T>& v, hipStream_t st) {
 // Kernel timing: bracket launches of selected classes with event pairs
 // ---------------------------------------------------------------------------
 
-constexpr size_t kTimingPairs = 16384;
+constexpr size_t kTimingPairs = 65536;
 
 template <typename F>
 void timed(ns_ctx* c, int cls, double bytes, hipStream_t st, F&& launch) {
@@ -453,7 +453,13 @@ void cgs2_launch(ns_ctx* c, KrylovWs& kw, int64_t n, int j, T* V, hipStream_t st
     ga.g = kw.g;
     ga.status = kw.status;
     ga.hstatus = c->d_mapped + kMapStatus + 2 * slot;
-    arnoldi_cgs2<T>(n, j, V, kw.ld, V + (int64_t)(j + 1) * kw.ld, kw.h, kw.h + (kw.m + 2), ga, c->d_red, st);
+    // algorithmic bytes of the four kernels with k = j + 1 basis vectors: pass-1
+    // dots (k + 1 vectors read), pass-1 update and pass-2 dots (2k + 2 read, 1
+    // written), pass-2 update (k + 1 read, 1 written), normalisation (1 + 1)
+    const double bytes = (4.0 * (j + 1) + 8.0) * (double)n * sizeof(T);
+    timed(c, NS_KT_CGS2, bytes, st, [&] {
+        arnoldi_cgs2<T>(n, j, V, kw.ld, V + (int64_t)(j + 1) * kw.ld, kw.h, kw.h + (kw.m + 2), ga, c->d_red, st);
+    });
     check_launch();
 }
 
@@ -639,6 +645,23 @@ struct Nested {
         M.xcd = xcd_rows(d.n, d.bs);
         return M;
     }
+    // Factored S_hat application (both passes), timed as one class.
+    // Algorithmic bytes: pass 1 reads the three B planes and the column
+    // indices, row pointers, x, diag(A)^-1 and writes t (3 per node); pass 2
+    // reads the three C planes, the D plane, columns, row pointers, x, t and
+    // writes y, plus the Chebyshev operands (b, dinv, d) when smoothing.
+    void sfact(const T* x, const int32_t* agg, const T* ec, T* y, T alpha, const T* z, T beta, const T* b,
+               const T* dinv, const T* coef, int step, T* d) {
+        const double sz = sizeof(T), n = N;
+        double bytes = (double)nnzb * (7 * sz + 8) + 8.0 * (n + 1) + n * sz * (1 + 3 + 3) + n * sz * (1 + 3 + 1);
+        if (coef) bytes += n * sz * (step != 0 ? 4 : 3);
+        else if (z) bytes += n * sz;
+        if (agg) bytes += 2 * n * (4 + sz);
+        timed(c, NS_KT_SFACT, bytes, K.st, [&] {
+            shat_factored<T>(N, c->d_rp, c->d_col, V(), nnzb, Typed<T>::dinvA(sy), x, agg, ec, as<T>(c->t_sf), y,
+                             alpha, z, beta, b, dinv, coef, step, d, xcd_rows(N, 1), K.st);
+        });
+    }
     RankOne<T> rank_one() const {
         RankOne<T> r;
         if (c->sym.n_out == 0) return r;
@@ -695,7 +718,6 @@ struct Nested {
         const bool tme = (l == 0 && bs == 3);
         // finest S_hat level: applied in factored form D - C diag(A)^{-1} B
         const bool sfact = (l == 0 && &H == &sy.S);
-        T* tsf = as<T>(c->t_sf);
         const double sz = sizeof(T);
         // algorithmic bytes: matrix values, columns and row pointers once; reads
         // x, b, dinv, the extra diagonal and d (steps after the first); writes d and x
@@ -705,8 +727,10 @@ struct Nested {
                 timed(c, NS_KT_CHEB_A0, bytes, st,
                       [&] { cheb_step<T>(bs, M, xi, xo, d, b, dinv, coef, step, agg, ec, st); });
             else if (sfact)
-                shat_factored<T>(N, c->d_rp, c->d_col, V(), nnzb, Typed<T>::dinvA(sy), xi, agg, ec, tsf, xo, T(1),
-                                 nullptr, T(0), b, dinv, coef, step, d, xcd_rows(N, 1), st);
+                this->sfact(xi, agg, ec, xo, T(1), nullptr, T(0), b, dinv, coef, step, d);
+            else if (l == 1 && &H == &sy.S)
+                timed(c, NS_KT_CHEB_S1, (double)L.nnz * (sz + 4) + 4.0 * (L.n + 1) + sz * nv * (step != 0 ? 7 : 6),
+                      st, [&] { cheb_step<T>(bs, M, xi, xo, d, b, dinv, coef, step, agg, ec, st); });
             else
                 cheb_step<T>(bs, M, xi, xo, d, b, dinv, coef, step, agg, ec, st);
         };
@@ -730,8 +754,7 @@ struct Nested {
                 timed(c, NS_KT_SPMV_A, bytes, st,
                       [&] { spmv<T>(bs, bs, M, a, as<T>(L.r), T(-1), b, T(1), nullptr, nullptr, st); });
             } else if (sfact) {
-                shat_factored<T>(N, c->d_rp, c->d_col, V(), nnzb, Typed<T>::dinvA(sy), a, nullptr, nullptr, tsf,
-                                 as<T>(L.r), T(-1), b, T(1), nullptr, nullptr, nullptr, 0, nullptr, xcd_rows(N, 1), st);
+                this->sfact(a, nullptr, nullptr, as<T>(L.r), T(-1), b, T(1), nullptr, nullptr, nullptr, 0, nullptr);
             } else {
                 spmv<T>(bs, bs, M, a, as<T>(L.r), T(-1), b, T(1), nullptr, nullptr, st);
             }
@@ -777,9 +800,7 @@ struct Nested {
         T* t = as<T>(c->t_ps);
         T* e = t + N;
         for (int i = 1; i < k; ++i) {
-            shat_factored<T>(N, c->d_rp, c->d_col, V(), nnzb, Typed<T>::dinvA(sy), z, nullptr, nullptr,
-                             as<T>(c->t_sf), t, T(-1), r, T(1), nullptr, nullptr, nullptr, 0, nullptr, xcd_rows(N, 1),
-                             K.st);
+            sfact(z, nullptr, nullptr, t, T(-1), r, T(1), nullptr, nullptr, nullptr, 0, nullptr);
             vcycle(sy.S, 0, t, e);
             axpby<T>(N, T(1), e, T(1), z, z, K.st);
         }
@@ -832,9 +853,7 @@ struct Nested {
     // step is one graph.
     int solveShat(const T* b, T* x) {
         auto applyM = [this](const T* in, T* out) {
-            shat_factored<T>(N, c->d_rp, c->d_col, V(), nnzb, Typed<T>::dinvA(sy), in, nullptr, nullptr,
-                             as<T>(c->t_sf), out, T(1), nullptr, T(0), nullptr, nullptr, nullptr, 0, nullptr,
-                             xcd_rows(N, 1), K.st);
+            sfact(in, nullptr, nullptr, out, T(1), nullptr, T(0), nullptr, nullptr, nullptr, 0, nullptr);
         };
         return gmres_left<T>(K, c->kw_S, N, applyM, [this](const T* in, T* out) { applyPS(in, out); }, b, x,
                              dfltd(K.o.rtol_S, 1e-3), dflt(K.o.m_S, 200), dflt(K.o.nmax_S, 200), kKindShat, true);

@@ -204,7 +204,7 @@ struct ns_ctx {
     int32_t kt_mask = 0;
     std::vector<hipEvent_t> kt_ev;           // pool: 2 events per timed launch
     std::vector<std::pair<int, double>> kt_pending;  // (class, bytes) per used pair
-    double kt_acc[3][3] = {{0}};             // per class: launches, ms, bytes
+    double kt_acc[NS_KT_COUNT][3] = {{0}};   // per class: launches, ms, bytes
     // library-owned stream (solves run here; graph capture needs a non-default stream)
     hipStream_t own = nullptr;
     hipEvent_t step_ev[2] = {nullptr, nullptr};  // completion of queued Arnoldi steps

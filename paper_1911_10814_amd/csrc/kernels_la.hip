@@ -92,6 +92,21 @@ void launch_timed(K kernel, dim3 grid, dim3 block, hipStream_t st, Args... args)
     }
 }
 
+// A timed class of several launches in sequence: the first records the start
+// event at its own start, the last the stop event at its own end.
+template <typename K, typename... Args>
+void launch_span(K kernel, dim3 grid, dim3 block, size_t shmem, hipStream_t st, bool first, bool last,
+                 Args... args) {
+    hipEvent_t e0 = first ? g_ev_start : nullptr, e1 = last ? g_ev_stop : nullptr;
+    if (e0 || e1) {
+        hipExtLaunchKernelGGL(kernel, grid, block, shmem, st, e0, e1, 0, args...);
+        if (first) g_ev_start = nullptr;
+        if (last) g_ev_stop = nullptr;
+    } else {
+        hipLaunchKernelGGL(kernel, grid, block, shmem, st, args...);
+    }
+}
+
 template <typename T, int BR, int BC, int W>
 __global__ __launch_bounds__(kBlock) void k_spmv(BlockOp<T> M, const T* __restrict__ x, T* __restrict__ y, T alpha,
                                                  const T* __restrict__ z, T beta, const T* __restrict__ rscale,
@@ -591,13 +606,13 @@ void arnoldi_cgs2(int64_t n, int j, const T* V, int64_t ldv, T* w, double* h1, d
     T* r1 = reinterpret_cast<T*>(red);
     T* r2 = r1 + (int64_t)(k + 1) * G;
     T* r3 = r2 + (int64_t)k * G;
-    hipLaunchKernelGGL((k_multidot<T>), dim3(G, (k + 1 + kDotGroup - 1) / kDotGroup), dim3(kCgsBlock), 0, st, n, k,
-                       V, ldv, w, r1);
-    hipLaunchKernelGGL((k_orth_dot<T>), dim3(G), dim3(kCgsBlock), (k + 1) * sizeof(T), st, n, k, V, ldv, r1, G, h1,
-                       w, r2);
-    hipLaunchKernelGGL((k_orth_update<T>), dim3(G), dim3(kCgsBlock), k * sizeof(T), st, n, k, V, ldv, r2, G, h2, w,
-                       r3);
-    hipLaunchKernelGGL((k_finish<T>), dim3(G), dim3(kCgsBlock), 0, st, n, w, r3, G, ga);
+    launch_span(k_multidot<T>, dim3(G, (k + 1 + kDotGroup - 1) / kDotGroup), dim3(kCgsBlock), 0, st, true, false,
+                n, k, V, ldv, (const T*)w, r1);
+    launch_span(k_orth_dot<T>, dim3(G), dim3(kCgsBlock), (k + 1) * sizeof(T), st, false, false, n, k, V, ldv,
+                (const T*)r1, G, h1, w, r2);
+    launch_span(k_orth_update<T>, dim3(G), dim3(kCgsBlock), k * sizeof(T), st, false, false, n, k, V, ldv,
+                (const T*)r2, G, h2, w, r3);
+    launch_span(k_finish<T>, dim3(G), dim3(kCgsBlock), 0, st, false, true, n, w, (const T*)r3, G, ga);
 }
 
 // Start of a GMRES cycle with the residual norm on the device: v /= nrm,
@@ -942,10 +957,10 @@ void shat_factored(int n, const int32_t* rp, const int32_t* col, const T* V, int
                    const T* dinv, const T* coef, int step, T* d, int xcd, hipStream_t st) {
     if (n <= 0) return;
     const dim3 grid(grid_for((int64_t)n * 16));
-    hipLaunchKernelGGL((k_sfact_bt<T, 16>), grid, dim3(kBlock), 0, st, n, rp, col, V, nnzb, dinvA, x, agg, ec, t,
-                       xcd);
-    hipLaunchKernelGGL((k_sfact_dc<T, 16>), grid, dim3(kBlock), 0, st, n, rp, col, V, nnzb, t, x, agg, ec, y, alpha,
-                       z, beta, b, dinv, coef, step, d, xcd);
+    launch_span(k_sfact_bt<T, 16>, grid, dim3(kBlock), 0, st, true, false, n, rp, col, V, nnzb, dinvA, x, agg, ec,
+                t, xcd);
+    launch_span(k_sfact_dc<T, 16>, grid, dim3(kBlock), 0, st, false, true, n, rp, col, V, nnzb, (const T*)t, x, agg,
+                ec, y, alpha, z, beta, b, dinv, coef, step, d, xcd);
 }
 
 // Restriction bc = P^T r of a precomputed residual; when xc != nullptr also

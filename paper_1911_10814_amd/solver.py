@@ -338,6 +338,21 @@ class NsContext:
         return y, out
 
 
+def stream_bench(mode: int, src: torch.Tensor, dst: torch.Tensor, reps: int = 10) -> float:
+    """Average ms per launch of the streaming kernel ``mode`` (0 read, 1 copy)
+    over src.numel() bytes (``ns_stream_bench``); src and dst are device byte tensors."""
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() < nbytes:
+        raise ValueError("dst smaller than src")
+    out = C.c_double()
+    with torch.cuda.device(src.device):
+        torch.cuda.synchronize()
+        st = _lib.load().ns_stream_bench(int(mode), _ptr(src), _ptr(dst), nbytes, int(reps), C.byref(out))
+    if st != 0:
+        raise NsError(st, "ns_stream_bench failed")
+    return out.value
+
+
 def context_for(case, **kw) -> NsContext:
     return NsContext(case, **kw).bind()
 
