@@ -249,6 +249,23 @@ ns_status ns_rank_one_dots(ns_ctx* ctx, const double* d_xv, double* h_out, hipSt
 ns_status ns_resistance_gradient(ns_ctx* ctx, const double* d_lambda, const double* d_x, double* h_grad,
                                  hipStream_t stream);
 
+/* ns_resistance_gradient_noalloc: for callers that cannot allocate (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): ns_resistance_gradient with its scratch (the two per-outlet dot
+ * products) in a file-scope device array of the library instead of the
+ * context's workspace, and its result written to device memory:
+ *   d_grad  [n_outlets] out (device): dL/dR_k
+ * Enqueues three kernels on `stream` and returns: no allocation, no copy, no
+ * synchronisation.  At most 4096 outlets (the array holds 2 x 4096 doubles per
+ * device, kept until the process ends).  Every call on one GPU shares that
+ * GPU's array, so calls that overlap on one GPU (other streams, other
+ * contexts, other host threads) race; calls on one stream are ordered.  The
+ * context's device must be current.  Errors: NS_ERR_ARG (null pointers, more
+ * than 4096 outlets), NS_ERR_STATE (as ns_resistance_gradient; another device
+ * current), NS_ERR_HIP. */
+ns_status ns_resistance_gradient_noalloc(ns_ctx* ctx, const double* d_lambda, const double* d_x, double* d_grad,
+                                         hipStream_t stream);
+
 /* ns_gen_alpha: the generalized-alpha parameters of Sec. 2.4.1 for the
  * spectral radius rho_inf in [0, 1]: h_out3 = {alpha_m, alpha_f, gamma},
  * alpha_m = (3 - rho_inf) / (2 (1 + rho_inf)), alpha_f = gamma = 1 / (1 + rho_inf).

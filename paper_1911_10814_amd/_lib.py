@@ -90,6 +90,7 @@ SIGNATURES = {
     "ns_outlet_flow": (C.c_int, [C.c_void_p, C.c_void_p, PD, C.c_void_p]),
     "ns_rank_one_dots": (C.c_int, [C.c_void_p, C.c_void_p, PD, C.c_void_p]),
     "ns_resistance_gradient": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, PD, C.c_void_p]),
+    "ns_resistance_gradient_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "ns_gen_alpha": (C.c_int, [C.c_double, PD]),
     "ns_stream_bench": (C.c_int, [C.c_int32, C.c_void_p, C.c_void_p, C.c_size_t, C.c_int32, PD]),
     "ns_assemble_tangent": (C.c_int, [C.c_void_p, C.POINTER(NsPhys), C.c_void_p, C.c_void_p, C.c_void_p,

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libns_hip.so")
-SOURCES = ["setup.cpp", "kernels_la.hip", "kernels_asm.hip", "api.hip", "stream.hip"]
+SOURCES = ["setup.cpp", "kernels_la.hip", "kernels_asm.hip", "api.hip", "stream.hip", "noalloc.hip"]
 ARCH = os.environ.get("NS_OFFLOAD_ARCH", "gfx950")
 
 

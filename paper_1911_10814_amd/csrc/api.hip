@@ -1442,6 +1442,8 @@ ns_status ns_ctx_bind(ns_ctx* c, void* ws, size_t bytes, hipStream_t st) {
             HIPCHK(hipHostGetDevicePointer((void**)&c->d_mapped, c->h_mapped, 0));
         }
         if (!c->own) HIPCHK(hipStreamCreateWithFlags(&c->own, hipStreamNonBlocking));
+        // the scratch of ns_resistance_gradient_noalloc on this device
+        HIPCHK(noalloc_scratch(c->device, &c->noalloc_scratch));
         for (int e = 0; e < 2; ++e)
             if (!c->step_ev[e]) HIPCHK(hipEventCreateWithFlags(&c->step_ev[e], hipEventDisableTiming));
         for (int a = 0; a < ns_ctx::kAux; ++a) {

@@ -178,6 +178,7 @@ struct ns_ctx {
     double* d_Pn = nullptr;      // [n_out] its P^k_n
     double* d_Q = nullptr;       // [n_out] its outlet flows Q^k
     double* d_grad = nullptr;    // [n_out] dL/dR of ns_resistance_gradient
+    double* noalloc_scratch = nullptr;  // device address of the allocation-free variant's scratch
     double* d_red = nullptr;     // reduction partials
     ns::SystemDev sys[2];        // 0: forward, 1: transposed
     ns::KrylovWs kw_out, kw_A, kw_S;

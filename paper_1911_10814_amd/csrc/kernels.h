@@ -217,6 +217,11 @@ void finalize_rhs(int N, const uint8_t* mask, const double* res, double* rhs, hi
 void add_traction(int n_slots, const int32_t* onode, const int32_t* oid, const double* P_af, const double* a_raw,
                   double* res, hipStream_t st);
 void newton_update(int64_t n, double gdt, const double* dx, double* y, double* ydot, hipStream_t st);
+// Largest outlet count of ns_resistance_gradient_noalloc: its file-scope
+// scratch holds two dot products per outlet (64 KiB).
+constexpr int kNoAllocMaxOutlets = 4096;
+// device address of that scratch on `device` (the current device), looked up once per device
+hipError_t noalloc_scratch(int device, double** out);
 // resistance outlets: ck = c_f R, P_af = (1 - af) P_n + af R Q (P_n == nullptr: R Q)
 void resistance_outlets(int n_out, const double* R, const double* P_n, const double* Q, double af, double cf,
                         double* ck, double* P_af, hipStream_t st);
