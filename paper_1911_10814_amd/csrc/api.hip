@@ -372,6 +372,10 @@ constexpr int kGraphMaxNodes = 1024;
 // finest A levels from this many rows add the prolongated correction in a pass
 // of its own (NS_PROLONG_PASS=0/1, read at bind, forces the fused step or the pass)
 constexpr int kProlongPassRows = 500000;
+// lanes per row of the factored S_hat passes: 8, two blocks in flight per lane
+// (measured 13 % faster than 16 lanes on the 4e6-node contraction-expansion,
+// 7 % on the 2e5-node pipe; 4 lanes was no faster than 16)
+constexpr int kSfactLanes = 8;
 
 template <typename T>
 double dev_norm(ns_ctx* c, int64_t n, const T* x, double* slot, hipStream_t st) {
@@ -482,12 +486,12 @@ void read_step_status(ns_ctx* c, KrylovWs& kw, hipStream_t st, double& resid, bo
 // stepM / stepP (optional): the operator and preconditioner as used inside an
 // Arnoldi step, where stepM may already perform the preconditioner's first
 // smoothing step on its output (the start and restart residuals use applyM
-// and applyP).
+// and applyP); with step_fused, stepM alone computes P^{-1} M v.
 template <typename T>
 int gmres_left(Ctl& K, KrylovWs& kw, int64_t n, const std::function<void(const T*, T*)>& applyM,
                const std::function<void(const T*, T*)>& applyP, const T* b, T* x, double rtol, int m, int nmax,
                int kind, bool m_capturable, const std::function<void(const T*, T*)>& stepM = {},
-               const std::function<void(const T*, T*)>& stepP = {}) {
+               const std::function<void(const T*, T*)>& stepP = {}, bool step_fused = false) {
     const auto& sM = stepM ? stepM : applyM;
     const auto& sP = stepP ? stepP : applyP;
     ns_ctx* c = K.c;
@@ -526,8 +530,12 @@ int gmres_left(Ctl& K, KrylovWs& kw, int64_t n, const std::function<void(const T
             T* vj = V + (int64_t)jj * kw.ld;
             T* vn = V + (int64_t)(jj + 1) * kw.ld;
             run_step(c, K, kind, jj, [&] {
-                sM(vj, tmp);
-                sP(tmp, vn);
+                if (step_fused) {
+                    sM(vj, vn);  // stepM already applies the preconditioner
+                } else {
+                    sM(vj, tmp);
+                    sP(tmp, vn);
+                }
                 cgs2_launch<T>(c, kw, n, jj, V, st, jj & 1);
             });
             HIPCHK(hipEventRecord(c->step_ev[jj & 1], st));
@@ -550,9 +558,9 @@ int gmres_left(Ctl& K, KrylovWs& kw, int64_t n, const std::function<void(const T
                 if (ahead) enqueue(j + 1);
                 read_step_status(c, kw, st, resid, bd, c->step_ev[j & 1], j & 1, false);
             } else {
-                sM(V + (int64_t)j * kw.ld, tmp);
+                sM(V + (int64_t)j * kw.ld, step_fused ? V + (int64_t)(j + 1) * kw.ld : tmp);
                 run_step(c, K, kind, j, [&] {
-                    sP(tmp, V + (int64_t)(j + 1) * kw.ld);
+                    if (!step_fused) sP(tmp, V + (int64_t)(j + 1) * kw.ld);
                     cgs2_launch<T>(c, kw, n, j, V, st);
                 });
                 read_step_status(c, kw, st, resid, bd, nullptr, 0, false);
@@ -628,7 +636,13 @@ struct Nested {
         M.v = V() + (4 * r0 + c0) * nnzb;
         M.rs = 4 * nnzb;
         M.cs = nnzb;
-        M.lanes = lanes_for(nnzb, N);
+        M.lanes = lanes_for(nnzb, N, 3);
+        // the B, C and D operators move 3 or 1 values per block: 8 lanes per
+        // row, two blocks in flight per lane, measured 20-25 % faster than 16
+        // lanes on the 2e6-node pipe and the 4e6-node contraction-expansion
+        // (the 3x3 A operator keeps 16: 9 values per block already keep
+        // enough loads in flight)
+        if (M.lanes == 16 && (r0 == 3 || c0 == 3)) M.lanes = 8;
         M.xcd = xcd_rows(N, c0 == 3 ? 1 : 3);
         return M;
     }
@@ -641,7 +655,7 @@ struct Nested {
         M.rs = d.rstride;
         M.cs = d.cstride;
         M.dextra = Typed<T>::dextra(d);
-        M.lanes = lanes_for(d.nnz, d.n);
+        M.lanes = lanes_for(d.nnz, d.n, d.bs);
         M.xcd = xcd_rows(d.n, d.bs);
         return M;
     }
@@ -659,7 +673,7 @@ struct Nested {
         if (agg) bytes += 2 * n * (4 + sz);
         timed(c, NS_KT_SFACT, bytes, K.st, [&] {
             shat_factored<T>(N, c->d_rp, c->d_col, V(), nnzb, Typed<T>::dinvA(sy), x, agg, ec, as<T>(c->t_sf), y,
-                             alpha, z, beta, b, dinv, coef, step, d, xcd_rows(N, 1), K.st);
+                             alpha, z, beta, b, dinv, coef, step, d, xcd_rows(N, 1), kSfactLanes, K.st);
         });
     }
     RankOne<T> rank_one() const {
@@ -684,15 +698,17 @@ struct Nested {
     }
     bool fuse_first(const std::vector<AmgLevelDev>& H) const { return H.size() > 1; }
     // y = (F + K) x
-    void applyA(const T* x, T* y, const FirstStep<T>* fs = nullptr) {
+    // y = (F + K) x, scaled row-wise by rscale when given (the point-Jacobi
+    // preconditioned operator diag(A)^{-1} A x in one pass)
+    void applyA(const T* x, T* y, const FirstStep<T>* fs = nullptr, const T* rscale = nullptr) {
         RankOne<T> r = rank_one();
         if (r.slot_of)
             outlet_dot<T>(c->sym.n_out, c->d_optr, c->d_onode, Typed<T>::amsk(c), Typed<T>::ck(c), x, as<T>(c->d_s),
                           K.st);
         const double s = sizeof(T);
-        const double bytes = (double)nnzb * (9 * s + 4) + 4.0 * (N + 1) + 6 * s * N;
+        const double bytes = (double)nnzb * (9 * s + 4) + 4.0 * (N + 1) + (rscale ? 9 : 6) * s * N;
         timed(c, NS_KT_SPMV_A, bytes, K.st, [&] {
-            spmv<T>(3, 3, op(0, 0), x, y, T(1), nullptr, T(0), nullptr, r.slot_of ? &r : nullptr, K.st, fs);
+            spmv<T>(3, 3, op(0, 0), x, y, T(1), nullptr, T(0), rscale, r.slot_of ? &r : nullptr, K.st, fs);
         });
     }
     // One V-cycle on level l for right-hand side b, result in xout.  On levels
@@ -811,7 +827,13 @@ struct Nested {
         // inner solves with a P of their own use graphs of their own
         const int kind = pc == K.o.pc_A ? kKindA : kKindInner;
         std::function<void(const T*, T*)> sM, sP;
-        if (pc != NS_PC_JACOBI && fuse_first(sy.A)) {
+        bool fused = false;
+        if (pc == NS_PC_JACOBI) {
+            // point Jacobi applied in the operator's epilogue (the same product
+            // diag(A)^{-1} (A v) as the separate scaling, one pass fewer)
+            sM = [this](const T* in, T* out) { applyA(in, out, nullptr, Typed<T>::dinv(sy.A[0])); };
+            fused = true;
+        } else if (fuse_first(sy.A)) {
             sM = [this](const T* in, T* out) {
                 const FirstStep<T> f = first_step(sy.A);
                 applyA(in, out, &f);
@@ -821,7 +843,7 @@ struct Nested {
         return gmres_left<T>(
             K, c->kw_A, 3 * (int64_t)N, [this](const T* in, T* out) { applyA(in, out); },
             [this, pc](const T* in, T* out) { applyPA(in, out, pc); }, b, x, rtol, dflt(K.o.m_A, 200),
-            dflt(K.o.nmax_A, 200), kind, true, sM, sP);
+            dflt(K.o.nmax_A, 200), kind, true, sM, sP, fused);
     }
     // Algorithm 2: y = D x - C A^{-1} (B x)
     void schur(const T* xp, T* y, const FirstStep<T>* fs = nullptr) {
@@ -1054,7 +1076,7 @@ void setup_device(ns_ctx* c, SystemDev& y, hipStream_t st) {
             M.rs = d.rstride;
             M.cs = d.cstride;
             M.dextra = d.dextra64;
-            M.lanes = lanes_for(d.nnz, d.n);
+            M.lanes = lanes_for(d.nnz, d.n, d.bs);
             smoother_bound_dev(c, M, d.bs, d.dinv64, d.x0, d.r, d.b, bnd + 3 * (h * L + l), ps);
         }
     };
@@ -1959,6 +1981,7 @@ ns_status ns_apply(ns_ctx* c, int32_t op, const ns_solve_opts* opts, const doubl
         else run(double{});
         check_launch();
         HIPCHK(hipStreamSynchronize(st));
+        timing_collect(c);
         if (K.o.h_sched_out)
             for (int i = 0; i < (int)K.sc.log.size() && i < K.o.sched_cap; ++i) K.o.h_sched_out[i] = K.sc.log[i];
         return NS_OK;

@@ -49,9 +49,15 @@ struct BlockOp {
 void set_launch_events(hipEvent_t start, hipEvent_t stop);
 bool launch_events_pending();
 
-// lanes per row for a pattern with nnz blocks over n rows: one pass over a
-// typical row, so consecutive rows give contiguous loads across the wavefront
-inline int lanes_for(int64_t nnz, int n) {
+// Lanes per row for a pattern with nnz blocks of bs x bs values over n rows.
+// Blocks of 3x3 values: one pass over a typical row, so consecutive rows give
+// contiguous loads across the wavefront.  Scalar rows (S_hat levels, 1 value
+// per entry): 8 lanes whatever the row length, each with several entries in
+// flight (a level-1 S_hat smoothing step on the 4e6-node contraction-expansion,
+// ~44 entries per row: 160 us with 8 lanes against 178 / 258 / 335 us with 16 /
+// 32 / 64).
+inline int lanes_for(int64_t nnz, int n, int bs) {
+    if (bs == 1) return 8;
     const double avg = n > 0 ? (double)nnz / n : 0.0;
     return avg <= 16.0 ? 16 : (avg <= 32.0 ? 32 : 64);
 }
@@ -137,7 +143,7 @@ void restrict_first(int nc, int bs, const int32_t* aptr, const int32_t* anodes, 
 template <typename T>
 void shat_factored(int n, const int32_t* rp, const int32_t* col, const T* V, int64_t nnzb, const T* dinvA, const T* x,
                    const int32_t* agg, const T* ec, T* t, T* y, T alpha, const T* z, T beta, const T* b,
-                   const T* dinv, const T* coef, int step, T* d, int xcd, hipStream_t st);
+                   const T* dinv, const T* coef, int step, T* d, int xcd, int lanes, hipStream_t st);
 // bc = P^T (b - M x) in one launch (residual rows summed per aggregate), plus
 // the coarse first Chebyshev step when xc != nullptr (as restrict_first)
 template <typename T>

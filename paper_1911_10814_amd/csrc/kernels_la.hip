@@ -5,6 +5,8 @@
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include <algorithm>
 #include <cmath>
 
@@ -141,7 +143,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv(BlockOp<T> M, const T* __restri
     T acc[BR];
 #pragma unroll
     for (int r = 0; r < BR; ++r) acc[r] = 0;
-    for (int k = kb + lane; k < ke; k += W) {
+    auto block = [&](int k) {
         const int j = M.col[k];
         T xj[BC];
 #pragma unroll
@@ -150,6 +152,17 @@ __global__ __launch_bounds__(kBlock) void k_spmv(BlockOp<T> M, const T* __restri
         for (int r = 0; r < BR; ++r)
 #pragma unroll
             for (int c = 0; c < BC; ++c) acc[r] += M.v[r * M.rs + c * M.cs + k] * xj[c];
+    };
+    if constexpr (W == 8 && BR * BC == 1) {
+        // scalar rows: several entries per lane, issued before any is used
+#pragma unroll 4
+        for (int k = kb + lane; k < ke; k += W) block(k);
+    } else if constexpr (W == 8) {
+        // two blocks per lane on a typical row: both issued before either is used
+#pragma unroll 2
+        for (int k = kb + lane; k < ke; k += W) block(k);
+    } else {
+        for (int k = kb + lane; k < ke; k += W) block(k);
     }
 #pragma unroll
     for (int off = W / 2; off > 0; off >>= 1)
@@ -191,6 +204,10 @@ void spmv_w(const BlockOp<T>& M, const T* x, T* y, T alpha, const T* z, T beta, 
             break;
         case 32:
             launch_timed(k_spmv<T, BR, BC, 32>, dim3(grid_for((int64_t)M.n * 32)), dim3(kBlock), st, M,
+                               x, y, alpha, z, beta, rscale, r1, fs);
+            break;
+        case 8:
+            launch_timed(k_spmv<T, BR, BC, 8>, dim3(grid_for((int64_t)M.n * 8)), dim3(kBlock), st, M,
                                x, y, alpha, z, beta, rscale, r1, fs);
             break;
         default:
@@ -781,23 +798,30 @@ __global__ __launch_bounds__(kBlock) void k_cheb_step(BlockOp<T> M, const T* __r
     T acc[BS];
 #pragma unroll
     for (int r = 0; r < BS; ++r) acc[r] = 0;
-    {
-        for (int k = kb + lane; k < ke; k += W) {
-            const int j = M.col[k];
-            T xj[BS];
-            if (agg) {
-                const int64_t J = agg[j];
+    auto block = [&](int k) {
+        const int j = M.col[k];
+        T xj[BS];
+        if (agg) {
+            const int64_t J = agg[j];
 #pragma unroll
-                for (int c = 0; c < BS; ++c) xj[c] = xin[(int64_t)BS * j + c] + ec[BS * J + c];
-            } else {
+            for (int c = 0; c < BS; ++c) xj[c] = xin[(int64_t)BS * j + c] + ec[BS * J + c];
+        } else {
 #pragma unroll
-                for (int c = 0; c < BS; ++c) xj[c] = xin[(int64_t)BS * j + c];
-            }
-#pragma unroll
-            for (int r = 0; r < BS; ++r)
-#pragma unroll
-                for (int c = 0; c < BS; ++c) acc[r] += M.v[r * M.rs + c * M.cs + k] * xj[c];
+            for (int c = 0; c < BS; ++c) xj[c] = xin[(int64_t)BS * j + c];
         }
+#pragma unroll
+        for (int r = 0; r < BS; ++r)
+#pragma unroll
+            for (int c = 0; c < BS; ++c) acc[r] += M.v[r * M.rs + c * M.cs + k] * xj[c];
+    };
+    if constexpr (BS == 1 && W <= 8) {
+#pragma unroll 4
+        for (int k = kb + lane; k < ke; k += W) block(k);
+    } else if constexpr (BS == 1 && W <= 32) {
+#pragma unroll 2
+        for (int k = kb + lane; k < ke; k += W) block(k);
+    } else {
+        for (int k = kb + lane; k < ke; k += W) block(k);
     }
 #pragma unroll
     for (int off = W / 2; off > 0; off >>= 1)
@@ -825,6 +849,10 @@ void cheb_step_w(const BlockOp<T>& M, const T* xin, T* xout, T* d, const T* b, c
     switch (M.lanes) {
         case 64:
             launch_timed(k_cheb_step<T, BS, 64>, dim3(grid_for((int64_t)M.n * 64)), dim3(kBlock), st, M,
+                               xin, xout, d, b, dinv, coef, step, agg, ec);
+            break;
+        case 8:
+            launch_timed(k_cheb_step<T, BS, 8>, dim3(grid_for((int64_t)M.n * 8)), dim3(kBlock), st, M,
                                xin, xout, d, b, dinv, coef, step, agg, ec);
             break;
         case 32:
@@ -873,6 +901,7 @@ __global__ __launch_bounds__(kBlock) void k_sfact_bt(int n, const int32_t* __res
     const T dai = (valid && lane < 3) ? dinvA[i] : T(0);  // loaded ahead of the row loop
     T acc[3] = {0, 0, 0};
     {
+#pragma unroll 2
         for (int k = kb + lane; k < ke; k += W) {
             const int j = col[k];
             T xj = x[j];
@@ -924,6 +953,7 @@ __global__ __launch_bounds__(kBlock) void k_sfact_dc(int n, const int32_t* __res
     }
     T acc = 0;
     {
+#pragma unroll 2
         for (int k = kb + lane; k < ke; k += W) {
             const int j = col[k];
             T xj = x[j];
@@ -954,13 +984,19 @@ __global__ __launch_bounds__(kBlock) void k_sfact_dc(int n, const int32_t* __res
 template <typename T>
 void shat_factored(int n, const int32_t* rp, const int32_t* col, const T* V, int64_t nnzb, const T* dinvA, const T* x,
                    const int32_t* agg, const T* ec, T* t, T* y, T alpha, const T* z, T beta, const T* b,
-                   const T* dinv, const T* coef, int step, T* d, int xcd, hipStream_t st) {
+                   const T* dinv, const T* coef, int step, T* d, int xcd, int lanes, hipStream_t st) {
     if (n <= 0) return;
-    const dim3 grid(grid_for((int64_t)n * 16));
-    launch_span(k_sfact_bt<T, 16>, grid, dim3(kBlock), 0, st, true, false, n, rp, col, V, nnzb, dinvA, x, agg, ec,
-                t, xcd);
-    launch_span(k_sfact_dc<T, 16>, grid, dim3(kBlock), 0, st, false, true, n, rp, col, V, nnzb, (const T*)t, x, agg,
-                ec, y, alpha, z, beta, b, dinv, coef, step, d, xcd);
+    auto run = [&](auto w) {
+        constexpr int W = decltype(w)::value;
+        const dim3 grid(grid_for((int64_t)n * W));
+        launch_span(k_sfact_bt<T, W>, grid, dim3(kBlock), 0, st, true, false, n, rp, col, V, nnzb, dinvA, x, agg, ec,
+                    t, xcd);
+        launch_span(k_sfact_dc<T, W>, grid, dim3(kBlock), 0, st, false, true, n, rp, col, V, nnzb, (const T*)t, x,
+                    agg, ec, y, alpha, z, beta, b, dinv, coef, step, d, xcd);
+    };
+    if (lanes == 4) run(std::integral_constant<int, 4>{});
+    else if (lanes == 8) run(std::integral_constant<int, 8>{});
+    else run(std::integral_constant<int, 16>{});
 }
 
 // Restriction bc = P^T r of a precomputed residual; when xc != nullptr also
@@ -1094,18 +1130,24 @@ void restrict_agg(int nc, int bs, const int32_t* aptr, const int32_t* anodes, co
                        r, bc);
 }
 
-// x += P ec: one thread per node (its aggregate loaded once for the node's
-// bs entries)
-template <typename T>
-__global__ void k_prolong(int n, int bs, const int32_t* agg, const T* ec, T* x) {
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n) return;
-    const int64_t a = agg[i];
-    for (int c = 0; c < bs; ++c) x[bs * i + c] += ec[bs * a + c];
+// x += P ec, one thread per vector entry (node i, component c): the x loads and stores
+// and the aggregate-map loads of a wavefront are contiguous
+template <typename T, int BS>
+__global__ __launch_bounds__(kBlock) void k_prolong(int64_t nv, const int32_t* __restrict__ agg,
+                                                    const T* __restrict__ ec, T* __restrict__ x) {
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= nv) return;
+    const int64_t i = t / BS;
+    const int c = (int)(t - i * BS);
+    x[t] += ec[(int64_t)BS * agg[i] + c];
 }
 template <typename T>
 void prolong_add(int n, int bs, const int32_t* agg, const T* ec, T* x, hipStream_t st) {
-    hipLaunchKernelGGL((k_prolong<T>), dim3(grid_for(n)), dim3(kBlock), 0, st, n, bs, agg, ec, x);
+    const int64_t nv = (int64_t)n * bs;
+    if (bs == 3)
+        hipLaunchKernelGGL((k_prolong<T, 3>), dim3(grid_for(nv)), dim3(kBlock), 0, st, nv, agg, ec, x);
+    else
+        hipLaunchKernelGGL((k_prolong<T, 1>), dim3(grid_for(nv)), dim3(kBlock), 0, st, nv, agg, ec, x);
 }
 
 // x = Minv b (FP64 arithmetic), one wavefront per row
@@ -1715,7 +1757,7 @@ void newton_update(int64_t n, double gdt, const double* dx, double* y, double* y
     template void restrict_agg<T>(int, int, const int32_t*, const int32_t*, const T*, T*, hipStream_t);              \
     template void shat_factored<T>(int, const int32_t*, const int32_t*, const T*, int64_t, const T*, const T*,       \
                                    const int32_t*, const T*, T*, T*, T, const T*, T, const T*, const T*, const T*,   \
-                                   int, T*, int, hipStream_t);                                                       \
+                                   int, T*, int, int, hipStream_t);                                                  \
     template void resid_restrict<T>(int, const BlockOp<T>&, const T*, const T*, int, const int32_t*, const int32_t*, \
                                     T*, T*, T*, const T*, const T*, const T*, hipStream_t);                          \
     template void prolong_add<T>(int, int, const int32_t*, const T*, T*, hipStream_t);                               \
