@@ -161,6 +161,11 @@ typedef struct {
     int32_t pc_I;           /* P of the inner A-solves of Algorithm 2
                              * (Sec. 4 suggests a light one there):
                              * 0 = as pc_A, 1 = AMG, 2 = Jacobi       [0]     */
+    int32_t cycle_index_A;  /* AMG cycle index on the A hierarchy: the coarse-
+                             * grid correction and post-smoothing are repeated
+                             * this many times on every level below the finest
+                             * (1 = V-cycle, 2 = W-cycle), 1..3       [1]     */
+    int32_t cycle_index_S;  /* the same on the S_hat hierarchy        [1]     */
     int32_t reserved;       /* must be 0 */
     /* Iteration schedule.  If h_sched != NULL, the i-th Krylov call (calls
      * numbered in the order they start: FGMRES, then each GMRES on A or S)
@@ -389,7 +394,8 @@ ns_status ns_newton_update(ns_ctx* ctx, double gamma_dt, const double* d_dx, dou
  *                   D, C pass with the smoothing or residual epilogue)
  *   NS_KT_CGS2      one CGS2 orthogonalisation step, any Krylov level (four
  *                   launches timed as one; bytes with k = j + 1 basis vectors
- *                   of length n: (4k + 8) n values)
+ *                   of length n: (4k + 8) n values, (3k + 7) n for k <= 16,
+ *                   where the pass-1 update and pass-2 dots read V once)
  *   NS_KT_CHEB_S1   a Chebyshev step on level 1 of the S_hat hierarchy
  * ns_kernel_timing(ctx, mask) enables timing of the classes in `mask` (bit
  * 1 << class) for later solves (0 disables); every timed launch is bracketed

@@ -36,6 +36,9 @@ written definition, which the GPU library implements independently:
   aggregate means, so the Galerkin correction (the M-orthogonal projection on
   range(P)) falls short of the smooth error; an over-correction c in (1, 2)
   compensates.  The cycle stays a fixed linear operator for any c;
+* cycle index ``cycle_index`` (default 1, the V-cycle): on every level below
+  the finest, the coarse-grid correction and the post-smoothing are applied
+  that many times in turn (2: a W-cycle); the finest level takes one;
 * coarsest level: dense LU solve in FP64.
 """
 from __future__ import annotations
@@ -159,11 +162,12 @@ class AMG:
     """V-cycle for M (scipy CSR) with block size ``bs`` on the node aggregates."""
 
     def __init__(self, M, bs: int, aggs, cheb_degree: int = 2, extra_diag=None, cheb_ratio: float = 10.0,
-                 cc_scale: float = 1.0):
+                 cc_scale: float = 1.0, cycle_index: int = 1):
         self.bs = bs
         self.deg = cheb_degree
         self.ratio = cheb_ratio
         self.cc_scale = cc_scale
+        self.gamma = cycle_index
         M = sp.csr_matrix(M, dtype=np.float64)
         if extra_diag is not None:
             M = (M + sp.diags(extra_diag)).tocsr()
@@ -189,7 +193,9 @@ class AMG:
             return sla.lu_solve(self.lu, b)
         M, dinv, lmax = self.M[level], self.dinv[level], self.lmax[level]
         x = chebyshev(M, dinv, b, None, self.deg, lmax / self.ratio, lmax)
-        r = b - M @ x
         P = self.P[level]
-        x = x + self.cc_scale * (P @ self.vcycle(P.T @ r, level + 1))
-        return chebyshev(M, dinv, b, x, self.deg, lmax / self.ratio, lmax)
+        for _ in range(self.gamma if level > 0 else 1):
+            r = b - M @ x
+            x = x + self.cc_scale * (P @ self.vcycle(P.T @ r, level + 1))
+            x = chebyshev(M, dinv, b, x, self.deg, lmax / self.ratio, lmax)
+        return x

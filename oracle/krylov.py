@@ -221,6 +221,8 @@ class SolveOpts:
     cycles_S: int = 1        # V-cycle iterations per application of P_S
     cc_scale_A: float = 1.0  # coarse-grid correction scaling of the A hierarchy
     cc_scale_S: float = 1.0  # and of the S_hat hierarchy
+    cycle_index_A: int = 1   # AMG cycle index below the finest level (1: V, 2: W), A hierarchy
+    cycle_index_S: int = 1   # and S_hat hierarchy
     pc: str = "scr"          # outer preconditioner: "scr" (Algorithm 3) or "simple" (Sec. 3.2)
     coarse_nodes: int = 128
     coarse_matchings: int = 3   # greedy matchings composed per coarsening step below the finest
@@ -243,12 +245,13 @@ class NestedSolver:
         for ak, ck in zip(S.a, S.c):
             dK += ck * ak * ak
         self.amgA = amg_mod.AMG(S.A_F, 3, self.aggs, opts.cheb_degree, extra_diag=dK, cheb_ratio=opts.cheb_ratio,
-                                cc_scale=opts.cc_scale_A)
+                                cc_scale=opts.cc_scale_A, cycle_index=opts.cycle_index_A)
         # S_hat = D - C diag(A)^{-1} B  (Sec. 3.1)
         import scipy.sparse as sp
         self.Shat = (S.D - S.C @ sp.diags(1.0 / dA) @ S.B).tocsr()
         self.amgS = amg_mod.AMG(self.Shat, 1, self.aggs, opts.cheb_degree_S or opts.cheb_degree,
-                                cheb_ratio=opts.cheb_ratio, cc_scale=opts.cc_scale_S)
+                                cheb_ratio=opts.cheb_ratio, cc_scale=opts.cc_scale_S,
+                                cycle_index=opts.cycle_index_S)
 
     def pS(self, r):
         """P_S: ``cycles_S`` steps of the stationary V-cycle iteration on

@@ -43,7 +43,8 @@ class NsSolveOpts(C.Structure):
                 ("cc_scale_S", C.c_double), ("m", C.c_int32), ("nmax", C.c_int32), ("m_A", C.c_int32),
                 ("nmax_A", C.c_int32), ("m_S", C.c_int32), ("nmax_S", C.c_int32), ("pc_A", C.c_int32),
                 ("precision", C.c_int32), ("cheb_degree", C.c_int32), ("cycles_S", C.c_int32),
-                ("pc", C.c_int32), ("cheb_degree_S", C.c_int32), ("pc_I", C.c_int32), ("reserved", C.c_int32),
+                ("pc", C.c_int32), ("cheb_degree_S", C.c_int32), ("pc_I", C.c_int32), ("cycle_index_A", C.c_int32),
+                ("cycle_index_S", C.c_int32), ("reserved", C.c_int32),
                 ("h_sched", PI), ("sched_len", C.c_int32), ("sched_cap", C.c_int32), ("h_sched_out", PI)]
 
 

@@ -425,8 +425,10 @@ void run_step(ns_ctx* c, const Ctl& K, int kind, int j, F&& body) {
     }
     const int sys = K.sy == &c->sys[0] ? 0 : 1;
     const int degA = dflt(K.o.cheb_degree, kDefaultChebDegree);
+    const int cycles = dflt(K.o.cycles_S, kDefaultCyclesS) + 16 * dflt(K.o.cycle_index_S, 1) +
+                       256 * dflt(K.o.cycle_index_A, 1);
     const ns_ctx::GraphKey key(kind, sys, K.o.precision, K.o.pc_A, K.o.pc_I, degA, dflt(K.o.cheb_degree_S, degA),
-                               dflt(K.o.cycles_S, kDefaultCyclesS), j);
+                               cycles, j);
     launch_cached(c, key, K.st, body);
 }
 
@@ -459,8 +461,10 @@ void cgs2_launch(ns_ctx* c, KrylovWs& kw, int64_t n, int j, T* V, hipStream_t st
     ga.hstatus = c->d_mapped + kMapStatus + 2 * slot;
     // algorithmic bytes of the four kernels with k = j + 1 basis vectors: pass-1
     // dots (k + 1 vectors read), pass-1 update and pass-2 dots (2k + 2 read, 1
-    // written), pass-2 update (k + 1 read, 1 written), normalisation (1 + 1)
-    const double bytes = (4.0 * (j + 1) + 8.0) * (double)n * sizeof(T);
+    // written; k + 1 read when k <= kOrthFuseMax, single pass), pass-2 update
+    // (k + 1 read, 1 written), normalisation (1 + 1)
+    const int k = j + 1;
+    const double bytes = (k <= kOrthFuseMax ? 3.0 * k + 7.0 : 4.0 * k + 8.0) * (double)n * sizeof(T);
     timed(c, NS_KT_CGS2, bytes, st, [&] {
         arnoldi_cgs2<T>(n, j, V, kw.ld, V + (int64_t)(j + 1) * kw.ld, kw.h, kw.h + (kw.m + 2), ga, c->d_red, st);
     });
@@ -756,11 +760,15 @@ struct Nested {
             cheb(a, bb, s, nullptr, nullptr);
             std::swap(a, bb);
         }
-        // coarse-grid correction: residual, restriction (+ first coarse step)
+        // coarse-grid correction: residual, restriction (+ first coarse step),
+        // the coarse cycle, then post-smoothing -- gamma times on the levels
+        // below the finest (gamma = 1: V-cycle, 2: W-cycle)
         AmgLevelDev& C = H[l + 1];
         const bool child_coarsest = (l + 2 == (int)H.size());
         T* xc = child_coarsest ? nullptr : as<T>(C.x0);
         const T* coefc = child_coarsest ? nullptr : Typed<T>::coef(C);
+        const int gamma = l == 0 ? 1 : dflt(&H == &sy.S ? K.o.cycle_index_S : K.o.cycle_index_A, 1);
+        for (int g = 0; g < gamma; ++g) {
         if (l == 0) {
             // finest level: a row-ordered residual SpMV (coalesced value
             // streams), then the restriction
@@ -798,6 +806,10 @@ struct Nested {
             cheb(a, bb, s, nullptr, nullptr);
             std::swap(a, bb);
         }
+        }
+        // (deg - 1) + gamma * deg buffer flips: an even count leaves the result
+        // in the scratch buffer
+        if (a != xout) axpby<T>(nv, T(1), a, T(0), nullptr, xout, st);
     }
     // P of an A-solve: pc_A for the intermediate ones, pc_I (if set) for the
     // inner ones of Algorithm 2
@@ -1267,6 +1279,8 @@ void check_solve_opts(const ns_solve_opts& o) {
     if (o.cheb_degree < 0 || o.cheb_degree > kMaxChebDegree || o.cheb_degree_S < 0 ||
         o.cheb_degree_S > kMaxChebDegree)
         throw Fail{NS_ERR_ARG, "Chebyshev degree out of range [1, 8]"};
+    if (o.cycle_index_A < 0 || o.cycle_index_A > 3 || o.cycle_index_S < 0 || o.cycle_index_S > 3)
+        throw Fail{NS_ERR_ARG, "AMG cycle index out of range [1, 3]"};
     for (double sc : {o.cc_scale_A, o.cc_scale_S})
         if (!(sc >= 0.0 && sc <= 2.0)) throw Fail{NS_ERR_ARG, "coarse-grid correction scale out of range [0, 2]"};
 }

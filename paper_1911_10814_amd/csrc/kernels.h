@@ -92,6 +92,9 @@ void mul(int64_t n, const T* a, const T* x, T* y, hipStream_t st);  // y = a .* 
 // |g_{j+1}|, [1] = breakdown flag, [2] = 1/h_{j+1,j}, [3] = ||w_pre||), and
 // w is normalised.  h1 [j+2] / h2 [j+1] receive the dot products of the two
 // passes (h1[j+1] = ||w_pre||^2); `red` holds the per-block partial sums.
+// Bases of up to this many vectors take the single-pass form of the pass-1
+// update and pass-2 dots (each thread's packs of the basis kept in registers).
+constexpr int kOrthFuseMax = 16;
 struct GivensArgs {
     int j = 0, ldh = 0;
     const double* h1 = nullptr;

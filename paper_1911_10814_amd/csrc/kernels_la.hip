@@ -560,8 +560,51 @@ __global__ __launch_bounds__(kCgsBlock) void k_orth_dot(int64_t n, int k, const 
     block_reduce_partials<T>(red1, k + 1, G1, hs);
     if (blockIdx.x == 0)
         for (int i = threadIdx.x; i <= k; i += kCgsBlock) h1[i] = (double)hs[i];
-    (void)orth_subtract<T>(n, k, V, ldv, hs, w);
     const int64_t np = n_packs<T>(n);
+    if (k <= kOrthFuseMax) {
+        // Short bases (the A-level solves): each thread keeps its packs of
+        // V_0..V_{k-1} in registers, so the update and the pass-2 dots read V
+        // once; the sums are the same, in the same order, as the two-pass form.
+        T acc[kOrthFuseMax];
+#pragma unroll
+        for (int i = 0; i < kOrthFuseMax; ++i) acc[i] = 0;
+        for (int64_t q = (int64_t)blockIdx.x * kCgsBlock + threadIdx.x; q < np;
+             q += (int64_t)gridDim.x * kCgsBlock) {
+            Pk<T> v[kOrthFuseMax];
+#pragma unroll
+            for (int i = 0; i < kOrthFuseMax; ++i)
+                if (i < k) v[i] = ld_pk(V + (int64_t)i * ldv, q, n);
+            Pk<T> sv;
+#pragma unroll
+            for (int e = 0; e < Pk<T>::W; ++e) sv.e[e] = 0;
+#pragma unroll
+            for (int i = 0; i < kOrthFuseMax; ++i)
+                if (i < k) {
+                    const T h = hs[i];
+#pragma unroll
+                    for (int e = 0; e < Pk<T>::W; ++e) sv.e[e] += v[i].e[e] * h;
+                }
+            Pk<T> wp = ld_pk(w, q, n);
+#pragma unroll
+            for (int e = 0; e < Pk<T>::W; ++e) wp.e[e] -= sv.e[e];
+            reinterpret_cast<Pk<T>*>(w)[q] = wp;
+#pragma unroll
+            for (int i = 0; i < kOrthFuseMax; ++i)
+                if (i < k) acc[i] += pk_dot(v[i], wp);
+        }
+        static_assert(kOrthFuseMax == 2 * kDotGroup, "two groups of pass-2 partials");
+        T g8[kDotGroup];
+#pragma unroll
+        for (int g = 0; g < kDotGroup; ++g) g8[g] = acc[g];
+        block_partials<T, kDotGroup>(g8, min(kDotGroup, k), lds, red2);
+        if (k > kDotGroup) {
+#pragma unroll
+            for (int g = 0; g < kDotGroup; ++g) g8[g] = acc[kDotGroup + g];
+            block_partials<T, kDotGroup>(g8, k - kDotGroup, lds, red2 + (int64_t)kDotGroup * gridDim.x);
+        }
+        return;
+    }
+    (void)orth_subtract<T>(n, k, V, ldv, hs, w);
     for (int i0 = 0; i0 < k; i0 += kDotGroup) {
         T acc[kDotGroup];
 #pragma unroll

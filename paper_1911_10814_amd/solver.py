@@ -40,6 +40,8 @@ class SolveOptions:
     cc_scale_A: float = 1.0      # AMG coarse-grid correction scaling, A hierarchy
     cc_scale_S: float = 1.0      # and S_hat hierarchy
     cycles_S: int = 1            # V-cycle iterations per application of P_S
+    cycle_index_A: int = 1       # AMG cycle index below the finest level (1: V, 2: W), A hierarchy
+    cycle_index_S: int = 1       # and S_hat hierarchy
     pc: str = "scr"              # outer preconditioner: "scr" (Algorithm 3) | "simple" (Sec. 3.2)
     schedule: list | None = None  # fixed iteration counts per Krylov call (replay)
     record: bool = True           # record the iteration count of every Krylov call
@@ -47,7 +49,8 @@ class SolveOptions:
     def to_c(self):
         o = _lib.NsSolveOpts()
         for f in ("rtol", "atol", "rtol_A", "rtol_S", "rtol_I", "m", "nmax", "m_A", "nmax_A", "m_S", "nmax_S",
-                  "cheb_degree", "cheb_degree_S", "cheb_ratio", "cycles_S", "cc_scale_A", "cc_scale_S"):
+                  "cheb_degree", "cheb_degree_S", "cheb_ratio", "cycles_S", "cc_scale_A", "cc_scale_S",
+                  "cycle_index_A", "cycle_index_S"):
             setattr(o, f, getattr(self, f))
         o.pc_A = {"amg": 0, "jacobi": 1}[self.pc_A]
         o.pc_I = {None: 0, "amg": 1, "jacobi": 2}[self.pc_I]

@@ -200,6 +200,28 @@ def test_nested_solve_replay_on_large_mesh_paths(name):
     assert ev <= 1e-10 and ep <= 1e-10
 
 
+@pytest.mark.parametrize("name", ["pipe_tiny", "ybif_small", "unstr_channel"])
+@pytest.mark.parametrize("gamma", [(2, 2), (1, 3)])
+def test_cycle_index_matches_oracle(name, gamma):
+    """W-cycles (cycle index 2) and cycle index 3 below the finest level: one
+    V-cycle of each hierarchy at 1e-11 and a replayed FP64 solve at 1e-10."""
+    from paper_1911_10814_amd import SolveOptions
+    kw = dict(cycle_index_A=gamma[0], cycle_index_S=gamma[1])
+    ctx = ctx_for(name)
+    ns = oracle_solver(name, **kw)
+    o = SolveOptions(**kw)
+    rng = np.random.default_rng(9)
+    x3 = rng.standard_normal(3 * ctx.N)
+    x1 = rng.standard_normal(ctx.N)
+    ea = rel(ctx.apply("vcycle_A", x3, o)[0].cpu().numpy(), ns.amgA.vcycle(x3))
+    es = rel(ctx.apply("vcycle_S", x1, o)[0].cpu().numpy(), ns.amgS.vcycle(x1))
+    assert ea <= 1e-11 and es <= 1e-11, (ea, es)
+    S = get_assembled(name)
+    xo, info = ns.solve(S.rhs)
+    xg, _ = ctx.solve(ctx._rhs, SolveOptions(schedule=info["schedule"], **kw))
+    assert rel(xg.cpu().numpy(), xo) <= 1e-10
+
+
 @pytest.mark.parametrize("name", ["channel2", "ybif_small"])
 def test_scaled_coarse_correction_replay_matches_oracle(name):
     """Over-scaled coarse-grid corrections on both hierarchies."""

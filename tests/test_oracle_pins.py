@@ -660,6 +660,37 @@ def test_amg_two_level_cycle_dense_formula(cc):
     assert np.abs(h.vcycle(b) - B @ b).max() <= 1e-10 * np.abs(B @ b).max()
 
 
+@pytest.mark.parametrize("gamma", [1, 2, 3])
+def test_amg_three_level_cycle_index_dense_formula(gamma):
+    """Three levels, degree-1 smoothing (T_l = D_l^-1 / theta_l), exact coarsest
+    solve: the finest level takes one coarse-grid correction, level 1 takes
+    gamma (each followed by its post-smoothing), written as dense matrices:
+    B_1 = X with X <- T_1, then gamma times X <- X + P_1 M_2^-1 P_1^T (I - M_1 X),
+    X <- X + T_1 (I - M_1 X); B_0 likewise with B_1 in place of M_2^-1, once."""
+    S = get_assembled("channel2")
+    c = get_case("channel2")
+    adj = amg.node_adjacency(c.n_nodes, c.tets)
+    aggs = amg.build_aggregates(adj, coarse_nodes=8)[:2]
+    assert len(aggs) == 2
+    h = amg.AMG(S.A_F, 3, aggs, cheb_degree=1, cycle_index=gamma)
+    Ms = [m.toarray() for m in h.M]
+    Ps = [p.toarray() for p in h.P]
+    Ts = [np.diag(1.0 / np.diag(Ms[l])) / (0.5 * (h.lmax[l] + h.lmax[l] / 10.0)) for l in range(2)]
+
+    def level(l, Bc, reps):
+        n = Ms[l].shape[0]
+        X = Ts[l].copy()
+        for _ in range(reps):
+            X = X + Ps[l] @ Bc @ Ps[l].T @ (np.eye(n) - Ms[l] @ X)
+            X = X + Ts[l] @ (np.eye(n) - Ms[l] @ X)
+        return X
+
+    B1 = level(1, np.linalg.inv(Ms[2]), gamma)
+    B0 = level(0, B1, 1)
+    b = np.random.default_rng(6).standard_normal(Ms[0].shape[0])
+    assert np.abs(h.vcycle(b) - B0 @ b).max() <= 1e-9 * np.abs(B0 @ b).max()
+
+
 # --------------------------------------------------------------------------- adjoint
 
 
