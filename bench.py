@@ -123,9 +123,10 @@ def stream_ceiling(dev):
 
 def kernels_mode(args):
     """Finest-level kernels launched on their own (the A operator SpMV, one
-    AMG V-cycle of A, one factored S_hat smoothing V-cycle) and a device copy of
-    known size that calibrates the FETCH_SIZE / WRITE_SIZE counters; prints
-    the algorithmic bytes per launch."""
+    AMG V-cycle of A, one V-cycle of S_hat with its factored finest level, one
+    point-Jacobi GMRES A-solve for the CGS2 kernels) and a device copy of known
+    size that calibrates the FETCH_SIZE / WRITE_SIZE counters; prints the
+    algorithmic bytes per launch of the A operator."""
     import numpy as np
     import torch
 
@@ -146,6 +147,8 @@ def kernels_mode(args):
         ctx.apply("vcycle_A", x3, o)
     for _ in range(args.reps):
         ctx.apply("vcycle_S", x1, o)
+    # one GMRES A-solve with point Jacobi: the CGS2 kernels at short bases
+    ctx.apply("solve_A", x3, SolveOptions(precision=args.precision, pc_A="jacobi", rtol_A=1e-3))
     log("kernels: operators done")
     copy_bytes = 512 << 20
     a = torch.ones(copy_bytes, dtype=torch.uint8, device="cuda")
