@@ -240,7 +240,7 @@ void layout(ns_ctx* c, Arena& A) {
     c->t_xhat = A.take<double>(N);
     c->t_xbar = A.take<double>(3 * (size_t)N);
     c->t_xt = A.take<double>(3 * (size_t)N);
-    c->t_sf = A.take<double>(3 * (size_t)N);
+    c->t_sf = A.take<double>(4 * (size_t)N);
     c->t_ps = A.take<double>(2 * (size_t)N);
     c->nt_yaf = A.take<double>(4 * (size_t)N);
     c->nt_ydam = A.take<double>(4 * (size_t)N);
@@ -647,6 +647,7 @@ struct Nested {
         // (the 3x3 A operator keeps 16: 9 values per block already keep
         // enough loads in flight)
         if (M.lanes == 16 && (r0 == 3 || c0 == 3)) M.lanes = 8;
+        M.unroll = unroll_for(nnzb, N);
         M.xcd = xcd_rows(N, c0 == 3 ? 1 : 3);
         return M;
     }
@@ -660,21 +661,23 @@ struct Nested {
         M.cs = d.cstride;
         M.dextra = Typed<T>::dextra(d);
         M.lanes = lanes_for(d.nnz, d.n, d.bs);
+        M.unroll = unroll_for(d.nnz, d.n);
         M.xcd = xcd_rows(d.n, d.bs);
         return M;
     }
     // Factored S_hat application (both passes), timed as one class.
     // Algorithmic bytes: pass 1 reads the three B planes and the column
-    // indices, row pointers, x, diag(A)^-1 and writes t (3 per node); pass 2
-    // reads the three C planes, the D plane, columns, row pointers, x, t and
-    // writes y, plus the Chebyshev operands (b, dinv, d) when smoothing.
+    // indices, row pointers, x, diag(A)^-1 (and the aggregate map with the
+    // coarse correction) and writes t (4 per node); pass 2 reads the three C
+    // planes, the D plane, columns, row pointers, t and writes y, plus the
+    // Chebyshev operands (b, dinv, d) when smoothing.
     void sfact(const T* x, const int32_t* agg, const T* ec, T* y, T alpha, const T* z, T beta, const T* b,
                const T* dinv, const T* coef, int step, T* d) {
         const double sz = sizeof(T), n = N;
-        double bytes = (double)nnzb * (7 * sz + 8) + 8.0 * (n + 1) + n * sz * (1 + 3 + 3) + n * sz * (1 + 3 + 1);
+        double bytes = (double)nnzb * (7 * sz + 8) + 8.0 * (n + 1) + n * sz * (1 + 3 + 4) + n * sz * (4 + 1);
         if (coef) bytes += n * sz * (step != 0 ? 4 : 3);
         else if (z) bytes += n * sz;
-        if (agg) bytes += 2 * n * (4 + sz);
+        if (agg) bytes += n * (4 + sz);
         timed(c, NS_KT_SFACT, bytes, K.st, [&] {
             shat_factored<T>(N, c->d_rp, c->d_col, V(), nnzb, Typed<T>::dinvA(sy), x, agg, ec, as<T>(c->t_sf), y,
                              alpha, z, beta, b, dinv, coef, step, d, xcd_rows(N, 1), kSfactLanes, K.st);
@@ -1089,6 +1092,7 @@ void setup_device(ns_ctx* c, SystemDev& y, hipStream_t st) {
             M.cs = d.cstride;
             M.dextra = d.dextra64;
             M.lanes = lanes_for(d.nnz, d.n, d.bs);
+            M.unroll = unroll_for(d.nnz, d.n);
             smoother_bound_dev(c, M, d.bs, d.dinv64, d.x0, d.r, d.b, bnd + 3 * (h * L + l), ps);
         }
     };

@@ -38,7 +38,8 @@ struct BlockOp {
     const T* v = nullptr;
     int64_t rs = 0, cs = 0;
     const T* dextra = nullptr;  // optional extra diagonal [BR*n]
-    int lanes = 16;             // lanes per block row (16, 32 or 64), from the mean row length
+    int lanes = 16;             // lanes per block row (8, 16, 32 or 64), from the mean row length
+    int unroll = 2;             // 8-lane rows: entries per lane per trip (2 or 4), from the mean row length
     int xcd = 0;                // 1: each XCD takes one contiguous range of rows (xcd_block)
 };
 
@@ -61,6 +62,9 @@ inline int lanes_for(int64_t nnz, int n, int bs) {
     const double avg = n > 0 ? (double)nnz / n : 0.0;
     return avg <= 16.0 ? 16 : (avg <= 32.0 ? 32 : 64);
 }
+// Entries per lane per trip of an 8-lane row walk: enough that a typical row
+// is one trip (all its loads in flight together).
+inline int unroll_for(int64_t nnz, int n) { return (double)nnz <= 16.0 * (n > 0 ? n : 1) ? 2 : 4; }
 
 // y = alpha * (M x [+ dextra x] [+ rank one]) + beta * z, then y *= rscale
 template <typename T>
@@ -140,7 +144,7 @@ template <typename T>
 void restrict_first(int nc, int bs, const int32_t* aptr, const int32_t* anodes, const T* r, T* bc, T* xc, T* dc,
                     const T* dinvc, const T* coefc, const T* scale, hipStream_t st);
 // Factored S_hat = D - C diag(A)^{-1} B on the node pattern (V: the 16 value
-// planes; t: [3n] scratch).  With coef == nullptr: y = alpha S_hat xx + beta z;
+// planes; t: [4n] scratch, 16-byte aligned).  With coef == nullptr: y = alpha S_hat xx + beta z;
 // else one Chebyshev step y = xx + d, d = c1 d + c2 dinv (b - S_hat xx), where
 // xx = x, or x + P ec when agg != nullptr.
 template <typename T>

@@ -4,9 +4,10 @@
 // tau_M, tau_C and the metric G built with the simplex matrix M) are
 // integrated with the 4-point degree-2 rule; the tangent blocks are the
 // alpha_m / alpha_f gamma dt weighted derivatives of Sec. 2.5 with tau_M and
-// tau_C held at the current state.  One thread per element, one launch per
-// colour (no two elements of a colour share a node), so every block and
-// residual entry is updated by plain read-modify-write without atomics.  The
+// tau_C held at the current state.  Sixteen lanes per element, one per
+// (a, b) node pair, and one launch per colour (no two elements of a colour
+// share a node), so every block and residual entry is updated by plain
+// read-modify-write without atomics.  The
 // blocks are accumulated as [nnzb][16] (128 contiguous bytes per block hit)
 // and transposed into the [16][nnzb] value planes the solver streams.
 #include <hip/hip_runtime.h>

@@ -109,7 +109,23 @@ void launch_span(K kernel, dim3 grid, dim3 block, size_t shmem, hipStream_t st, 
     }
 }
 
-template <typename T, int BR, int BC, int W>
+// A lane's walk over its row's blocks k = kb + lane + m W, U blocks per trip:
+// every load of a trip (column indices, value planes, then the gathers that
+// depend on the columns) is issued before any is used, and all lanes of a
+// row take the same trips (no divergent remainder).  A block at or past the
+// row end repeats the trip's first (an address already being fetched) and
+// adds nothing.  Blocks are accumulated in the order of k either way.
+template <int U>
+__device__ inline void trip_blocks(int k0, int ke, int W, int (&kk)[U], bool (&on)[U]) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int k = k0 + u * W;
+        on[u] = k < ke;
+        kk[u] = on[u] ? k : k0;
+    }
+}
+
+template <typename T, int BR, int BC, int W, int U>
 __global__ __launch_bounds__(kBlock) void k_spmv(BlockOp<T> M, const T* __restrict__ x, T* __restrict__ y, T alpha,
                                                  const T* __restrict__ z, T beta, const T* __restrict__ rscale,
                                                  RankOne<T> ro, FirstStep<T> fs) {
@@ -143,26 +159,31 @@ __global__ __launch_bounds__(kBlock) void k_spmv(BlockOp<T> M, const T* __restri
     T acc[BR];
 #pragma unroll
     for (int r = 0; r < BR; ++r) acc[r] = 0;
-    auto block = [&](int k) {
-        const int j = M.col[k];
-        T xj[BC];
+    for (int k0 = kb + lane; k0 < ke; k0 += U * W) {
+        int kk[U];
+        bool on[U];
+        trip_blocks<U>(k0, ke, W, kk, on);
+        int j[U];
 #pragma unroll
-        for (int c = 0; c < BC; ++c) xj[c] = x[(int64_t)BC * j + c];
+        for (int u = 0; u < U; ++u) j[u] = M.col[kk[u]];
+        T v[U][BR * BC];
 #pragma unroll
-        for (int r = 0; r < BR; ++r)
+        for (int u = 0; u < U; ++u)
 #pragma unroll
-            for (int c = 0; c < BC; ++c) acc[r] += M.v[r * M.rs + c * M.cs + k] * xj[c];
-    };
-    if constexpr (W == 8 && BR * BC == 1) {
-        // scalar rows: several entries per lane, issued before any is used
-#pragma unroll 4
-        for (int k = kb + lane; k < ke; k += W) block(k);
-    } else if constexpr (W == 8) {
-        // two blocks per lane on a typical row: both issued before either is used
-#pragma unroll 2
-        for (int k = kb + lane; k < ke; k += W) block(k);
-    } else {
-        for (int k = kb + lane; k < ke; k += W) block(k);
+            for (int r = 0; r < BR; ++r)
+#pragma unroll
+                for (int c = 0; c < BC; ++c) v[u][r * BC + c] = M.v[r * M.rs + c * M.cs + kk[u]];
+        T xj[U][BC];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int c = 0; c < BC; ++c) xj[u][c] = x[(int64_t)BC * j[u] + c];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int r = 0; r < BR; ++r)
+#pragma unroll
+                for (int c = 0; c < BC; ++c) acc[r] += v[u][r * BC + c] * (on[u] ? xj[u][c] : T(0));
     }
 #pragma unroll
     for (int off = W / 2; off > 0; off >>= 1)
@@ -199,20 +220,24 @@ void spmv_w(const BlockOp<T>& M, const T* x, T* y, T alpha, const T* z, T beta, 
             const RankOne<T>& r1, const FirstStep<T>& fs, hipStream_t st) {
     switch (M.lanes) {
         case 64:
-            launch_timed(k_spmv<T, BR, BC, 64>, dim3(grid_for((int64_t)M.n * 64)), dim3(kBlock), st, M,
-                               x, y, alpha, z, beta, rscale, r1, fs);
+            launch_timed(k_spmv<T, BR, BC, 64, 1>, dim3(grid_for((int64_t)M.n * 64)), dim3(kBlock), st, M, x, y,
+                         alpha, z, beta, rscale, r1, fs);
             break;
         case 32:
-            launch_timed(k_spmv<T, BR, BC, 32>, dim3(grid_for((int64_t)M.n * 32)), dim3(kBlock), st, M,
-                               x, y, alpha, z, beta, rscale, r1, fs);
+            launch_timed(k_spmv<T, BR, BC, 32, 1>, dim3(grid_for((int64_t)M.n * 32)), dim3(kBlock), st, M, x, y,
+                         alpha, z, beta, rscale, r1, fs);
             break;
         case 8:
-            launch_timed(k_spmv<T, BR, BC, 8>, dim3(grid_for((int64_t)M.n * 8)), dim3(kBlock), st, M,
-                               x, y, alpha, z, beta, rscale, r1, fs);
+            if (M.unroll == 4)
+                launch_timed(k_spmv<T, BR, BC, 8, 4>, dim3(grid_for((int64_t)M.n * 8)), dim3(kBlock), st, M, x, y,
+                             alpha, z, beta, rscale, r1, fs);
+            else
+                launch_timed(k_spmv<T, BR, BC, 8, 2>, dim3(grid_for((int64_t)M.n * 8)), dim3(kBlock), st, M, x, y,
+                             alpha, z, beta, rscale, r1, fs);
             break;
         default:
-            launch_timed(k_spmv<T, BR, BC, 16>, dim3(grid_for((int64_t)M.n * 16)), dim3(kBlock), st, M,
-                               x, y, alpha, z, beta, rscale, r1, fs);
+            launch_timed(k_spmv<T, BR, BC, 16, 1>, dim3(grid_for((int64_t)M.n * 16)), dim3(kBlock), st, M, x, y,
+                         alpha, z, beta, rscale, r1, fs);
     }
 }
 
@@ -806,7 +831,7 @@ void cheb_first(int64_t n, const T* b, const T* dinv, const T* coef, T* x, T* d,
 // Fused residual + Chebyshev update: r = b - M x; d = c1 d + c2 dinv r; xout = x + d,
 // where x = xin, or x = xin + P ec (prolongation of the coarse correction ec
 // through the aggregate map) when agg != nullptr.
-template <typename T, int BS, int W>
+template <typename T, int BS, int W, int U>
 __global__ __launch_bounds__(kBlock) void k_cheb_step(BlockOp<T> M, const T* __restrict__ xin, T* __restrict__ xout,
                                                       T* __restrict__ d, const T* __restrict__ b,
                                                       const T* __restrict__ dinv, const T* __restrict__ coef,
@@ -841,30 +866,40 @@ __global__ __launch_bounds__(kBlock) void k_cheb_step(BlockOp<T> M, const T* __r
     T acc[BS];
 #pragma unroll
     for (int r = 0; r < BS; ++r) acc[r] = 0;
-    auto block = [&](int k) {
-        const int j = M.col[k];
-        T xj[BS];
+    for (int k0 = kb + lane; k0 < ke; k0 += U * W) {
+        int kk[U];
+        bool on[U];
+        trip_blocks<U>(k0, ke, W, kk, on);
+        int j[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) j[u] = M.col[kk[u]];
+        T v[U][BS * BS];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int r = 0; r < BS; ++r)
+#pragma unroll
+                for (int c = 0; c < BS; ++c) v[u][r * BS + c] = M.v[r * M.rs + c * M.cs + kk[u]];
+        T xj[U][BS];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int c = 0; c < BS; ++c) xj[u][c] = xin[(int64_t)BS * j[u] + c];
         if (agg) {
-            const int64_t J = agg[j];
+            int J[U];
 #pragma unroll
-            for (int c = 0; c < BS; ++c) xj[c] = xin[(int64_t)BS * j + c] + ec[BS * J + c];
-        } else {
+            for (int u = 0; u < U; ++u) J[u] = agg[j[u]];
 #pragma unroll
-            for (int c = 0; c < BS; ++c) xj[c] = xin[(int64_t)BS * j + c];
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int c = 0; c < BS; ++c) xj[u][c] += ec[(int64_t)BS * J[u] + c];
         }
 #pragma unroll
-        for (int r = 0; r < BS; ++r)
+        for (int u = 0; u < U; ++u)
 #pragma unroll
-            for (int c = 0; c < BS; ++c) acc[r] += M.v[r * M.rs + c * M.cs + k] * xj[c];
-    };
-    if constexpr (BS == 1 && W <= 8) {
-#pragma unroll 4
-        for (int k = kb + lane; k < ke; k += W) block(k);
-    } else if constexpr (BS == 1 && W <= 32) {
-#pragma unroll 2
-        for (int k = kb + lane; k < ke; k += W) block(k);
-    } else {
-        for (int k = kb + lane; k < ke; k += W) block(k);
+            for (int r = 0; r < BS; ++r)
+#pragma unroll
+                for (int c = 0; c < BS; ++c) acc[r] += v[u][r * BS + c] * (on[u] ? xj[u][c] : T(0));
     }
 #pragma unroll
     for (int off = W / 2; off > 0; off >>= 1)
@@ -891,20 +926,24 @@ void cheb_step_w(const BlockOp<T>& M, const T* xin, T* xout, T* d, const T* b, c
                  const int32_t* agg, const T* ec, hipStream_t st) {
     switch (M.lanes) {
         case 64:
-            launch_timed(k_cheb_step<T, BS, 64>, dim3(grid_for((int64_t)M.n * 64)), dim3(kBlock), st, M,
-                               xin, xout, d, b, dinv, coef, step, agg, ec);
+            launch_timed(k_cheb_step<T, BS, 64, 1>, dim3(grid_for((int64_t)M.n * 64)), dim3(kBlock), st, M, xin,
+                         xout, d, b, dinv, coef, step, agg, ec);
             break;
         case 8:
-            launch_timed(k_cheb_step<T, BS, 8>, dim3(grid_for((int64_t)M.n * 8)), dim3(kBlock), st, M,
-                               xin, xout, d, b, dinv, coef, step, agg, ec);
+            if (M.unroll == 4)
+                launch_timed(k_cheb_step<T, BS, 8, 4>, dim3(grid_for((int64_t)M.n * 8)), dim3(kBlock), st, M, xin,
+                             xout, d, b, dinv, coef, step, agg, ec);
+            else
+                launch_timed(k_cheb_step<T, BS, 8, 2>, dim3(grid_for((int64_t)M.n * 8)), dim3(kBlock), st, M, xin,
+                             xout, d, b, dinv, coef, step, agg, ec);
             break;
         case 32:
-            launch_timed(k_cheb_step<T, BS, 32>, dim3(grid_for((int64_t)M.n * 32)), dim3(kBlock), st, M,
-                               xin, xout, d, b, dinv, coef, step, agg, ec);
+            launch_timed(k_cheb_step<T, BS, 32, 1>, dim3(grid_for((int64_t)M.n * 32)), dim3(kBlock), st, M, xin,
+                         xout, d, b, dinv, coef, step, agg, ec);
             break;
         default:
-            launch_timed(k_cheb_step<T, BS, 16>, dim3(grid_for((int64_t)M.n * 16)), dim3(kBlock), st, M,
-                               xin, xout, d, b, dinv, coef, step, agg, ec);
+            launch_timed(k_cheb_step<T, BS, 16, 1>, dim3(grid_for((int64_t)M.n * 16)), dim3(kBlock), st, M, xin,
+                         xout, d, b, dinv, coef, step, agg, ec);
     }
 }
 
@@ -921,89 +960,147 @@ void cheb_step(int bs, const BlockOp<T>& M, const T* xin, T* xout, T* d, const T
 // level, two passes over the node-block value planes (V: the 16 planes, B in
 // planes 4r+3, C in planes 12+c, D in plane 15), instead of one pass over the
 // explicit distance-2 pattern of S_hat (several times more gathers):
-//   pass 1: t = dinvA .* (B xx)                        (3 values per node)
+//   pass 1: t4[4i..4i+2] = dinvA .* (B xx), t4[4i+3] = xx_i
 //   pass 2: s = D xx - C t, then the Chebyshev update with residual b - s
 //           (coef != nullptr), else y = alpha s + beta z
 // where xx = x, or x + P ec (prolongated coarse correction) when agg != nullptr.
-template <typename T, int W>
+// Pass 2 gathers one 4-wide record per block (the three t values and xx of
+// the column node), so the aggregate map is read by pass 1 only.  Both passes
+// walk their rows U blocks per lane per trip as the block SpMV does.
+template <typename T>
+struct Vec4 {
+    T a, b, c, d;
+};
+__device__ inline Vec4<float> load4(const float* p) {
+    const float4 q = *reinterpret_cast<const float4*>(p);
+    return {q.x, q.y, q.z, q.w};
+}
+__device__ inline Vec4<double> load4(const double* p) {
+    const double2 q0 = reinterpret_cast<const double2*>(p)[0];
+    const double2 q1 = reinterpret_cast<const double2*>(p)[1];
+    return {q0.x, q0.y, q1.x, q1.y};
+}
+
+template <typename T, int W, bool AGG>
 __global__ __launch_bounds__(kBlock) void k_sfact_bt(int n, const int32_t* __restrict__ rp,
                                                      const int32_t* __restrict__ col, const T* __restrict__ V,
                                                      int64_t nnzb, const T* __restrict__ dinvA,
                                                      const T* __restrict__ x, const int32_t* __restrict__ agg,
-                                                     const T* __restrict__ ec, T* __restrict__ t, int xcd) {
+                                                     const T* __restrict__ ec, T* __restrict__ t4, int xcd) {
+    constexpr int U = W < 16 ? 16 / W : 1;
     const int64_t tid = (xcd ? xcd_block() : (int64_t)blockIdx.x) * kBlock + threadIdx.x;
     const int row = (int)(tid / W);
     const int lane = threadIdx.x % W;
     const bool valid = row < n;
-    const int64_t i = 3 * (int64_t)row + lane;
     int kb = 0, ke = 0;
     if (valid) {
         kb = rp[row];
         ke = rp[row + 1];
     }
-    const T dai = (valid && lane < 3) ? dinvA[i] : T(0);  // loaded ahead of the row loop
+    // own-row operands, loaded ahead of the row loop: diag(A)^{-1} on lanes
+    // 0-2, the row's xx on lane 3
+    T dai = 0, xo = 0, eco = 0;
+    if (valid && lane < 3) dai = dinvA[3 * (int64_t)row + lane];
+    if (valid && lane == 3) {
+        xo = x[row];
+        if (AGG) eco = ec[agg[row]];
+    }
     T acc[3] = {0, 0, 0};
-    {
-#pragma unroll 2
-        for (int k = kb + lane; k < ke; k += W) {
-            const int j = col[k];
-            T xj = x[j];
-            if (agg) xj += ec[agg[j]];
+    for (int k0 = kb + lane; k0 < ke; k0 += U * W) {
+        int kk[U];
+        bool on[U];
+        trip_blocks<U>(k0, ke, W, kk, on);
+        int j[U];
 #pragma unroll
-            for (int r = 0; r < 3; ++r) acc[r] += V[(4 * r + 3) * nnzb + k] * xj;
+        for (int u = 0; u < U; ++u) j[u] = col[kk[u]];
+        T v[U][3];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int r = 0; r < 3; ++r) v[u][r] = V[(4 * r + 3) * nnzb + kk[u]];
+        T xj[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) xj[u] = x[j[u]];
+        if (AGG) {
+            int J[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) J[u] = agg[j[u]];
+#pragma unroll
+            for (int u = 0; u < U; ++u) xj[u] += ec[J[u]];
         }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int r = 0; r < 3; ++r) acc[r] += v[u][r] * (on[u] ? xj[u] : T(0));
     }
 #pragma unroll
     for (int off = W / 2; off > 0; off >>= 1)
 #pragma unroll
         for (int r = 0; r < 3; ++r) acc[r] += __shfl_xor(acc[r], off, W);
-    if (!valid || lane >= 3) return;
-    const T s = lane == 0 ? acc[0] : (lane == 1 ? acc[1] : acc[2]);
-    t[i] = dai * s;
+    if (!valid || lane > 3) return;
+    T out;
+    if (lane == 3) {
+        out = xo;
+        if (AGG) out += eco;
+    } else {
+        out = dai * (lane == 0 ? acc[0] : (lane == 1 ? acc[1] : acc[2]));
+    }
+    t4[4 * (int64_t)row + lane] = out;
 }
 
 template <typename T, int W>
 __global__ __launch_bounds__(kBlock) void k_sfact_dc(int n, const int32_t* __restrict__ rp,
                                                      const int32_t* __restrict__ col, const T* __restrict__ V,
-                                                     int64_t nnzb, const T* __restrict__ t, const T* __restrict__ x,
-                                                     const int32_t* __restrict__ agg, const T* __restrict__ ec,
-                                                     T* __restrict__ y, T alpha, const T* __restrict__ z, T beta,
+                                                     int64_t nnzb, const T* __restrict__ t4, T* __restrict__ y,
+                                                     T alpha, const T* __restrict__ z, T beta,
                                                      const T* __restrict__ b, const T* __restrict__ dinv,
                                                      const T* __restrict__ coef, int step, T* __restrict__ d,
                                                      int xcd) {
+    constexpr int U = W < 16 ? 16 / W : 1;
     const int64_t tid = (xcd ? xcd_block() : (int64_t)blockIdx.x) * kBlock + threadIdx.x;
     const int row = (int)(tid / W);
     const int lane = threadIdx.x % W;
     const bool valid = row < n;
-    // own-row epilogue operands, loaded ahead of the row loop with no use of a
-    // loaded value before it: the row's aggregate first (its coarse
-    // correction is one more load), then the row bounds and the rest
+    // own-row epilogue operands, loaded ahead of the row loop
     const bool smooth_lane = valid && lane == 0 && coef;
-    int ag = 0, kb = 0, ke = 0;
-    if (smooth_lane && agg) ag = agg[row];
+    int kb = 0, ke = 0;
     if (valid) {
         kb = rp[row];
         ke = rp[row + 1];
     }
-    T zi = 0, xi = 0, eci = 0, bi = 0, dvi = 0, dprev = 0;
+    T zi = 0, xi = 0, bi = 0, dvi = 0, dprev = 0;
     if (valid && lane == 0 && !coef && z) zi = z[row];
     if (smooth_lane) {
-        xi = x[row];
+        xi = t4[4 * (int64_t)row + 3];
         bi = b[row];
         dvi = dinv[row];
         if (step != 0) dprev = d[row];
-        if (agg) eci = ec[ag];
     }
     T acc = 0;
-    {
-#pragma unroll 2
-        for (int k = kb + lane; k < ke; k += W) {
-            const int j = col[k];
-            T xj = x[j];
-            if (agg) xj += ec[agg[j]];
-            acc += V[15 * nnzb + k] * xj;
+    for (int k0 = kb + lane; k0 < ke; k0 += U * W) {
+        int kk[U];
+        bool on[U];
+        trip_blocks<U>(k0, ke, W, kk, on);
+        int j[U];
 #pragma unroll
-            for (int c = 0; c < 3; ++c) acc -= V[(12 + c) * nnzb + k] * t[3 * (int64_t)j + c];
+        for (int u = 0; u < U; ++u) j[u] = col[kk[u]];
+        T vd[U], vc[U][3];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            vd[u] = V[15 * nnzb + kk[u]];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) vc[u][c] = V[(12 + c) * nnzb + kk[u]];
+        }
+        Vec4<T> q[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) q[u] = load4(t4 + 4 * (int64_t)j[u]);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (!on[u]) q[u] = Vec4<T>{0, 0, 0, 0};
+            acc += vd[u] * q[u].d;
+            acc -= vc[u][0] * q[u].a;
+            acc -= vc[u][1] * q[u].b;
+            acc -= vc[u][2] * q[u].c;
         }
     }
 #pragma unroll
@@ -1015,7 +1112,6 @@ __global__ __launch_bounds__(kBlock) void k_sfact_dc(int n, const int32_t* __res
         y[row] = out;
         return;
     }
-    if (agg) xi += eci;
     T c1, c2;
     cheb_coef(coef, step, c1, c2);
     T di = c2 * dvi * (bi - acc);
@@ -1032,10 +1128,14 @@ void shat_factored(int n, const int32_t* rp, const int32_t* col, const T* V, int
     auto run = [&](auto w) {
         constexpr int W = decltype(w)::value;
         const dim3 grid(grid_for((int64_t)n * W));
-        launch_span(k_sfact_bt<T, W>, grid, dim3(kBlock), 0, st, true, false, n, rp, col, V, nnzb, dinvA, x, agg, ec,
-                    t, xcd);
-        launch_span(k_sfact_dc<T, W>, grid, dim3(kBlock), 0, st, false, true, n, rp, col, V, nnzb, (const T*)t, x,
-                    agg, ec, y, alpha, z, beta, b, dinv, coef, step, d, xcd);
+        if (agg)
+            launch_span(k_sfact_bt<T, W, true>, grid, dim3(kBlock), 0, st, true, false, n, rp, col, V, nnzb, dinvA,
+                        x, agg, ec, t, xcd);
+        else
+            launch_span(k_sfact_bt<T, W, false>, grid, dim3(kBlock), 0, st, true, false, n, rp, col, V, nnzb, dinvA,
+                        x, agg, ec, t, xcd);
+        launch_span(k_sfact_dc<T, W>, grid, dim3(kBlock), 0, st, false, true, n, rp, col, V, nnzb, (const T*)t, y,
+                    alpha, z, beta, b, dinv, coef, step, d, xcd);
     };
     if (lanes == 4) run(std::integral_constant<int, 4>{});
     else if (lanes == 8) run(std::integral_constant<int, 8>{});
