@@ -372,10 +372,10 @@ constexpr int kGraphMaxNodes = 1024;
 // finest A levels from this many rows add the prolongated correction in a pass
 // of its own (NS_PROLONG_PASS=0/1, read at bind, forces the fused step or the pass)
 constexpr int kProlongPassRows = 500000;
-// lanes per row of the factored S_hat passes: 8, two blocks in flight per lane
-// (measured 13 % faster than 16 lanes on the 4e6-node contraction-expansion,
-// 7 % on the 2e5-node pipe; 4 lanes was no faster than 16)
-constexpr int kSfactLanes = 8;
+// lanes per row of the factored S_hat passes: 4, a typical row in one trip of
+// four blocks per lane (both passes together on the 4e6-node
+// contraction-expansion: 500 us with 4 lanes, 545 with 8, 721 with 16)
+constexpr int kSfactLanes = 4;
 
 template <typename T>
 double dev_norm(ns_ctx* c, int64_t n, const T* x, double* slot, hipStream_t st) {
@@ -641,12 +641,14 @@ struct Nested {
         M.rs = 4 * nnzb;
         M.cs = nnzb;
         M.lanes = lanes_for(nnzb, N, 3);
-        // the B, C and D operators move 3 or 1 values per block: 8 lanes per
-        // row, two blocks in flight per lane, measured 20-25 % faster than 16
-        // lanes on the 2e6-node pipe and the 4e6-node contraction-expansion
-        // (the 3x3 A operator keeps 16: 9 values per block already keep
-        // enough loads in flight)
-        if (M.lanes == 16 && (r0 == 3 || c0 == 3)) M.lanes = 8;
+        // The thin operators move fewer bytes per block, so fewer lanes per
+        // row (more rows, more loads in flight per wave) pay: C (3 values and a
+        // 3-wide gather per block) 8 lanes, B and D (one gathered value per
+        // block) 4 lanes.  Measured on the 4e6-node contraction-expansion
+        // against 16 lanes: C 288 against 386 us, B 268 against 369 us, D 157
+        // against 298 us; the 3x3 A operator is fastest with 16 (487 against
+        // 533 us with 8 and 556 us with 4).
+        if (M.lanes == 16 && (r0 == 3 || c0 == 3)) M.lanes = c0 == 3 ? 4 : 8;
         M.unroll = unroll_for(nnzb, N);
         M.xcd = xcd_rows(N, c0 == 3 ? 1 : 3);
         return M;

@@ -39,7 +39,7 @@ struct BlockOp {
     int64_t rs = 0, cs = 0;
     const T* dextra = nullptr;  // optional extra diagonal [BR*n]
     int lanes = 16;             // lanes per block row (8, 16, 32 or 64), from the mean row length
-    int unroll = 2;             // 8-lane rows: entries per lane per trip (2 or 4), from the mean row length
+    int unroll = 2;             // 4- and 8-lane rows: 16 (2) or 32 (4) entries per trip, from the mean row length
     int xcd = 0;                // 1: each XCD takes one contiguous range of rows (xcd_block)
 };
 
@@ -62,8 +62,8 @@ inline int lanes_for(int64_t nnz, int n, int bs) {
     const double avg = n > 0 ? (double)nnz / n : 0.0;
     return avg <= 16.0 ? 16 : (avg <= 32.0 ? 32 : 64);
 }
-// Entries per lane per trip of an 8-lane row walk: enough that a typical row
-// is one trip (all its loads in flight together).
+// Entries per trip of a 4- or 8-lane row walk (2: 16 entries, 4: 32): enough
+// that a typical row is one trip (all its loads in flight together).
 inline int unroll_for(int64_t nnz, int n) { return (double)nnz <= 16.0 * (n > 0 ? n : 1) ? 2 : 4; }
 
 // y = alpha * (M x [+ dextra x] [+ rank one]) + beta * z, then y *= rscale

@@ -227,6 +227,14 @@ void spmv_w(const BlockOp<T>& M, const T* x, T* y, T alpha, const T* z, T beta, 
             launch_timed(k_spmv<T, BR, BC, 32, 1>, dim3(grid_for((int64_t)M.n * 32)), dim3(kBlock), st, M, x, y,
                          alpha, z, beta, rscale, r1, fs);
             break;
+        case 4:
+            if (M.unroll == 4)
+                launch_timed(k_spmv<T, BR, BC, 4, 8>, dim3(grid_for((int64_t)M.n * 4)), dim3(kBlock), st, M, x, y,
+                             alpha, z, beta, rscale, r1, fs);
+            else
+                launch_timed(k_spmv<T, BR, BC, 4, 4>, dim3(grid_for((int64_t)M.n * 4)), dim3(kBlock), st, M, x, y,
+                             alpha, z, beta, rscale, r1, fs);
+            break;
         case 8:
             if (M.unroll == 4)
                 launch_timed(k_spmv<T, BR, BC, 8, 4>, dim3(grid_for((int64_t)M.n * 8)), dim3(kBlock), st, M, x, y,
