@@ -444,11 +444,18 @@ __host__ __device__ inline int64_t n_packs(int64_t n) {
 }
 
 // Blocks of every CGS2 kernel for a vector of length n: about one pack per
-// thread, at most 256 partial sums per reduced value.
+// thread, at most kCgsMaxBlocks partial sums per reduced value (two blocks of
+// 512 threads per CU; measured on the 4e6-node contraction-expansion against
+// 256, 1024 and 2048 blocks: 298 against 318, 311 and 370 us per Arnoldi step
+// of the A-solves, 1207 against 1319, 1360 and 1651 us on the S_hat solve's
+// long bases).  The partials fit the reduction buffer: (2k + 2) kCgsMaxBlocks
+// values for k <= mmax basis vectors.
+constexpr int64_t kCgsMaxBlocks = 512;
+static_assert(2 * kCgsMaxBlocks <= kMaxRedBlocks, "CGS2 partials exceed the reduction buffer");
 template <typename T>
 inline unsigned cgs_grid(int64_t n) {
     const int64_t g = (n_packs<T>(n) + kCgsBlock - 1) / kCgsBlock;
-    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(g, 256));
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(g, kCgsMaxBlocks));
 }
 
 // every block: out_lds[i] = sum_b red[i*G + b] for i < nv (one wave per value)
