@@ -406,7 +406,7 @@ void mul(int64_t n, const T* a, const T* x, T* y, hipStream_t st) {
 // the same 16-byte packs of w in every kernel.
 // ---------------------------------------------------------------------------
 
-constexpr int kDotGroup = 8;
+constexpr int kDotGroup = 16;
 constexpr int kCgsBlock = 512;
 constexpr int kCgsWaves = kCgsBlock / 64;
 
@@ -458,14 +458,26 @@ inline unsigned cgs_grid(int64_t n) {
     return (unsigned)std::max<int64_t>(1, std::min<int64_t>(g, kCgsMaxBlocks));
 }
 
-// every block: out_lds[i] = sum_b red[i*G + b] for i < nv (one wave per value)
+// every block: out_lds[i] = sum_b red[i*G + b] for i < nv (one wave per
+// value); a lane's first kRedLoads partials are all loaded before any is
+// added, and every lane adds its partials in order of b
+constexpr int kRedLoads = 8;
+static_assert(kCgsMaxBlocks <= 64 * kRedLoads, "CGS2 partials: one round of loads per lane");
 template <typename T>
 __device__ inline void block_reduce_partials(const T* __restrict__ red, int nv, unsigned G, T* out_lds) {
     const int nw = blockDim.x >> 6;
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     for (int i = wv; i < nv; i += nw) {
+        T p[kRedLoads];
+#pragma unroll
+        for (int u = 0; u < kRedLoads; ++u) {
+            const unsigned b = lane + 64u * u;
+            p[u] = b < G ? red[(int64_t)i * G + b] : T(0);
+        }
         T s = 0;
-        for (unsigned b = lane; b < G; b += 64) s += red[(int64_t)i * G + b];
+#pragma unroll
+        for (int u = 0; u < kRedLoads; ++u) s += p[u];
+        for (unsigned b = lane + 64u * kRedLoads; b < G; b += 64) s += red[(int64_t)i * G + b];
         s = wave_sum(s);
         if (lane == 0) out_lds[i] = s;
     }
@@ -632,16 +644,8 @@ __global__ __launch_bounds__(kCgsBlock) void k_orth_dot(int64_t n, int k, const 
             for (int i = 0; i < kOrthFuseMax; ++i)
                 if (i < k) acc[i] += pk_dot(v[i], wp);
         }
-        static_assert(kOrthFuseMax == 2 * kDotGroup, "two groups of pass-2 partials");
-        T g8[kDotGroup];
-#pragma unroll
-        for (int g = 0; g < kDotGroup; ++g) g8[g] = acc[g];
-        block_partials<T, kDotGroup>(g8, min(kDotGroup, k), lds, red2);
-        if (k > kDotGroup) {
-#pragma unroll
-            for (int g = 0; g < kDotGroup; ++g) g8[g] = acc[kDotGroup + g];
-            block_partials<T, kDotGroup>(g8, k - kDotGroup, lds, red2 + (int64_t)kDotGroup * gridDim.x);
-        }
+        static_assert(kOrthFuseMax == kDotGroup, "one group of pass-2 partials");
+        block_partials<T, kDotGroup>(acc, k, lds, red2);
         return;
     }
     (void)orth_subtract<T>(n, k, V, ldv, hs, w);
