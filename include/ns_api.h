@@ -211,13 +211,15 @@ ns_status ns_ctx_create(const ns_mesh* mesh, const ns_ctx_opts* opts, ns_ctx** o
  * Meshes of up to 1024 nodes replay each Krylov step and set-up chain from
  * a HIP graph captured on first use; larger ones launch directly (the
  * environment variable NS_GRAPHS=0 or 1, read here, forces either form).
- * Two more kernel-path choices are made by size and can be forced here the
- * same way (both compute the same sums; used to test every path on small
+ * Three more kernel-path choices are made by size and can be forced here
+ * the same way (each computes the same sums; used to test every path on small
  * meshes): NS_XCD_ROWS=0/1, block-SpMV rows mapped to one contiguous range
- * per XCD (default: when the gathered vector is <= 8 MB), and
+ * per XCD (default: when the gathered vector is <= 8 MB);
  * NS_PROLONG_PASS=0/1, the finest A level's coarse correction added by a
  * pass of its own instead of inside the first post-smoothing step (default:
- * from 5e5 rows).
+ * from 5e5 rows); and NS_ROW_UNROLL=2/4, the trip of the 4- and 8-lane row
+ * walks of the sparse products, 16 or 32 entries per trip (default: 32 for
+ * matrices whose mean row is longer than 16 entries).
  * Errors: NS_ERR_WORKSPACE, NS_ERR_HIP. */
 ns_status ns_ctx_bind(ns_ctx* ctx, void* d_workspace, size_t bytes, hipStream_t stream);
 

@@ -377,6 +377,12 @@ constexpr int kProlongPassRows = 500000;
 // contraction-expansion: 500 us with 4 lanes, 545 with 8, 721 with 16)
 constexpr int kSfactLanes = 4;
 
+// trip of the 4- and 8-lane row walks: by mean row length, or as forced at
+// bind (NS_ROW_UNROLL)
+inline int unroll_of(const ns_ctx* c, int64_t nnz, int n) {
+    return c->unroll_mode > 0 ? c->unroll_mode : unroll_for(nnz, n);
+}
+
 template <typename T>
 double dev_norm(ns_ctx* c, int64_t n, const T* x, double* slot, hipStream_t st) {
     norm2<T>(n, x, slot, c->d_red, st, c->d_mapped + kMapNorm);
@@ -649,7 +655,7 @@ struct Nested {
         // against 298 us; the 3x3 A operator is fastest with 16 (487 against
         // 533 us with 8 and 556 us with 4).
         if (M.lanes == 16 && (r0 == 3 || c0 == 3)) M.lanes = c0 == 3 ? 4 : 8;
-        M.unroll = unroll_for(nnzb, N);
+        M.unroll = unroll_of(c, nnzb, N);
         M.xcd = xcd_rows(N, c0 == 3 ? 1 : 3);
         return M;
     }
@@ -663,7 +669,7 @@ struct Nested {
         M.cs = d.cstride;
         M.dextra = Typed<T>::dextra(d);
         M.lanes = lanes_for(d.nnz, d.n, d.bs);
-        M.unroll = unroll_for(d.nnz, d.n);
+        M.unroll = unroll_of(c, d.nnz, d.n);
         M.xcd = xcd_rows(d.n, d.bs);
         return M;
     }
@@ -1094,7 +1100,7 @@ void setup_device(ns_ctx* c, SystemDev& y, hipStream_t st) {
             M.cs = d.cstride;
             M.dextra = d.dextra64;
             M.lanes = lanes_for(d.nnz, d.n, d.bs);
-            M.unroll = unroll_for(d.nnz, d.n);
+            M.unroll = unroll_of(c, d.nnz, d.n);
             smoother_bound_dev(c, M, d.bs, d.dinv64, d.x0, d.r, d.b, bnd + 3 * (h * L + l), ps);
         }
     };
@@ -1503,6 +1509,8 @@ ns_status ns_ctx_bind(ns_ctx* c, void* ws, size_t bytes, hipStream_t st) {
         c->xcd_mode = (xr && (xr[0] == '0' || xr[0] == '1')) ? xr[0] - '0' : -1;
         const char* pp = getenv("NS_PROLONG_PASS");
         c->prolong_mode = (pp && (pp[0] == '0' || pp[0] == '1')) ? pp[0] - '0' : -1;
+        const char* ru = getenv("NS_ROW_UNROLL");
+        c->unroll_mode = (ru && (ru[0] == '2' || ru[0] == '4') && ru[1] == '\0') ? ru[0] - '0' : -1;
         HIPCHK(hipStreamSynchronize(st));
         c->bound = true;
         return NS_OK;

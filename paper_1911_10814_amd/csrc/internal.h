@@ -218,6 +218,7 @@ struct ns_ctx {
     bool use_graphs = true;
     int xcd_mode = -1;           // XCD-contiguous row ranges: -1 by size, 0 off, 1 on
     int prolong_mode = -1;       // finest A prolongation: -1 by size, 0 fused into smoothing, 1 separate pass
+    int unroll_mode = -1;        // 4- and 8-lane row walks: -1 by mean row length, else 2 or 4 (16 or 32 per trip)
     // captured Arnoldi steps, (kind, system, precision, pc_A, pc_I, degrees, cycles_S, j), and
     // set-up chains, (set-up kind, system, 0 ..., chain) -> executable graph
     using GraphKey = std::tuple<int, int, int, int, int, int, int, int, int>;

@@ -40,6 +40,11 @@ def ctx_for(name):
 # XCD row ranges once the gathered vector exceeds 8 MB), forced on the small
 # meshes through the switches the library reads at bind.
 LARGE_PATHS = {"NS_PROLONG_PASS": "1", "NS_XCD_ROWS": "0"}
+# Row walks of 32 entries per trip, which the sparse products take on
+# matrices whose mean row is longer than 16 entries (unstructured meshes,
+# coarse levels), forced on the finest levels too.
+LONG_ROWS = {"NS_ROW_UNROLL": "4"}
+FORCED = {"large_mesh_paths": LARGE_PATHS, "long_row_trips": LONG_ROWS}
 _CTX_FORCED = {}
 
 
@@ -97,9 +102,10 @@ def test_outlet_vectors_and_flow(name):
 
 @pytest.mark.parametrize("name", CASES)
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-13), ("fp32_inner", 2e-6)])
-def test_operators_match_oracle(name, prec, tol):
+@pytest.mark.parametrize("paths", ["by_size", "long_row_trips"])
+def test_operators_match_oracle(name, prec, tol, paths):
     from paper_1911_10814_amd import SolveOptions
-    ctx = ctx_for(name)
+    ctx = ctx_for(name) if paths == "by_size" else ctx_forced(name, FORCED[paths])
     S = get_assembled(name)
     N = ctx.N
     rng = np.random.default_rng(11)
@@ -127,11 +133,11 @@ def test_shat_matches_oracle(name):
 
 
 @pytest.mark.parametrize("name", CASES)
-@pytest.mark.parametrize("paths", ["by_size", "large_mesh_paths"])
+@pytest.mark.parametrize("paths", ["by_size", "large_mesh_paths", "long_row_trips"])
 @pytest.mark.parametrize("scale", [(1.0, 1.0), (1.6, 1.8)])
 def test_vcycles_match_oracle(name, paths, scale):
     from paper_1911_10814_amd import SolveOptions
-    ctx = ctx_for(name) if paths == "by_size" else ctx_forced(name, LARGE_PATHS)
+    ctx = ctx_for(name) if paths == "by_size" else ctx_forced(name, FORCED[paths])
     ns = oracle_solver(name, cc_scale_A=scale[0], cc_scale_S=scale[1])
     o = SolveOptions(cc_scale_A=scale[0], cc_scale_S=scale[1])
     rng = np.random.default_rng(5)
@@ -184,19 +190,21 @@ def test_nested_solve_fp64_replay_and_tolerance(name):
 
 
 @pytest.mark.parametrize("name", ["pipe_tiny", "ybif_small", "conexp_small", "unstr_channel"])
-def test_nested_solve_replay_on_large_mesh_paths(name):
+@pytest.mark.parametrize("paths", ["large_mesh_paths", "long_row_trips"])
+def test_nested_solve_replay_on_large_mesh_paths(name, paths):
     """The whole FP64 nested solve through the kernel paths the large meshes
     take (separate prolongation pass on the finest A level, block SpMVs without
-    XCD row ranges), replayed on the oracle's iteration path."""
+    XCD row ranges) or the long-row walks, replayed on the oracle's iteration
+    path."""
     from paper_1911_10814_amd import SolveOptions
-    ctx = ctx_forced(name, LARGE_PATHS)
+    ctx = ctx_forced(name, FORCED[paths])
     S = get_assembled(name)
     xo, info = oracle_solver(name).solve(S.rhs)
     xg, gi = ctx.solve(ctx._rhs, SolveOptions(schedule=info["schedule"]))
     n3 = 3 * ctx.N
     xg = xg.cpu().numpy()
     ev, ep = rel(xg[:n3], xo[:n3]), rel(xg[n3:], xo[n3:])
-    print(name, "large-mesh paths replay err v", ev, "p", ep, flush=True)
+    print(name, paths, "replay err v", ev, "p", ep, flush=True)
     assert ev <= 1e-10 and ep <= 1e-10
 
 
