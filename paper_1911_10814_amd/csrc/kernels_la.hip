@@ -756,28 +756,58 @@ void backsolve(int k, int ldh, const double* H, const double* g, double* y, hipS
     hipLaunchKernelGGL(k_backsolve, dim3(1), dim3(64), 0, st, k, ldh, H, g, y);
 }
 
+// x (+)= V y over the first k basis vectors: 16-byte packs of V per thread,
+// eight vectors' packs loaded before they are used, each element's sum in FP64
+// in the order of the basis.
+constexpr int kCombineUnroll = 8;
 template <typename T, typename TX>
 __global__ __launch_bounds__(kBlock) void k_combine(int64_t n, int k, const T* __restrict__ V, int64_t ldv,
                                                     const double* __restrict__ y, TX* __restrict__ x, int acc) {
+    constexpr int W = Pk<T>::W;
     __shared__ double ys[256];
-    for (int64_t t0 = (int64_t)blockIdx.x * kBlock; t0 < n; t0 += (int64_t)gridDim.x * kBlock) {
-        const int64_t t = t0 + threadIdx.x;
-        double s = 0.0;
+    const int64_t np = n_packs<T>(n);
+    for (int64_t q0 = (int64_t)blockIdx.x * kBlock; q0 < np; q0 += (int64_t)gridDim.x * kBlock) {
+        const int64_t q = q0 + threadIdx.x;
+        double s[W];
+#pragma unroll
+        for (int e = 0; e < W; ++e) s[e] = 0.0;
         for (int c0 = 0; c0 < k; c0 += 256) {
             const int cnt = min(256, k - c0);
             __syncthreads();
             if ((int)threadIdx.x < cnt) ys[threadIdx.x] = y[c0 + threadIdx.x];
             __syncthreads();
-            if (t < n)
-                for (int i = 0; i < cnt; ++i) s += (double)V[(c0 + i) * ldv + t] * ys[i];
+            if (q < np) {
+                int i = 0;
+                for (; i + kCombineUnroll <= cnt; i += kCombineUnroll) {
+                    Pk<T> v[kCombineUnroll];
+#pragma unroll
+                    for (int u = 0; u < kCombineUnroll; ++u) v[u] = ld_pk(V + (int64_t)(c0 + i + u) * ldv, q, n);
+#pragma unroll
+                    for (int u = 0; u < kCombineUnroll; ++u)
+#pragma unroll
+                        for (int e = 0; e < W; ++e) s[e] += (double)v[u].e[e] * ys[i + u];
+                }
+                for (; i < cnt; ++i) {
+                    const Pk<T> v = ld_pk(V + (int64_t)(c0 + i) * ldv, q, n);
+#pragma unroll
+                    for (int e = 0; e < W; ++e) s[e] += (double)v.e[e] * ys[i];
+                }
+            }
         }
-        if (t < n) x[t] = acc ? (TX)((double)x[t] + s) : (TX)s;
+        if (q < np) {
+#pragma unroll
+            for (int e = 0; e < W; ++e) {
+                const int64_t t = q * W + e;
+                if (t < n) x[t] = acc ? (TX)((double)x[t] + s[e]) : (TX)s[e];
+            }
+        }
     }
 }
 template <typename T, typename TX>
 void combine(int64_t n, int k, const T* V, int64_t ldv, const double* y, TX* x, bool accumulate, hipStream_t st) {
-    hipLaunchKernelGGL((k_combine<T, TX>), dim3(orth_grid(n)), dim3(kBlock), 0, st, n, k, V, ldv, y, x,
-                       accumulate ? 1 : 0);
+    const int64_t blocks = std::min<int64_t>((n_packs<T>(n) + kBlock - 1) / kBlock, 4096);
+    hipLaunchKernelGGL((k_combine<T, TX>), dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(kBlock), 0, st, n,
+                       k, V, ldv, y, x, accumulate ? 1 : 0);
 }
 
 // ||x||: partials, then a one-block finalisation
