@@ -211,15 +211,18 @@ ns_status ns_ctx_create(const ns_mesh* mesh, const ns_ctx_opts* opts, ns_ctx** o
  * Meshes of up to 1024 nodes replay each Krylov step and set-up chain from
  * a HIP graph captured on first use; larger ones launch directly (the
  * environment variable NS_GRAPHS=0 or 1, read here, forces either form).
- * Three more kernel-path choices are made by size and can be forced here
+ * Four more kernel-path choices are made by size and can be forced here
  * the same way (each computes the same sums; used to test every path on small
  * meshes): NS_XCD_ROWS=0/1, block-SpMV rows mapped to one contiguous range
  * per XCD (default: when the gathered vector is <= 8 MB);
  * NS_PROLONG_PASS=0/1, the finest A level's coarse correction added by a
  * pass of its own instead of inside the first post-smoothing step (default:
- * from 5e5 rows); and NS_ROW_UNROLL=2/4, the trip of the 4- and 8-lane row
+ * from 5e5 rows); NS_ROW_UNROLL=2/4, the trip of the 4- and 8-lane row
  * walks of the sparse products, 16 or 32 entries per trip (default: 32 for
- * matrices whose mean row is longer than 16 entries).
+ * matrices whose mean row is longer than 16 entries); and NS_COL16=0, the
+ * finest-level products reading the 32-bit column indices instead of 16-bit
+ * offsets from the row (default: the offsets, whenever every node's
+ * neighbours lie within 32767 of it in the numbering).
  * Errors: NS_ERR_WORKSPACE, NS_ERR_HIP. */
 ns_status ns_ctx_bind(ns_ctx* ctx, void* d_workspace, size_t bytes, hipStream_t stream);
 

@@ -79,6 +79,7 @@ void layout(ns_ctx* c, Arena& A) {
     const int NO = S.n_out;
     c->d_rp = up(A, S.g.rp);
     c->d_col = up(A, S.g.col);
+    c->d_dcol = S.dcol.empty() ? nullptr : up(A, S.dcol);
     c->d_diag = up(A, S.diag_pos);
     c->d_rowof = up(A, S.row_of);
     c->d_tmap = up(A, S.tmap);
@@ -382,6 +383,11 @@ constexpr int kSfactLanes = 4;
 inline int unroll_of(const ns_ctx* c, int64_t nnz, int n) {
     return c->unroll_mode > 0 ? c->unroll_mode : unroll_for(nnz, n);
 }
+// 16-bit column offsets of the node graph for the finest-level products, when
+// the numbering allows them (NS_COL16=0 at bind keeps the 32-bit columns)
+inline const int16_t* dcol_of(const ns_ctx* c) { return c->col16 ? c->d_dcol : nullptr; }
+// bytes of one column index of the node graph as the finest-level products read it
+inline double col_bytes(const ns_ctx* c) { return c->col16 ? 2.0 : 4.0; }
 
 template <typename T>
 double dev_norm(ns_ctx* c, int64_t n, const T* x, double* slot, hipStream_t st) {
@@ -643,6 +649,7 @@ struct Nested {
         M.n = N;
         M.rp = c->d_rp;
         M.col = c->d_col;
+        M.dcol = dcol_of(c);
         M.v = V() + (4 * r0 + c0) * nnzb;
         M.rs = 4 * nnzb;
         M.cs = nnzb;
@@ -664,6 +671,7 @@ struct Nested {
         M.n = d.n;
         M.rp = d.rp;
         M.col = d.col;
+        if (d.col == c->d_col) M.dcol = dcol_of(c);
         M.v = Typed<T>::lv(d);
         M.rs = d.rstride;
         M.cs = d.cstride;
@@ -682,13 +690,15 @@ struct Nested {
     void sfact(const T* x, const int32_t* agg, const T* ec, T* y, T alpha, const T* z, T beta, const T* b,
                const T* dinv, const T* coef, int step, T* d) {
         const double sz = sizeof(T), n = N;
-        double bytes = (double)nnzb * (7 * sz + 8) + 8.0 * (n + 1) + n * sz * (1 + 3 + 4) + n * sz * (4 + 1);
+        double bytes = (double)nnzb * (7 * sz + 2 * col_bytes(c)) + 8.0 * (n + 1) + n * sz * (1 + 3 + 4) +
+                       n * sz * (4 + 1);
         if (coef) bytes += n * sz * (step != 0 ? 4 : 3);
         else if (z) bytes += n * sz;
         if (agg) bytes += n * (4 + sz);
         timed(c, NS_KT_SFACT, bytes, K.st, [&] {
-            shat_factored<T>(N, c->d_rp, c->d_col, V(), nnzb, Typed<T>::dinvA(sy), x, agg, ec, as<T>(c->t_sf), y,
-                             alpha, z, beta, b, dinv, coef, step, d, xcd_rows(N, 1), kSfactLanes, K.st);
+            shat_factored<T>(N, c->d_rp, c->d_col, dcol_of(c), V(), nnzb, Typed<T>::dinvA(sy), x, agg, ec,
+                             as<T>(c->t_sf), y, alpha, z, beta, b, dinv, coef, step, d, xcd_rows(N, 1), kSfactLanes,
+                             K.st);
         });
     }
     RankOne<T> rank_one() const {
@@ -721,7 +731,7 @@ struct Nested {
             outlet_dot<T>(c->sym.n_out, c->d_optr, c->d_onode, Typed<T>::amsk(c), Typed<T>::ck(c), x, as<T>(c->d_s),
                           K.st);
         const double s = sizeof(T);
-        const double bytes = (double)nnzb * (9 * s + 4) + 4.0 * (N + 1) + (rscale ? 9 : 6) * s * N;
+        const double bytes = (double)nnzb * (9 * s + col_bytes(c)) + 4.0 * (N + 1) + (rscale ? 9 : 6) * s * N;
         timed(c, NS_KT_SPMV_A, bytes, K.st, [&] {
             spmv<T>(3, 3, op(0, 0), x, y, T(1), nullptr, T(0), rscale, r.slot_of ? &r : nullptr, K.st, fs);
         });
@@ -753,7 +763,8 @@ struct Nested {
         // algorithmic bytes: matrix values, columns and row pointers once; reads
         // x, b, dinv, the extra diagonal and d (steps after the first); writes d and x
         auto cheb = [&](const T* xi, T* xo, int step, const int32_t* agg, const T* ec) {
-            const double bytes = (double)L.nnz * (9 * sz + 4) + 4.0 * (L.n + 1) + sz * nv * (step != 0 ? 7 : 6);
+            const double cb = l == 0 ? col_bytes(c) : 4.0;
+            const double bytes = (double)L.nnz * (9 * sz + cb) + 4.0 * (L.n + 1) + sz * nv * (step != 0 ? 7 : 6);
             if (tme)
                 timed(c, NS_KT_CHEB_A0, bytes, st,
                       [&] { cheb_step<T>(bs, M, xi, xo, d, b, dinv, coef, step, agg, ec, st); });
@@ -785,7 +796,7 @@ struct Nested {
             // streams), then the restriction
             if (tme) {
                 // same SpMV class as the A operator, plus reads of b and the extra diagonal
-                const double bytes = (double)L.nnz * (9 * sz + 4) + 4.0 * (L.n + 1) + sz * nv * 4;
+                const double bytes = (double)L.nnz * (9 * sz + col_bytes(c)) + 4.0 * (L.n + 1) + sz * nv * 4;
                 timed(c, NS_KT_SPMV_A, bytes, st,
                       [&] { spmv<T>(bs, bs, M, a, as<T>(L.r), T(-1), b, T(1), nullptr, nullptr, st); });
             } else if (sfact) {
@@ -1095,6 +1106,7 @@ void setup_device(ns_ctx* c, SystemDev& y, hipStream_t st) {
             M.n = d.n;
             M.rp = d.rp;
             M.col = d.col;
+            if (d.col == c->d_col) M.dcol = dcol_of(c);
             M.v = d.v64;
             M.rs = d.rstride;
             M.cs = d.cstride;
@@ -1437,6 +1449,7 @@ ns_status ns_ctx_bind(ns_ctx* c, void* ws, size_t bytes, hipStream_t st) {
         const Symbolic& S = c->sym;
         h2d(c->d_rp, S.g.rp, st);
         h2d(c->d_col, S.g.col, st);
+        if (c->d_dcol) h2d(c->d_dcol, S.dcol, st);
         h2d(c->d_diag, S.diag_pos, st);
         h2d(c->d_rowof, S.row_of, st);
         h2d(c->d_tmap, S.tmap, st);
@@ -1509,6 +1522,8 @@ ns_status ns_ctx_bind(ns_ctx* c, void* ws, size_t bytes, hipStream_t st) {
         c->xcd_mode = (xr && (xr[0] == '0' || xr[0] == '1')) ? xr[0] - '0' : -1;
         const char* pp = getenv("NS_PROLONG_PASS");
         c->prolong_mode = (pp && (pp[0] == '0' || pp[0] == '1')) ? pp[0] - '0' : -1;
+        const char* cs16 = getenv("NS_COL16");
+        c->col16 = c->d_dcol != nullptr && !(cs16 && cs16[0] == '0');
         const char* ru = getenv("NS_ROW_UNROLL");
         c->unroll_mode = (ru && (ru[0] == '2' || ru[0] == '4') && ru[1] == '\0') ? ru[0] - '0' : -1;
         HIPCHK(hipStreamSynchronize(st));

@@ -38,6 +38,7 @@ struct BlockOp {
     const T* v = nullptr;
     int64_t rs = 0, cs = 0;
     const T* dextra = nullptr;  // optional extra diagonal [BR*n]
+    const int16_t* dcol = nullptr;  // when set, column of block k of row i is i + dcol[k] (col is not read)
     int lanes = 16;             // lanes per block row (8, 16, 32 or 64), from the mean row length
     int unroll = 2;             // 4- and 8-lane rows: 16 (2) or 32 (4) entries per trip, from the mean row length
     int xcd = 0;                // 1: each XCD takes one contiguous range of rows (xcd_block)
@@ -144,13 +145,15 @@ template <typename T>
 void restrict_first(int nc, int bs, const int32_t* aptr, const int32_t* anodes, const T* r, T* bc, T* xc, T* dc,
                     const T* dinvc, const T* coefc, const T* scale, hipStream_t st);
 // Factored S_hat = D - C diag(A)^{-1} B on the node pattern (V: the 16 value
-// planes; t: [4n] scratch, 16-byte aligned).  With coef == nullptr: y = alpha S_hat xx + beta z;
+// planes; t: [4n] scratch, 16-byte aligned; columns from dcol as in BlockOp
+// when it is set, else from col).  With coef == nullptr: y = alpha S_hat xx + beta z;
 // else one Chebyshev step y = xx + d, d = c1 d + c2 dinv (b - S_hat xx), where
 // xx = x, or x + P ec when agg != nullptr.
 template <typename T>
-void shat_factored(int n, const int32_t* rp, const int32_t* col, const T* V, int64_t nnzb, const T* dinvA, const T* x,
-                   const int32_t* agg, const T* ec, T* t, T* y, T alpha, const T* z, T beta, const T* b,
-                   const T* dinv, const T* coef, int step, T* d, int xcd, int lanes, hipStream_t st);
+void shat_factored(int n, const int32_t* rp, const int32_t* col, const int16_t* dcol, const T* V, int64_t nnzb,
+                   const T* dinvA, const T* x, const int32_t* agg, const T* ec, T* t, T* y, T alpha, const T* z,
+                   T beta, const T* b, const T* dinv, const T* coef, int step, T* d, int xcd, int lanes,
+                   hipStream_t st);
 // bc = P^T (b - M x) in one launch (residual rows summed per aggregate), plus
 // the coarse first Chebyshev step when xc != nullptr (as restrict_first)
 template <typename T>

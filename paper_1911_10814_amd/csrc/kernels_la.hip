@@ -159,32 +159,40 @@ __global__ __launch_bounds__(kBlock) void k_spmv(BlockOp<T> M, const T* __restri
     T acc[BR];
 #pragma unroll
     for (int r = 0; r < BR; ++r) acc[r] = 0;
-    for (int k0 = kb + lane; k0 < ke; k0 += U * W) {
-        int kk[U];
-        bool on[U];
-        trip_blocks<U>(k0, ke, W, kk, on);
-        int j[U];
+    // the column source (16-bit offsets from the row, or 32-bit columns) is
+    // chosen once, outside the walk, so that a trip's loads issue together
+    auto walk = [&](auto column) {
+        for (int k0 = kb + lane; k0 < ke; k0 += U * W) {
+            int kk[U];
+            bool on[U];
+            trip_blocks<U>(k0, ke, W, kk, on);
+            int j[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) j[u] = M.col[kk[u]];
-        T v[U][BR * BC];
+            for (int u = 0; u < U; ++u) j[u] = column(kk[u]);
+            T v[U][BR * BC];
 #pragma unroll
-        for (int u = 0; u < U; ++u)
+            for (int u = 0; u < U; ++u)
 #pragma unroll
-            for (int r = 0; r < BR; ++r)
+                for (int r = 0; r < BR; ++r)
 #pragma unroll
-                for (int c = 0; c < BC; ++c) v[u][r * BC + c] = M.v[r * M.rs + c * M.cs + kk[u]];
-        T xj[U][BC];
+                    for (int c = 0; c < BC; ++c) v[u][r * BC + c] = M.v[r * M.rs + c * M.cs + kk[u]];
+            T xj[U][BC];
 #pragma unroll
-        for (int u = 0; u < U; ++u)
+            for (int u = 0; u < U; ++u)
 #pragma unroll
-            for (int c = 0; c < BC; ++c) xj[u][c] = x[(int64_t)BC * j[u] + c];
+                for (int c = 0; c < BC; ++c) xj[u][c] = x[(int64_t)BC * j[u] + c];
 #pragma unroll
-        for (int u = 0; u < U; ++u)
+            for (int u = 0; u < U; ++u)
 #pragma unroll
-            for (int r = 0; r < BR; ++r)
+                for (int r = 0; r < BR; ++r)
 #pragma unroll
-                for (int c = 0; c < BC; ++c) acc[r] += v[u][r * BC + c] * (on[u] ? xj[u][c] : T(0));
-    }
+                    for (int c = 0; c < BC; ++c) acc[r] += v[u][r * BC + c] * (on[u] ? xj[u][c] : T(0));
+        }
+    };
+    if (M.dcol)
+        walk([&](int k) { return row + (int)M.dcol[k]; });
+    else
+        walk([&](int k) { return M.col[k]; });
 #pragma unroll
     for (int off = W / 2; off > 0; off >>= 1)
 #pragma unroll
@@ -915,41 +923,49 @@ __global__ __launch_bounds__(kBlock) void k_cheb_step(BlockOp<T> M, const T* __r
     T acc[BS];
 #pragma unroll
     for (int r = 0; r < BS; ++r) acc[r] = 0;
-    for (int k0 = kb + lane; k0 < ke; k0 += U * W) {
-        int kk[U];
-        bool on[U];
-        trip_blocks<U>(k0, ke, W, kk, on);
-        int j[U];
+    // the column source (16-bit offsets from the row, or 32-bit columns) is
+    // chosen once, outside the walk, so that a trip's loads issue together
+    auto walk = [&](auto column) {
+        for (int k0 = kb + lane; k0 < ke; k0 += U * W) {
+            int kk[U];
+            bool on[U];
+            trip_blocks<U>(k0, ke, W, kk, on);
+            int j[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) j[u] = M.col[kk[u]];
-        T v[U][BS * BS];
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-#pragma unroll
-            for (int r = 0; r < BS; ++r)
-#pragma unroll
-                for (int c = 0; c < BS; ++c) v[u][r * BS + c] = M.v[r * M.rs + c * M.cs + kk[u]];
-        T xj[U][BS];
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-#pragma unroll
-            for (int c = 0; c < BS; ++c) xj[u][c] = xin[(int64_t)BS * j[u] + c];
-        if (agg) {
-            int J[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) J[u] = agg[j[u]];
+            for (int u = 0; u < U; ++u) j[u] = column(kk[u]);
+            T v[U][BS * BS];
 #pragma unroll
             for (int u = 0; u < U; ++u)
 #pragma unroll
-                for (int c = 0; c < BS; ++c) xj[u][c] += ec[(int64_t)BS * J[u] + c];
+                for (int r = 0; r < BS; ++r)
+#pragma unroll
+                    for (int c = 0; c < BS; ++c) v[u][r * BS + c] = M.v[r * M.rs + c * M.cs + kk[u]];
+            T xj[U][BS];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int c = 0; c < BS; ++c) xj[u][c] = xin[(int64_t)BS * j[u] + c];
+            if (agg) {
+                int J[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) J[u] = agg[j[u]];
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+#pragma unroll
+                    for (int c = 0; c < BS; ++c) xj[u][c] += ec[(int64_t)BS * J[u] + c];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int r = 0; r < BS; ++r)
+#pragma unroll
+                    for (int c = 0; c < BS; ++c) acc[r] += v[u][r * BS + c] * (on[u] ? xj[u][c] : T(0));
         }
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-#pragma unroll
-            for (int r = 0; r < BS; ++r)
-#pragma unroll
-                for (int c = 0; c < BS; ++c) acc[r] += v[u][r * BS + c] * (on[u] ? xj[u][c] : T(0));
-    }
+    };
+    if (M.dcol)
+        walk([&](int k) { return row + (int)M.dcol[k]; });
+    else
+        walk([&](int k) { return M.col[k]; });
 #pragma unroll
     for (int off = W / 2; off > 0; off >>= 1)
 #pragma unroll
@@ -1032,7 +1048,8 @@ __device__ inline Vec4<double> load4(const double* p) {
 
 template <typename T, int W, bool AGG>
 __global__ __launch_bounds__(kBlock) void k_sfact_bt(int n, const int32_t* __restrict__ rp,
-                                                     const int32_t* __restrict__ col, const T* __restrict__ V,
+                                                     const int32_t* __restrict__ col,
+                                                     const int16_t* __restrict__ dcol, const T* __restrict__ V,
                                                      int64_t nnzb, const T* __restrict__ dinvA,
                                                      const T* __restrict__ x, const int32_t* __restrict__ agg,
                                                      const T* __restrict__ ec, T* __restrict__ t4, int xcd) {
@@ -1055,33 +1072,41 @@ __global__ __launch_bounds__(kBlock) void k_sfact_bt(int n, const int32_t* __res
         if (AGG) eco = ec[agg[row]];
     }
     T acc[3] = {0, 0, 0};
-    for (int k0 = kb + lane; k0 < ke; k0 += U * W) {
-        int kk[U];
-        bool on[U];
-        trip_blocks<U>(k0, ke, W, kk, on);
-        int j[U];
+    // the column source (16-bit offsets from the row, or 32-bit columns) is
+    // chosen once, outside the walk, so that a trip's loads issue together
+    auto walk = [&](auto column) {
+        for (int k0 = kb + lane; k0 < ke; k0 += U * W) {
+            int kk[U];
+            bool on[U];
+            trip_blocks<U>(k0, ke, W, kk, on);
+            int j[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) j[u] = col[kk[u]];
-        T v[U][3];
+            for (int u = 0; u < U; ++u) j[u] = column(kk[u]);
+            T v[U][3];
 #pragma unroll
-        for (int u = 0; u < U; ++u)
+            for (int u = 0; u < U; ++u)
 #pragma unroll
-            for (int r = 0; r < 3; ++r) v[u][r] = V[(4 * r + 3) * nnzb + kk[u]];
-        T xj[U];
+                for (int r = 0; r < 3; ++r) v[u][r] = V[(4 * r + 3) * nnzb + kk[u]];
+            T xj[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) xj[u] = x[j[u]];
-        if (AGG) {
-            int J[U];
+            for (int u = 0; u < U; ++u) xj[u] = x[j[u]];
+            if (AGG) {
+                int J[U];
 #pragma unroll
-            for (int u = 0; u < U; ++u) J[u] = agg[j[u]];
+                for (int u = 0; u < U; ++u) J[u] = agg[j[u]];
 #pragma unroll
-            for (int u = 0; u < U; ++u) xj[u] += ec[J[u]];
+                for (int u = 0; u < U; ++u) xj[u] += ec[J[u]];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int r = 0; r < 3; ++r) acc[r] += v[u][r] * (on[u] ? xj[u] : T(0));
         }
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-#pragma unroll
-            for (int r = 0; r < 3; ++r) acc[r] += v[u][r] * (on[u] ? xj[u] : T(0));
-    }
+    };
+    if (dcol)
+        walk([&](int k) { return row + (int)dcol[k]; });
+    else
+        walk([&](int k) { return col[k]; });
 #pragma unroll
     for (int off = W / 2; off > 0; off >>= 1)
 #pragma unroll
@@ -1099,7 +1124,8 @@ __global__ __launch_bounds__(kBlock) void k_sfact_bt(int n, const int32_t* __res
 
 template <typename T, int W>
 __global__ __launch_bounds__(kBlock) void k_sfact_dc(int n, const int32_t* __restrict__ rp,
-                                                     const int32_t* __restrict__ col, const T* __restrict__ V,
+                                                     const int32_t* __restrict__ col,
+                                                     const int16_t* __restrict__ dcol, const T* __restrict__ V,
                                                      int64_t nnzb, const T* __restrict__ t4, T* __restrict__ y,
                                                      T alpha, const T* __restrict__ z, T beta,
                                                      const T* __restrict__ b, const T* __restrict__ dinv,
@@ -1126,32 +1152,40 @@ __global__ __launch_bounds__(kBlock) void k_sfact_dc(int n, const int32_t* __res
         if (step != 0) dprev = d[row];
     }
     T acc = 0;
-    for (int k0 = kb + lane; k0 < ke; k0 += U * W) {
-        int kk[U];
-        bool on[U];
-        trip_blocks<U>(k0, ke, W, kk, on);
-        int j[U];
+    // the column source (16-bit offsets from the row, or 32-bit columns) is
+    // chosen once, outside the walk, so that a trip's loads issue together
+    auto walk = [&](auto column) {
+        for (int k0 = kb + lane; k0 < ke; k0 += U * W) {
+            int kk[U];
+            bool on[U];
+            trip_blocks<U>(k0, ke, W, kk, on);
+            int j[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) j[u] = col[kk[u]];
-        T vd[U], vc[U][3];
+            for (int u = 0; u < U; ++u) j[u] = column(kk[u]);
+            T vd[U], vc[U][3];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            vd[u] = V[15 * nnzb + kk[u]];
+            for (int u = 0; u < U; ++u) {
+                vd[u] = V[15 * nnzb + kk[u]];
 #pragma unroll
-            for (int c = 0; c < 3; ++c) vc[u][c] = V[(12 + c) * nnzb + kk[u]];
+                for (int c = 0; c < 3; ++c) vc[u][c] = V[(12 + c) * nnzb + kk[u]];
+            }
+            Vec4<T> q[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) q[u] = load4(t4 + 4 * (int64_t)j[u]);
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (!on[u]) q[u] = Vec4<T>{0, 0, 0, 0};
+                acc += vd[u] * q[u].d;
+                acc -= vc[u][0] * q[u].a;
+                acc -= vc[u][1] * q[u].b;
+                acc -= vc[u][2] * q[u].c;
+            }
         }
-        Vec4<T> q[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) q[u] = load4(t4 + 4 * (int64_t)j[u]);
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            if (!on[u]) q[u] = Vec4<T>{0, 0, 0, 0};
-            acc += vd[u] * q[u].d;
-            acc -= vc[u][0] * q[u].a;
-            acc -= vc[u][1] * q[u].b;
-            acc -= vc[u][2] * q[u].c;
-        }
-    }
+    };
+    if (dcol)
+        walk([&](int k) { return row + (int)dcol[k]; });
+    else
+        walk([&](int k) { return col[k]; });
 #pragma unroll
     for (int off = W / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, W);
     if (!valid || lane != 0) return;
@@ -1170,21 +1204,22 @@ __global__ __launch_bounds__(kBlock) void k_sfact_dc(int n, const int32_t* __res
 }
 
 template <typename T>
-void shat_factored(int n, const int32_t* rp, const int32_t* col, const T* V, int64_t nnzb, const T* dinvA, const T* x,
-                   const int32_t* agg, const T* ec, T* t, T* y, T alpha, const T* z, T beta, const T* b,
-                   const T* dinv, const T* coef, int step, T* d, int xcd, int lanes, hipStream_t st) {
+void shat_factored(int n, const int32_t* rp, const int32_t* col, const int16_t* dcol, const T* V, int64_t nnzb,
+                   const T* dinvA, const T* x, const int32_t* agg, const T* ec, T* t, T* y, T alpha, const T* z,
+                   T beta, const T* b, const T* dinv, const T* coef, int step, T* d, int xcd, int lanes,
+                   hipStream_t st) {
     if (n <= 0) return;
     auto run = [&](auto w) {
         constexpr int W = decltype(w)::value;
         const dim3 grid(grid_for((int64_t)n * W));
         if (agg)
-            launch_span(k_sfact_bt<T, W, true>, grid, dim3(kBlock), 0, st, true, false, n, rp, col, V, nnzb, dinvA,
-                        x, agg, ec, t, xcd);
+            launch_span(k_sfact_bt<T, W, true>, grid, dim3(kBlock), 0, st, true, false, n, rp, col, dcol, V, nnzb,
+                        dinvA, x, agg, ec, t, xcd);
         else
-            launch_span(k_sfact_bt<T, W, false>, grid, dim3(kBlock), 0, st, true, false, n, rp, col, V, nnzb, dinvA,
-                        x, agg, ec, t, xcd);
-        launch_span(k_sfact_dc<T, W>, grid, dim3(kBlock), 0, st, false, true, n, rp, col, V, nnzb, (const T*)t, y,
-                    alpha, z, beta, b, dinv, coef, step, d, xcd);
+            launch_span(k_sfact_bt<T, W, false>, grid, dim3(kBlock), 0, st, true, false, n, rp, col, dcol, V, nnzb,
+                        dinvA, x, agg, ec, t, xcd);
+        launch_span(k_sfact_dc<T, W>, grid, dim3(kBlock), 0, st, false, true, n, rp, col, dcol, V, nnzb,
+                    (const T*)t, y, alpha, z, beta, b, dinv, coef, step, d, xcd);
     };
     if (lanes == 4) run(std::integral_constant<int, 4>{});
     else if (lanes == 8) run(std::integral_constant<int, 8>{});
@@ -1947,9 +1982,9 @@ void newton_update(int64_t n, double gdt, const double* dx, double* y, double* y
     template void restrict_first<T>(int, int, const int32_t*, const int32_t*, const T*, T*, T*, T*, const T*,         \
                                     const T*, const T*, hipStream_t);                                                 \
     template void restrict_agg<T>(int, int, const int32_t*, const int32_t*, const T*, T*, hipStream_t);              \
-    template void shat_factored<T>(int, const int32_t*, const int32_t*, const T*, int64_t, const T*, const T*,       \
-                                   const int32_t*, const T*, T*, T*, T, const T*, T, const T*, const T*, const T*,   \
-                                   int, T*, int, int, hipStream_t);                                                  \
+    template void shat_factored<T>(int, const int32_t*, const int32_t*, const int16_t*, const T*, int64_t, const T*, \
+                                   const T*, const int32_t*, const T*, T*, T*, T, const T*, T, const T*, const T*,   \
+                                   const T*, int, T*, int, int, hipStream_t);                                        \
     template void resid_restrict<T>(int, const BlockOp<T>&, const T*, const T*, int, const int32_t*, const int32_t*, \
                                     T*, T*, T*, const T*, const T*, const T*, hipStream_t);                          \
     template void prolong_add<T>(int, int, const int32_t*, const T*, T*, hipStream_t);                               \

@@ -174,6 +174,24 @@ std::string build_symbolic(const ns_mesh* m, const ns_ctx_opts& o, Symbolic& S) 
     const Csr& g = S.g;
     const int64_t nnzb = g.nnz();
     if (nnzb >= INT32_MAX) return "too many blocks for 32-bit indices";
+    // column offsets from the row in 16 bits (half the index stream of the
+    // finest-level products) when the node numbering keeps every neighbour
+    // within 32767 of the node
+    {
+        bool fits = true;
+        for (int i = 0; i < N && fits; ++i)
+            for (int k = g.rp[i]; k < g.rp[i + 1]; ++k)
+                if (g.col[k] - i > 32767 || g.col[k] - i < -32767) {
+                    fits = false;
+                    break;
+                }
+        S.dcol.clear();
+        if (fits) {
+            S.dcol.resize(nnzb);
+            for (int i = 0; i < N; ++i)
+                for (int k = g.rp[i]; k < g.rp[i + 1]; ++k) S.dcol[k] = (int16_t)(g.col[k] - i);
+        }
+    }
     S.diag_pos.resize(N);
     S.row_of.resize(nnzb);
     S.tmap.resize(nnzb);

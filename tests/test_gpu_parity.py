@@ -44,7 +44,11 @@ LARGE_PATHS = {"NS_PROLONG_PASS": "1", "NS_XCD_ROWS": "0"}
 # matrices whose mean row is longer than 16 entries (unstructured meshes,
 # coarse levels), forced on the finest levels too.
 LONG_ROWS = {"NS_ROW_UNROLL": "4"}
-FORCED = {"large_mesh_paths": LARGE_PATHS, "long_row_trips": LONG_ROWS}
+# 32-bit column indices in the finest-level products, which meshes whose node
+# numbering puts a neighbour more than 32767 away take (every mesh here fits
+# the 16-bit column offsets).
+COL32 = {"NS_COL16": "0"}
+FORCED = {"large_mesh_paths": LARGE_PATHS, "long_row_trips": LONG_ROWS, "int32_columns": COL32}
 _CTX_FORCED = {}
 
 
@@ -102,7 +106,7 @@ def test_outlet_vectors_and_flow(name):
 
 @pytest.mark.parametrize("name", CASES)
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-13), ("fp32_inner", 2e-6)])
-@pytest.mark.parametrize("paths", ["by_size", "long_row_trips"])
+@pytest.mark.parametrize("paths", ["by_size", "long_row_trips", "int32_columns"])
 def test_operators_match_oracle(name, prec, tol, paths):
     from paper_1911_10814_amd import SolveOptions
     ctx = ctx_for(name) if paths == "by_size" else ctx_forced(name, FORCED[paths])
@@ -133,7 +137,7 @@ def test_shat_matches_oracle(name):
 
 
 @pytest.mark.parametrize("name", CASES)
-@pytest.mark.parametrize("paths", ["by_size", "large_mesh_paths", "long_row_trips"])
+@pytest.mark.parametrize("paths", ["by_size", "large_mesh_paths", "long_row_trips", "int32_columns"])
 @pytest.mark.parametrize("scale", [(1.0, 1.0), (1.6, 1.8)])
 def test_vcycles_match_oracle(name, paths, scale):
     from paper_1911_10814_amd import SolveOptions
@@ -190,7 +194,7 @@ def test_nested_solve_fp64_replay_and_tolerance(name):
 
 
 @pytest.mark.parametrize("name", ["pipe_tiny", "ybif_small", "conexp_small", "unstr_channel"])
-@pytest.mark.parametrize("paths", ["large_mesh_paths", "long_row_trips"])
+@pytest.mark.parametrize("paths", ["large_mesh_paths", "long_row_trips", "int32_columns"])
 def test_nested_solve_replay_on_large_mesh_paths(name, paths):
     """The whole FP64 nested solve through the kernel paths the large meshes
     take (separate prolongation pass on the finest A level, block SpMVs without
