@@ -414,6 +414,13 @@ typedef enum {
     NS_KT_COUNT = 6
 } ns_kernel_class;
 ns_status ns_kernel_timing(ns_ctx* ctx, int32_t mask);
+/* ns_kernel_timing_period(ctx, period): bracket only every period-th launch
+ * of each timed class (1, the default: every launch), counting from this
+ * call; the launches in between run without events, so a long solve is
+ * timed on a sample with a period-th of the events' own cost.  The totals
+ * read back are those of the sampled launches (their count, time and bytes).
+ * Errors: NS_ERR_ARG for period < 1. */
+ns_status ns_kernel_timing_period(ns_ctx* ctx, int32_t period);
 ns_status ns_kernel_timing_read(ns_ctx* ctx, int32_t kclass, double* h_out3);
 
 /* ns_stream_bench: the streaming ceiling of the device, for comparing the

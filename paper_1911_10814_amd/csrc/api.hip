@@ -267,7 +267,7 @@ constexpr size_t kTimingPairs = 65536;
 template <typename F>
 void timed(ns_ctx* c, int cls, double bytes, hipStream_t st, F&& launch) {
     const size_t used = c->kt_pending.size();
-    if (!(c->kt_mask & (1 << cls)) || used >= kTimingPairs) {
+    if (!(c->kt_mask & (1 << cls)) || used >= kTimingPairs || c->kt_seen[cls]++ % (uint64_t)c->kt_period != 0) {
         launch();
         return;
     }
@@ -1860,6 +1860,13 @@ ns_status ns_time_step(ns_ctx* c, const ns_phys* phys, ns_outlet_model* om, cons
 ns_status ns_kernel_timing(ns_ctx* c, int32_t mask) {
     if (!c || mask < 0 || mask >= (1 << NS_KT_COUNT)) return NS_ERR_ARG;
     c->kt_mask = mask;
+    return NS_OK;
+}
+
+ns_status ns_kernel_timing_period(ns_ctx* c, int32_t period) {
+    if (!c || period < 1) return NS_ERR_ARG;
+    c->kt_period = period;
+    for (int i = 0; i < NS_KT_COUNT; ++i) c->kt_seen[i] = 0;
     return NS_OK;
 }
 

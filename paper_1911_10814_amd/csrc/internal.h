@@ -205,6 +205,8 @@ struct ns_ctx {
     bool resistance_mode = false;  // the last assembly took resistance outlets (ns_phys.h_R)
     // kernel timing (HIP event pairs around launches of selected classes)
     int32_t kt_mask = 0;
+    int32_t kt_period = 1;                   // bracket every kt_period-th launch of a timed class
+    uint64_t kt_seen[NS_KT_COUNT] = {};      // launches of each class since the period was set
     std::vector<hipEvent_t> kt_ev;           // pool: 2 events per timed launch
     std::vector<std::pair<int, double>> kt_pending;  // (class, bytes) per used pair
     double kt_acc[NS_KT_COUNT][3] = {{0}};   // per class: launches, ms, bytes

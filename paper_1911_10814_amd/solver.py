@@ -292,11 +292,13 @@ class NsContext:
         out = {k: arrs[k] for k in ("Pi", "P", "Q")}
         return y, ydot, info, out
 
-    def kernel_timing(self, classes=()):
-        """Time launches of the given kernel classes (see ``ns_kernel_class``) in later solves."""
+    def kernel_timing(self, classes=(), period: int = 1):
+        """Time launches of the given kernel classes (see ``ns_kernel_class``) in later solves,
+        every ``period``-th launch of each class."""
         mask = 0
         for k in classes:
             mask |= 1 << _lib.KERNEL_CLASSES[k]
+        self._check(self.lib.ns_kernel_timing_period(self.h, int(period)))
         self._check(self.lib.ns_kernel_timing(self.h, mask))
 
     def kernel_timing_read(self, cls):
