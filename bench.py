@@ -33,6 +33,7 @@ METRIC = "Newton-step solve time @rtol 1e-8, FP32-inner vs FP64; BSR SpMV HBM GB
 HBM_PEAK_GBS = 8000.0
 STREAM_BYTES = 2 << 30  # 2 GiB: far beyond the 256 MB last-level cache
 KT_PERIOD = 4  # kernel classes timed on every 4th launch during the timed steps
+LLC_BYTES = 256e6  # MI355X last-level (Infinity) cache
 
 
 def log(msg):
@@ -334,7 +335,9 @@ def main():
                      "traffic": measured_traffic(dom, args.config),
                      "bytes_per_launch": round(by_l / n_l) if n_l else None, "launches_timed": n_l,
                      "measured_stream_GBps": stream, "frac_of_measured_read": (
-                         round(achieved / stream["read_GBps"], 4) if achieved else None)},
+                         round(achieved / stream["read_GBps"], 4) if achieved else None),
+                     # a launch whose bytes fit the last-level cache is not an HBM figure
+                     "fits_last_level_cache": bool(n_l and by_l / n_l < LLC_BYTES)},
     }
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
