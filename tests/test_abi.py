@@ -139,3 +139,17 @@ def test_entry_points_reject_an_unbound_context_without_a_gpu():
     # context options out of range
     with pytest.raises(NsError, match="coarse_matchings"):
         NsContext(c, coarse_matchings=7)
+
+
+def test_kernel_timing_arguments_are_checked_without_a_gpu():
+    """The timing switches are host-side state: a bad class mask or sampling
+    period is NS_ERR_ARG (-1), valid ones are accepted on an unbound context."""
+    from paper_1911_10814_amd import NsContext, _lib
+    ctx = NsContext(get_case("channel2"))
+    lib = _lib.load()
+    assert lib.ns_kernel_timing_period(ctx.h, 0) == -1
+    assert lib.ns_kernel_timing_period(ctx.h, -3) == -1
+    assert lib.ns_kernel_timing_period(ctx.h, 4) == 0
+    assert lib.ns_kernel_timing(ctx.h, 1 << 6) == -1
+    assert lib.ns_kernel_timing(ctx.h, (1 << 6) - 1) == 0
+    assert lib.ns_kernel_timing(ctx.h, 0) == 0

@@ -438,6 +438,33 @@ def test_failure_statuses():
     _CTX.pop(name, None)
 
 
+def test_sampled_kernel_timing():
+    """Timing brackets every p-th launch of a class and changes nothing in the
+    solve: the same solution bitwise, the sampled launches a p-th of all (to
+    within one), bytes per launch and durations positive."""
+    from paper_1911_10814_amd import SolveOptions
+    name = "conexp_small"
+    ctx = ctx_for(name)
+    o = SolveOptions(precision="fp32_inner", pc_A="jacobi")
+    classes = ("spmv_A", "cgs2", "sfact")
+    x0, _ = ctx.solve(ctx._rhs, o)
+    counts = {}
+    for period in (1, 3):
+        ctx.kernel_timing(classes, period=period)
+        for k in classes:
+            ctx.kernel_timing_read(k)
+        x, _ = ctx.solve(ctx._rhs, o)
+        torch.cuda.synchronize()
+        counts[period] = {k: ctx.kernel_timing_read(k) for k in classes}
+        ctx.kernel_timing(())
+        assert torch.equal(x, x0), period
+    for k in classes:
+        n1, ms1, b1 = counts[1][k]
+        n3, ms3, b3 = counts[3][k]
+        assert n1 > 10 and abs(n3 - n1 / 3) <= 1, (k, n1, n3)
+        assert ms1 > 0 and ms3 > 0 and b1 > 0 and b3 > 0
+
+
 @pytest.mark.parametrize("name", ["channel2", "plate_small"])
 def test_graph_replays_match_eager_launches(monkeypatch, name):
     """The captured graphs (Arnoldi steps and set-up chains) give bitwise the
