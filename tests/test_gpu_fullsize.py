@@ -144,6 +144,52 @@ def test_sampled_tangent_rows_and_residual(full):
     assert np.abs(rg - S.rhs[d]).max() <= 1e-12 * max(np.abs(S.rhs[d]).max(), 1e-300)
 
 
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-13), ("fp32_inner", 1e-5)])
+def test_sampled_operator_rows(full, prec, tol):
+    """The operators of the path at full size, in the launch configuration the
+    solves use (16-bit column offsets, rows without XCD ranges, the lane counts
+    of the large meshes), against the oracle's complete rows at the sampled
+    nodes: 4x4 outer operator with the rank-one term, A = F + K, B, C and D.
+    Each sampled entry within tol of the sum of |T_ij x_j| over its row: FP64
+    rounding, or in FP32 the rounding of values and input (2^-24 each) plus
+    FP32 accumulation over at most ~250 products per row (worst case 1.5e-5,
+    tol 1e-5; measured ~1e-7)."""
+    from paper_1911_10814_amd import SolveOptions
+    case, ctx, S = full.case, full.ctx, full.S
+    N = case.n_nodes
+    n3 = 3 * N
+    x = np.random.default_rng(17).standard_normal(4 * N)
+    o = SolveOptions(precision=prec)
+    d3 = rows_of(full.nodes, N)[:, :3].ravel()
+    dp = full.nodes
+    rank_one = np.zeros(n3)
+    for ak, ck in zip(full.a, S.c):
+        rank_one += ck * ak * (ak @ x[:n3])
+    absK = np.zeros(n3)
+    for ak, ck in zip(full.a, S.c):
+        absK += abs(ck) * np.abs(ak) * (np.abs(ak) @ np.abs(x[:n3]))
+    aAF, aB, aC, aD = (abs(M) for M in (S.A_F, S.B, S.C, S.D))
+    ax = np.abs(x)
+    want = {
+        "A": (S.A_F @ x[:n3] + rank_one, aAF @ ax[:n3] + absK, x[:n3], d3),
+        "B": (S.B @ x[n3:], aB @ ax[n3:], x[n3:], d3),
+        "C": (S.C @ x[:n3], aC @ ax[:n3], x[:n3], dp),
+        "D": (S.D @ x[n3:], aD @ ax[n3:], x[n3:], dp),
+    }
+    worst = {}
+    for op, (ref, scale, xin, rows) in want.items():
+        y = ctx.apply(op, xin, o)[0].cpu().numpy()
+        e = np.abs(y[rows] - ref[rows]) / np.maximum(scale[rows], 1e-300)
+        worst[op] = float(e.max())
+    yf = ctx.apply("full", x, o)[0].cpu().numpy()
+    full_ref = np.concatenate([want["A"][0] + want["B"][0], want["C"][0] + want["D"][0]])
+    full_scale = np.concatenate([want["A"][1] + want["B"][1], want["C"][1] + want["D"][1]])
+    rows4 = rows_of(full.nodes, N).ravel()
+    worst["full"] = float((np.abs(yf[rows4] - full_ref[rows4]) / np.maximum(full_scale[rows4], 1e-300)).max())
+    print(case.name, prec, "sampled operator rows, worst error / row scale", worst, flush=True)
+    assert max(worst.values()) <= tol
+
+
 def _solve_and_check(full, opts, label, with_info=False):
     x, info = full.ctx.solve(full.rhs, opts)
     print(full.case.name, label, {k: info[k] for k in ("outer_iters", "a_iters", "s_iters", "inner_iters",
