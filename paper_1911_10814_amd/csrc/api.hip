@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdlib>
@@ -365,7 +366,9 @@ void read_status(ns_ctx* c, const double* d_status, int n, hipStream_t st) {
 
 // host-mapped scalar slots written by kernels: [0..1] Arnoldi status, [8] norms
 // [9 + kind] initial residual norm of a left GMRES call of that kind
-constexpr int kMapStatus = 0, kMapNorm = 8, kMapNorm0 = 9;
+constexpr int kMapStatus = 0, kMapNorm = 8, kMapNorm0 = 9, kMapSeq = 32;
+// longest poll of a step's status before falling back to the event wait
+constexpr int kStatusPollMs = 50;
 // graph kinds of Arnoldi steps (one mapped initial-norm slot each)
 constexpr int kKindA = 0, kKindS = 1, kKindOuter = 2, kKindShat = 3, kKindInner = 4, kKindSetup = 5;
 // meshes up to this many nodes replay captured graphs by default
@@ -471,6 +474,18 @@ void cgs2_launch(ns_ctx* c, KrylovWs& kw, int64_t n, int j, T* V, hipStream_t st
     ga.g = kw.g;
     ga.status = kw.status;
     ga.hstatus = c->d_mapped + kMapStatus + 2 * slot;
+    // the step number lets the host read the status as soon as the Givens
+    // update has stored it; a captured step would replay a fixed number, so
+    // graphs leave it out and their status is read after the step's event
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    HIPCHK(hipStreamIsCapturing(st, &cs));
+    if (cs == hipStreamCaptureStatusNone) {
+        ga.hseq = reinterpret_cast<unsigned long long*>(c->d_mapped + kMapSeq + slot);
+        ga.seq = ++c->step_seq;
+        c->slot_seq[slot] = ga.seq;
+    } else {
+        c->slot_seq[slot] = 0;
+    }
     // algorithmic bytes of the four kernels with k = j + 1 basis vectors: pass-1
     // dots (k + 1 vectors read), pass-1 update and pass-2 dots (2k + 2 read, 1
     // written; k + 1 read when k <= kOrthFuseMax, single pass), pass-2 update
@@ -485,10 +500,33 @@ void cgs2_launch(ns_ctx* c, KrylovWs& kw, int64_t n, int j, T* V, hipStream_t st
 
 void read_step_status(ns_ctx* c, KrylovWs& kw, hipStream_t st, double& resid, bool& bd, hipEvent_t ev = nullptr,
                       int slot = 0, bool check = true) {
-    if (ev)
-        HIPCHK(hipEventSynchronize(ev));
-    else
-        HIPCHK(hipStreamSynchronize(st));
+    // The step's Givens update stores the status and then its step number in
+    // mapped host memory: poll for the number (the rest of the step's last
+    // kernel keeps running, and later launches queue behind it), for at most
+    // kStatusPollMs, then wait for the step's event or the stream as usual.
+    bool seen = false;
+    const unsigned long long want = c->slot_seq[slot];
+    if (want) {
+        const volatile unsigned long long* hs =
+            reinterpret_cast<const volatile unsigned long long*>(c->h_mapped + kMapSeq + slot);
+        const auto t0 = std::chrono::steady_clock::now();
+        for (unsigned it = 0;; ++it) {
+            if (*hs == want) {
+                seen = true;
+                break;
+            }
+            if ((it & 1023u) == 1023u &&
+                std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(kStatusPollMs))
+                break;
+        }
+        std::atomic_thread_fence(std::memory_order_acquire);
+    }
+    if (!seen) {
+        if (ev)
+            HIPCHK(hipEventSynchronize(ev));
+        else
+            HIPCHK(hipStreamSynchronize(st));
+    }
     const volatile double* h = c->h_mapped + kMapStatus + 2 * slot;
     resid = h[0];
     bd = h[1] != 0.0;
@@ -1501,7 +1539,11 @@ ns_status ns_ctx_bind(ns_ctx* c, void* ws, size_t bytes, hipStream_t st) {
             HIPCHK(hipHostMalloc((void**)&c->h_mapped, 64 * sizeof(double),
                                  hipHostMallocMapped | hipHostMallocCoherent));
             HIPCHK(hipHostGetDevicePointer((void**)&c->d_mapped, c->h_mapped, 0));
+            std::memset(c->h_mapped, 0, 64 * sizeof(double));
         }
+        c->step_seq = 0;
+        c->slot_seq[0] = c->slot_seq[1] = 0;
+        std::memset(c->h_mapped + kMapSeq, 0, 2 * sizeof(double));
         if (!c->own) HIPCHK(hipStreamCreateWithFlags(&c->own, hipStreamNonBlocking));
         // the scratch of ns_resistance_gradient_noalloc on this device
         HIPCHK(noalloc_scratch(c->device, &c->noalloc_scratch));

@@ -195,6 +195,8 @@ struct ns_ctx {
     double* h_pinned = nullptr;  // pinned host scalars
     double* h_mapped = nullptr;  // pinned, device-mapped host scalars written by kernels
     double* d_mapped = nullptr;  // device address of h_mapped
+    unsigned long long step_seq = 0;     // numbers the Arnoldi steps whose status the host reads
+    unsigned long long slot_seq[2] = {};  // step number expected in each status slot (0: wait for the stream)
     std::vector<double> h_xyz;   // host copies uploaded by ns_ctx_bind
     std::vector<uint8_t> h_mask;
     uint64_t version = 0;        // incremented by every assembly

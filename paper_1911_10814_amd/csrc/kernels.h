@@ -106,6 +106,11 @@ struct GivensArgs {
     const double* h2 = nullptr;
     double *H = nullptr, *cs = nullptr, *sn = nullptr, *g = nullptr, *status = nullptr;
     double* hstatus = nullptr;  // optional host-mapped copy of status[0..1]
+    // optional host-mapped step number, stored (system-scope release) after
+    // hstatus, so that the host can see the step's status without waiting for
+    // the end of the kernel
+    unsigned long long* hseq = nullptr;
+    unsigned long long seq = 0;
 };
 template <typename T>
 void arnoldi_cgs2(int64_t n, int j, const T* V, int64_t ldv, T* w, double* h1, double* h2, const GivensArgs& ga,

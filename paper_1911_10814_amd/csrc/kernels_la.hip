@@ -547,6 +547,7 @@ __device__ void givens_step(const GivensArgs& a, double hn2) {
         a.hstatus[0] = a.status[0];
         a.hstatus[1] = a.status[1];
     }
+    if (a.hseq) __hip_atomic_store(a.hseq, a.seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 inline unsigned orth_grid(int64_t n) {
