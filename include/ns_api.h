@@ -211,7 +211,7 @@ ns_status ns_ctx_create(const ns_mesh* mesh, const ns_ctx_opts* opts, ns_ctx** o
  * Meshes of up to 1024 nodes replay each Krylov step and set-up chain from
  * a HIP graph captured on first use; larger ones launch directly (the
  * environment variable NS_GRAPHS=0 or 1, read here, forces either form).
- * Four more kernel-path choices are made by size and can be forced here
+ * Five more kernel-path choices are made by size and can be forced here
  * the same way (each computes the same sums; used to test every path on small
  * meshes): NS_XCD_ROWS=0/1, block-SpMV rows mapped to one contiguous range
  * per XCD (default: when the gathered vector is <= 8 MB);
@@ -222,7 +222,12 @@ ns_status ns_ctx_create(const ns_mesh* mesh, const ns_ctx_opts* opts, ns_ctx** o
  * matrices whose mean row is longer than 16 entries); and NS_COL16=0, the
  * finest-level products reading the 32-bit column indices instead of 16-bit
  * offsets from the row (default: the offsets, whenever every node's
- * neighbours lie within 32767 of it in the numbering).
+ * neighbours lie within 32767 of it in the numbering); and NS_ELL=0, the
+ * FP32 tangent planes kept in the node graph's row layout instead of
+ * fixed-width rows (default: fixed-width rows of the longest row's length,
+ * padded with zero blocks, whenever the 16-bit offsets apply and no row is
+ * longer than 16 blocks; the padding adds only exact zeros, so the results
+ * are the same bit for bit).
  * Errors: NS_ERR_WORKSPACE, NS_ERR_HIP. */
 ns_status ns_ctx_bind(ns_ctx* ctx, void* d_workspace, size_t bytes, hipStream_t stream);
 

@@ -81,6 +81,7 @@ void layout(ns_ctx* c, Arena& A) {
     c->d_rp = up(A, S.g.rp);
     c->d_col = up(A, S.g.col);
     c->d_dcol = S.dcol.empty() ? nullptr : up(A, S.dcol);
+    c->d_dcol_ell = S.dcol_ell.empty() ? nullptr : up(A, S.dcol_ell);
     c->d_diag = up(A, S.diag_pos);
     c->d_rowof = up(A, S.row_of);
     c->d_tmap = up(A, S.tmap);
@@ -168,7 +169,8 @@ void layout(ns_ctx* c, Arena& A) {
     for (int s = 0; s < 2; ++s) {
         SystemDev& y = c->sys[s];
         y.V64 = A.take<double>((size_t)nnzb * 16);
-        y.V32 = A.take<float>((size_t)nnzb * 16);
+        // FP32 planes: the node graph's layout or the fixed-width rows (chosen at bind)
+        y.V32 = A.take<float>((size_t)std::max<int64_t>(nnzb, (int64_t)N * S.ell) * 16);
         y.dK64 = A.take<double>((size_t)N * 3);
         y.diagA64 = A.take<double>((size_t)N * 3);
         y.dinvA64 = A.take<double>((size_t)N * 3);
@@ -674,6 +676,12 @@ struct Nested {
     Nested(Ctl& k) : K(k), c(k.c), sy(*k.sy), N(k.c->sym.N), nnzb(k.c->sym.g.nnz()) {}
 
     const T* V() const { return Typed<T>::V(sy); }
+    // FP32 planes in the fixed-width row layout (chosen at bind): plane
+    // stride N*ell, slot l of row i at i*ell + l, columns as 16-bit offsets
+    bool ell_planes() const { return sizeof(T) == 4 && c->ell32; }
+    int ell() const { return ell_planes() ? c->sym.ell : 0; }
+    int64_t plane() const { return ell_planes() ? (int64_t)N * c->sym.ell : nnzb; }
+    const int16_t* dcol_planes() const { return ell_planes() ? c->d_dcol_ell : dcol_of(c); }
     // XCD-contiguous row ranges pay while a row range's share of the gathered
     // vector stays L2-resident: on when the gathered vector (n*bc values) is
     // at most kXcdMaxXBytes (measured: +15 % on the 2e5-node pipe, -5 % on the
@@ -687,10 +695,11 @@ struct Nested {
         M.n = N;
         M.rp = c->d_rp;
         M.col = c->d_col;
-        M.dcol = dcol_of(c);
-        M.v = V() + (4 * r0 + c0) * nnzb;
-        M.rs = 4 * nnzb;
-        M.cs = nnzb;
+        M.dcol = dcol_planes();
+        M.ell = ell();
+        M.v = V() + (4 * r0 + c0) * plane();
+        M.rs = 4 * plane();
+        M.cs = plane();
         M.lanes = lanes_for(nnzb, N, 3);
         // The thin operators move fewer bytes per block, so fewer lanes per
         // row (more rows, more loads in flight per wave) pay: C (3 values and a
@@ -713,6 +722,12 @@ struct Nested {
         M.v = Typed<T>::lv(d);
         M.rs = d.rstride;
         M.cs = d.cstride;
+        if (M.v == V()) {  // the finest A level shares the operator's planes
+            M.dcol = dcol_planes();
+            M.ell = ell();
+            M.rs = 4 * plane();
+            M.cs = plane();
+        }
         M.dextra = Typed<T>::dextra(d);
         M.lanes = lanes_for(d.nnz, d.n, d.bs);
         M.unroll = unroll_of(c, d.nnz, d.n);
@@ -734,9 +749,9 @@ struct Nested {
         else if (z) bytes += n * sz;
         if (agg) bytes += n * (4 + sz);
         timed(c, NS_KT_SFACT, bytes, K.st, [&] {
-            shat_factored<T>(N, c->d_rp, c->d_col, dcol_of(c), V(), nnzb, Typed<T>::dinvA(sy), x, agg, ec,
-                             as<T>(c->t_sf), y, alpha, z, beta, b, dinv, coef, step, d, xcd_rows(N, 1), kSfactLanes,
-                             K.st);
+            shat_factored<T>(N, c->d_rp, c->d_col, dcol_planes(), ell(), V(), plane(), Typed<T>::dinvA(sy), x,
+                             agg, ec, as<T>(c->t_sf), y, alpha, z, beta, b, dinv, coef, step, d, xcd_rows(N, 1),
+                             kSfactLanes, K.st);
         });
     }
     RankOne<T> rank_one() const {
@@ -1256,7 +1271,10 @@ void convert32(ns_ctx* c, SystemDev& y, hipStream_t st) {
     const int N = S.N;
     const int64_t nnzb = S.g.nnz();
     const int L = (int)S.lv.size();
-    convert<double, float>(nnzb * 16, y.V64, y.V32, st);
+    if (c->ell32)
+        to_ell<double, float>(N, S.ell, c->d_rp, y.V64, nnzb, 16, y.V32, st);
+    else
+        convert<double, float>(nnzb * 16, y.V64, y.V32, st);
     convert<double, float>(3 * (int64_t)N, y.dK64, y.dK32, st);
     convert<double, float>(3 * (int64_t)N, y.dinvA64, y.dinvA32, st);
     convert<double, float>(S.shat.nnz(), y.shat64, y.shat32, st);
@@ -1488,6 +1506,7 @@ ns_status ns_ctx_bind(ns_ctx* c, void* ws, size_t bytes, hipStream_t st) {
         h2d(c->d_rp, S.g.rp, st);
         h2d(c->d_col, S.g.col, st);
         if (c->d_dcol) h2d(c->d_dcol, S.dcol, st);
+        if (c->d_dcol_ell) h2d(c->d_dcol_ell, S.dcol_ell, st);
         h2d(c->d_diag, S.diag_pos, st);
         h2d(c->d_rowof, S.row_of, st);
         h2d(c->d_tmap, S.tmap, st);
@@ -1566,6 +1585,8 @@ ns_status ns_ctx_bind(ns_ctx* c, void* ws, size_t bytes, hipStream_t st) {
         c->prolong_mode = (pp && (pp[0] == '0' || pp[0] == '1')) ? pp[0] - '0' : -1;
         const char* cs16 = getenv("NS_COL16");
         c->col16 = c->d_dcol != nullptr && !(cs16 && cs16[0] == '0');
+        const char* ce = getenv("NS_ELL");
+        c->ell32 = c->col16 && c->d_dcol_ell != nullptr && !(ce && ce[0] == '0');
         const char* ru = getenv("NS_ROW_UNROLL");
         c->unroll_mode = (ru && (ru[0] == '2' || ru[0] == '4') && ru[1] == '\0') ? ru[0] - '0' : -1;
         HIPCHK(hipStreamSynchronize(st));
@@ -2047,8 +2068,8 @@ ns_status ns_apply(ns_ctx* c, int32_t op, const ns_solve_opts* opts, const doubl
                     if (r.slot_of)
                         outlet_dot<T>(c->sym.n_out, c->d_optr, c->d_onode, Typed<T>::amsk(c), Typed<T>::ck(c), x,
                                       as<T>(c->d_s), st);
-                    spmv_full<T>(N, c->d_rp, c->d_col, P.V(), c->sym.g.nnz(), x, y, T(1), nullptr, T(0),
-                                 r.slot_of ? &r : nullptr, st);
+                    spmv_full<T>(N, c->d_rp, c->d_col, P.V(), P.plane(), x, y, T(1), nullptr, T(0),
+                                 r.slot_of ? &r : nullptr, st, P.ell(), P.dcol_planes());
                     break;
                 }
                 case NS_OP_A: P.applyA(x, y); break;

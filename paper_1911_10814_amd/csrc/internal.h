@@ -41,6 +41,11 @@ struct Symbolic {
     int N = 0, E = 0, n_out = 0, F = 0;
     Csr g;                               // node graph = BSR pattern
     std::vector<int16_t> dcol;           // [nnzb] col - row when every |col - row| <= 32767, else empty
+    // fixed-width rows for the FP32 planes: ell = the longest row (<= 16, and
+    // dcol available), row i's blocks at i*ell + l, padded with zero blocks
+    // whose offset is 0; 0 when the pattern does not allow it
+    int ell = 0;
+    std::vector<int16_t> dcol_ell;       // [N*ell] column offsets in that layout
     std::vector<int32_t> diag_pos;       // [N]
     std::vector<int32_t> row_of;         // [nnzb]
     std::vector<int32_t> tmap;           // [nnzb] index of the transposed block
@@ -160,6 +165,7 @@ struct ns_ctx {
     // device copies of the symbolic data
     int32_t *d_rp = nullptr, *d_col = nullptr, *d_diag = nullptr, *d_rowof = nullptr, *d_tmap = nullptr;
     int16_t* d_dcol = nullptr;   // 16-bit column offsets of the node graph (null when they do not fit)
+    int16_t* d_dcol_ell = nullptr;  // the same in the fixed-width row layout (null without one)
     int32_t *d_tets = nullptr, *d_emap = nullptr;
     int32_t *d_faces = nullptr, *d_fmap = nullptr, *d_fslot = nullptr, *d_face_out = nullptr;
     int32_t *d_onode = nullptr, *d_oid = nullptr, *d_slot_of = nullptr, *d_optr = nullptr;
@@ -226,6 +232,7 @@ struct ns_ctx {
     int prolong_mode = -1;       // finest A prolongation: -1 by size, 0 fused into smoothing, 1 separate pass
     int unroll_mode = -1;        // 4- and 8-lane row walks: -1 by mean row length, else 2 or 4 (16 or 32 per trip)
     bool col16 = false;          // finest-level products read the 16-bit column offsets
+    bool ell32 = false;          // the FP32 tangent planes are stored in the fixed-width row layout
     // captured Arnoldi steps, (kind, system, precision, pc_A, pc_I, degrees, cycles_S, j), and
     // set-up chains, (set-up kind, system, 0 ..., chain) -> executable graph
     using GraphKey = std::tuple<int, int, int, int, int, int, int, int, int>;

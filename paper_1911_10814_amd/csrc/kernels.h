@@ -39,6 +39,7 @@ struct BlockOp {
     int64_t rs = 0, cs = 0;
     const T* dextra = nullptr;  // optional extra diagonal [BR*n]
     const int16_t* dcol = nullptr;  // when set, column of block k of row i is i + dcol[k] (col is not read)
+    int ell = 0;  // > 0: fixed-width rows, row i's blocks at i*ell + l (l < ell; zero blocks pad), rp not read
     int lanes = 16;             // lanes per block row (8, 16, 32 or 64), from the mean row length
     int unroll = 2;             // 4- and 8-lane rows: 16 (2) or 32 (4) entries per trip, from the mean row length
     int xcd = 0;                // 1: each XCD takes one contiguous range of rows (xcd_block)
@@ -75,7 +76,8 @@ void spmv(int br, int bc, const BlockOp<T>& M, const T* x, T* y, T alpha, const 
 // Full 4x4 field-split operator: y = alpha [A B; C D] x + beta z.
 template <typename T>
 void spmv_full(int n, const int32_t* rp, const int32_t* col, const T* V, int64_t nnzb, const T* x, T* y,
-               T alpha, const T* z, T beta, const RankOne<T>* ro, hipStream_t st);
+               T alpha, const T* z, T beta, const RankOne<T>* ro, hipStream_t st, int ell = 0,
+               const int16_t* dcol_ell = nullptr);
 
 // s[k] = c[k] * sum_{slots of k} a . x
 template <typename T>
@@ -155,10 +157,15 @@ void restrict_first(int nc, int bs, const int32_t* aptr, const int32_t* anodes, 
 // else one Chebyshev step y = xx + d, d = c1 d + c2 dinv (b - S_hat xx), where
 // xx = x, or x + P ec when agg != nullptr.
 template <typename T>
-void shat_factored(int n, const int32_t* rp, const int32_t* col, const int16_t* dcol, const T* V, int64_t nnzb,
-                   const T* dinvA, const T* x, const int32_t* agg, const T* ec, T* t, T* y, T alpha, const T* z,
-                   T beta, const T* b, const T* dinv, const T* coef, int step, T* d, int xcd, int lanes,
+void shat_factored(int n, const int32_t* rp, const int32_t* col, const int16_t* dcol, int ell, const T* V,
+                   int64_t nnzb, const T* dinvA, const T* x, const int32_t* agg, const T* ec, T* t, T* y, T alpha,
+                   const T* z, T beta, const T* b, const T* dinv, const T* coef, int step, T* d, int xcd, int lanes,
                    hipStream_t st);
+// Planes of a node-graph matrix (p planes of nnzb values, row pointers rp)
+// converted into the fixed-width row layout (p planes of n*ell values, row
+// i's blocks at i*ell + l, zero past the row's end).
+template <typename Tin, typename Tout>
+void to_ell(int n, int ell, const int32_t* rp, const Tin* src, int64_t nnzb, int planes, Tout* dst, hipStream_t st);
 // bc = P^T (b - M x) in one launch (residual rows summed per aggregate), plus
 // the coarse first Chebyshev step when xc != nullptr (as restrict_first)
 template <typename T>

@@ -139,8 +139,13 @@ __global__ __launch_bounds__(kBlock) void k_spmv(BlockOp<T> M, const T* __restri
     // term's dependent loads follow the loop.
     int kb = 0, ke = 0;
     if (valid) {
-        kb = M.rp[row];
-        ke = M.rp[row + 1];
+        if (M.ell) {
+            kb = row * M.ell;
+            ke = kb + M.ell;
+        } else {
+            kb = M.rp[row];
+            ke = M.rp[row + 1];
+        }
     }
     const bool out_lane = valid && lane < BR;
     const int64_t i = (int64_t)BR * row + lane;
@@ -263,6 +268,7 @@ void spmv(int br, int bc, const BlockOp<T>& M, const T* x, T* y, T alpha, const 
     RankOne<T> r1 = ro ? *ro : RankOne<T>{};
     FirstStep<T> fs = fsp ? *fsp : FirstStep<T>{};
     if (M.n <= 0) return;
+    if (M.ell && !M.dcol) throw std::runtime_error("spmv: fixed-width rows need their column offsets");
     if (br == 3 && bc == 3)
         spmv_w<T, 3, 3>(M, x, y, alpha, z, beta, rscale, r1, fs, st);
     else if (br == 3 && bc == 1)
@@ -278,7 +284,8 @@ template <typename T, int W>
 __global__ __launch_bounds__(kBlock) void k_spmv_full(int n, const int32_t* __restrict__ rp,
                                                       const int32_t* __restrict__ col, const T* __restrict__ V,
                                                       int64_t nnzb, const T* __restrict__ x, T* __restrict__ y,
-                                                      T alpha, const T* __restrict__ z, T beta, RankOne<T> ro) {
+                                                      T alpha, const T* __restrict__ z, T beta, RankOne<T> ro,
+                                                      int ell, const int16_t* __restrict__ dcol) {
     const int64_t tid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const int row = (int)(tid / W);
     const int lane = threadIdx.x % W;
@@ -296,9 +303,10 @@ __global__ __launch_bounds__(kBlock) void k_spmv_full(int n, const int32_t* __re
     }
     T acc[4] = {0, 0, 0, 0};
     if (valid) {
-        const int k1 = rp[row + 1];
-        for (int k = rp[row] + lane; k < k1; k += W) {
-            const int j = col[k];
+        const int k0 = ell ? row * ell : rp[row];
+        const int k1 = ell ? k0 + ell : rp[row + 1];
+        for (int k = k0 + lane; k < k1; k += W) {
+            const int j = ell ? row + dcol[k] : col[k];
             T xj[4] = {x[3 * (int64_t)j], x[3 * (int64_t)j + 1], x[3 * (int64_t)j + 2], xp[j]};
 #pragma unroll
             for (int r = 0; r < 4; ++r)
@@ -323,11 +331,37 @@ __global__ __launch_bounds__(kBlock) void k_spmv_full(int n, const int32_t* __re
 
 template <typename T>
 void spmv_full(int n, const int32_t* rp, const int32_t* col, const T* V, int64_t nnzb, const T* x, T* y, T alpha,
-               const T* z, T beta, const RankOne<T>* ro, hipStream_t st) {
+               const T* z, T beta, const RankOne<T>* ro, hipStream_t st, int ell, const int16_t* dcol_ell) {
     RankOne<T> r1 = ro ? *ro : RankOne<T>{};
+    if (ell && !dcol_ell) throw std::runtime_error("spmv_full: fixed-width rows need their column offsets");
     launch_timed(k_spmv_full<T, 16>, dim3(grid_for((int64_t)n * 16)), dim3(kBlock), st, n, rp, col, V, nnzb, x, y,
-                 alpha, z, beta, r1);
+                 alpha, z, beta, r1, ell, dcol_ell);
 }
+
+// Fixed-width row layout: thread (row, l) copies slot l of the row from every
+// plane, writing zero past the row's end.
+template <typename Tin, typename Tout>
+__global__ __launch_bounds__(kBlock) void k_to_ell(int n, int ell, const int32_t* __restrict__ rp,
+                                                   const Tin* __restrict__ src, int64_t nnzb, int planes,
+                                                   Tout* __restrict__ dst) {
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t total = (int64_t)n * ell;
+    if (t >= total) return;
+    const int row = (int)(t / ell);
+    const int l = (int)(t - (int64_t)row * ell);
+    const int k = rp[row] + l;
+    const bool in = k < rp[row + 1];
+    for (int p = 0; p < planes; ++p) dst[p * total + t] = in ? (Tout)src[p * nnzb + k] : Tout(0);
+}
+
+template <typename Tin, typename Tout>
+void to_ell(int n, int ell, const int32_t* rp, const Tin* src, int64_t nnzb, int planes, Tout* dst, hipStream_t st) {
+    const int64_t total = (int64_t)n * ell;
+    if (total <= 0) return;
+    hipLaunchKernelGGL((k_to_ell<Tin, Tout>), dim3(grid_for(total)), dim3(kBlock), 0, st, n, ell, rp, src, nnzb,
+                       planes, dst);
+}
+template void to_ell<double, float>(int, int, const int32_t*, const double*, int64_t, int, float*, hipStream_t);
 
 // s[k] = c[k] * sum over outlet k's slots of a . x   (one block per outlet)
 template <typename T>
@@ -909,8 +943,13 @@ __global__ __launch_bounds__(kBlock) void k_cheb_step(BlockOp<T> M, const T* __r
     int ag = 0, kb = 0, ke = 0;
     if (out_lane && agg) ag = agg[row];
     if (valid) {
-        kb = M.rp[row];
-        ke = M.rp[row + 1];
+        if (M.ell) {
+            kb = row * M.ell;
+            ke = kb + M.ell;
+        } else {
+            kb = M.rp[row];
+            ke = M.rp[row + 1];
+        }
     }
     T xi = 0, eci = 0, ex = 0, bi = 0, dvi = 0, dprev = 0;
     if (out_lane) {
@@ -1016,6 +1055,7 @@ void cheb_step_w(const BlockOp<T>& M, const T* xin, T* xout, T* d, const T* b, c
 template <typename T>
 void cheb_step(int bs, const BlockOp<T>& M, const T* xin, T* xout, T* d, const T* b, const T* dinv, const T* coef,
                int step, const int32_t* agg, const T* ec, hipStream_t st) {
+    if (M.ell && !M.dcol) throw std::runtime_error("cheb_step: fixed-width rows need their column offsets");
     if (bs == 3)
         cheb_step_w<T, 3>(M, xin, xout, d, b, dinv, coef, step, agg, ec, st);
     else
@@ -1050,7 +1090,8 @@ __device__ inline Vec4<double> load4(const double* p) {
 template <typename T, int W, bool AGG>
 __global__ __launch_bounds__(kBlock) void k_sfact_bt(int n, const int32_t* __restrict__ rp,
                                                      const int32_t* __restrict__ col,
-                                                     const int16_t* __restrict__ dcol, const T* __restrict__ V,
+                                                     const int16_t* __restrict__ dcol, int ell,
+                                                     const T* __restrict__ V,
                                                      int64_t nnzb, const T* __restrict__ dinvA,
                                                      const T* __restrict__ x, const int32_t* __restrict__ agg,
                                                      const T* __restrict__ ec, T* __restrict__ t4, int xcd) {
@@ -1061,8 +1102,13 @@ __global__ __launch_bounds__(kBlock) void k_sfact_bt(int n, const int32_t* __res
     const bool valid = row < n;
     int kb = 0, ke = 0;
     if (valid) {
-        kb = rp[row];
-        ke = rp[row + 1];
+        if (ell) {
+            kb = row * ell;
+            ke = kb + ell;
+        } else {
+            kb = rp[row];
+            ke = rp[row + 1];
+        }
     }
     // own-row operands, loaded ahead of the row loop: diag(A)^{-1} on lanes
     // 0-2, the row's xx on lane 3
@@ -1126,7 +1172,8 @@ __global__ __launch_bounds__(kBlock) void k_sfact_bt(int n, const int32_t* __res
 template <typename T, int W>
 __global__ __launch_bounds__(kBlock) void k_sfact_dc(int n, const int32_t* __restrict__ rp,
                                                      const int32_t* __restrict__ col,
-                                                     const int16_t* __restrict__ dcol, const T* __restrict__ V,
+                                                     const int16_t* __restrict__ dcol, int ell,
+                                                     const T* __restrict__ V,
                                                      int64_t nnzb, const T* __restrict__ t4, T* __restrict__ y,
                                                      T alpha, const T* __restrict__ z, T beta,
                                                      const T* __restrict__ b, const T* __restrict__ dinv,
@@ -1141,8 +1188,13 @@ __global__ __launch_bounds__(kBlock) void k_sfact_dc(int n, const int32_t* __res
     const bool smooth_lane = valid && lane == 0 && coef;
     int kb = 0, ke = 0;
     if (valid) {
-        kb = rp[row];
-        ke = rp[row + 1];
+        if (ell) {
+            kb = row * ell;
+            ke = kb + ell;
+        } else {
+            kb = rp[row];
+            ke = rp[row + 1];
+        }
     }
     T zi = 0, xi = 0, bi = 0, dvi = 0, dprev = 0;
     if (valid && lane == 0 && !coef && z) zi = z[row];
@@ -1205,21 +1257,22 @@ __global__ __launch_bounds__(kBlock) void k_sfact_dc(int n, const int32_t* __res
 }
 
 template <typename T>
-void shat_factored(int n, const int32_t* rp, const int32_t* col, const int16_t* dcol, const T* V, int64_t nnzb,
-                   const T* dinvA, const T* x, const int32_t* agg, const T* ec, T* t, T* y, T alpha, const T* z,
-                   T beta, const T* b, const T* dinv, const T* coef, int step, T* d, int xcd, int lanes,
+void shat_factored(int n, const int32_t* rp, const int32_t* col, const int16_t* dcol, int ell, const T* V,
+                   int64_t nnzb, const T* dinvA, const T* x, const int32_t* agg, const T* ec, T* t, T* y, T alpha,
+                   const T* z, T beta, const T* b, const T* dinv, const T* coef, int step, T* d, int xcd, int lanes,
                    hipStream_t st) {
     if (n <= 0) return;
+    if (ell && !dcol) throw std::runtime_error("shat_factored: fixed-width rows need their column offsets");
     auto run = [&](auto w) {
         constexpr int W = decltype(w)::value;
         const dim3 grid(grid_for((int64_t)n * W));
         if (agg)
-            launch_span(k_sfact_bt<T, W, true>, grid, dim3(kBlock), 0, st, true, false, n, rp, col, dcol, V, nnzb,
-                        dinvA, x, agg, ec, t, xcd);
+            launch_span(k_sfact_bt<T, W, true>, grid, dim3(kBlock), 0, st, true, false, n, rp, col, dcol, ell, V,
+                        nnzb, dinvA, x, agg, ec, t, xcd);
         else
-            launch_span(k_sfact_bt<T, W, false>, grid, dim3(kBlock), 0, st, true, false, n, rp, col, dcol, V, nnzb,
-                        dinvA, x, agg, ec, t, xcd);
-        launch_span(k_sfact_dc<T, W>, grid, dim3(kBlock), 0, st, false, true, n, rp, col, dcol, V, nnzb,
+            launch_span(k_sfact_bt<T, W, false>, grid, dim3(kBlock), 0, st, true, false, n, rp, col, dcol, ell, V,
+                        nnzb, dinvA, x, agg, ec, t, xcd);
+        launch_span(k_sfact_dc<T, W>, grid, dim3(kBlock), 0, st, false, true, n, rp, col, dcol, ell, V, nnzb,
                     (const T*)t, y, alpha, z, beta, b, dinv, coef, step, d, xcd);
     };
     if (lanes == 4) run(std::integral_constant<int, 4>{});
@@ -1334,6 +1387,7 @@ void resid_restrict(int bs, const BlockOp<T>& M, const T* x, const T* b, int nc,
                     const int32_t* anodes, T* bc, T* xc, T* dc, const T* dinvc, const T* coefc, const T* scale,
                     hipStream_t st) {
     if (nc <= 0) return;
+    if (M.ell) throw std::runtime_error("resid_restrict: walks the node-graph row layout only");
     const dim3 grid(grid_for((int64_t)nc * 64));
     if (bs == 3)
         hipLaunchKernelGGL((k_resid_restrict<T, 3>), grid, dim3(kBlock), 0, st, M, x, b, nc, aptr, anodes, bc, xc, dc,
@@ -1967,7 +2021,7 @@ void newton_update(int64_t n, double gdt, const double* dx, double* y, double* y
     template void spmv<T>(int, int, const BlockOp<T>&, const T*, T*, T, const T*, T, const T*, const RankOne<T>*,   \
                           hipStream_t, const FirstStep<T>*);                                                         \
     template void spmv_full<T>(int, const int32_t*, const int32_t*, const T*, int64_t, const T*, T*, T, const T*, T, \
-                               const RankOne<T>*, hipStream_t);                                                      \
+                               const RankOne<T>*, hipStream_t, int, const int16_t*);                                 \
     template void outlet_dot<T>(int, const int32_t*, const int32_t*, const T*, const T*, const T*, T*, hipStream_t);  \
     template void axpby<T>(int64_t, T, const T*, T, const T*, T*, hipStream_t);                                      \
     template void fill<T>(int64_t, T, T*, hipStream_t);                                                              \
@@ -1983,9 +2037,9 @@ void newton_update(int64_t n, double gdt, const double* dx, double* y, double* y
     template void restrict_first<T>(int, int, const int32_t*, const int32_t*, const T*, T*, T*, T*, const T*,         \
                                     const T*, const T*, hipStream_t);                                                 \
     template void restrict_agg<T>(int, int, const int32_t*, const int32_t*, const T*, T*, hipStream_t);              \
-    template void shat_factored<T>(int, const int32_t*, const int32_t*, const int16_t*, const T*, int64_t, const T*, \
-                                   const T*, const int32_t*, const T*, T*, T*, T, const T*, T, const T*, const T*,   \
-                                   const T*, int, T*, int, int, hipStream_t);                                        \
+    template void shat_factored<T>(int, const int32_t*, const int32_t*, const int16_t*, int, const T*, int64_t,      \
+                                   const T*, const T*, const int32_t*, const T*, T*, T*, T, const T*, T, const T*,   \
+                                   const T*, const T*, int, T*, int, int, hipStream_t);                              \
     template void resid_restrict<T>(int, const BlockOp<T>&, const T*, const T*, int, const int32_t*, const int32_t*, \
                                     T*, T*, T*, const T*, const T*, const T*, hipStream_t);                          \
     template void prolong_add<T>(int, int, const int32_t*, const T*, T*, hipStream_t);                               \

@@ -191,6 +191,17 @@ std::string build_symbolic(const ns_mesh* m, const ns_ctx_opts& o, Symbolic& S) 
             for (int i = 0; i < N; ++i)
                 for (int k = g.rp[i]; k < g.rp[i + 1]; ++k) S.dcol[k] = (int16_t)(g.col[k] - i);
         }
+        // fixed-width rows (no row-pointer load in the FP32 products) when no
+        // row is longer than 16 blocks
+        int wmax = 0;
+        for (int i = 0; i < N; ++i) wmax = std::max(wmax, g.rp[i + 1] - g.rp[i]);
+        S.ell = (fits && wmax <= 16) ? wmax : 0;
+        S.dcol_ell.clear();
+        if (S.ell > 0) {
+            S.dcol_ell.assign((size_t)N * S.ell, 0);
+            for (int i = 0; i < N; ++i)
+                for (int k = g.rp[i]; k < g.rp[i + 1]; ++k) S.dcol_ell[(size_t)i * S.ell + (k - g.rp[i])] = S.dcol[k];
+        }
     }
     S.diag_pos.resize(N);
     S.row_of.resize(nnzb);

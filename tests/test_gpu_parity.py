@@ -48,7 +48,12 @@ LONG_ROWS = {"NS_ROW_UNROLL": "4"}
 # numbering puts a neighbour more than 32767 away take (every mesh here fits
 # the 16-bit column offsets).
 COL32 = {"NS_COL16": "0"}
-FORCED = {"large_mesh_paths": LARGE_PATHS, "long_row_trips": LONG_ROWS, "int32_columns": COL32}
+# FP32 tangent planes in the node graph's row layout instead of the fixed-width
+# rows that meshes with no row longer than 16 blocks take (every mesh here but
+# the unstructured channel); the unstructured channel takes this layout anyway.
+CSR32 = {"NS_ELL": "0"}
+FORCED = {"large_mesh_paths": LARGE_PATHS, "long_row_trips": LONG_ROWS, "int32_columns": COL32,
+          "csr_planes": CSR32}
 _CTX_FORCED = {}
 
 
@@ -106,7 +111,7 @@ def test_outlet_vectors_and_flow(name):
 
 @pytest.mark.parametrize("name", CASES)
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-13), ("fp32_inner", 2e-6)])
-@pytest.mark.parametrize("paths", ["by_size", "long_row_trips", "int32_columns"])
+@pytest.mark.parametrize("paths", ["by_size", "long_row_trips", "int32_columns", "csr_planes"])
 def test_operators_match_oracle(name, prec, tol, paths):
     from paper_1911_10814_amd import SolveOptions
     ctx = ctx_for(name) if paths == "by_size" else ctx_forced(name, FORCED[paths])
@@ -137,7 +142,7 @@ def test_shat_matches_oracle(name):
 
 
 @pytest.mark.parametrize("name", CASES)
-@pytest.mark.parametrize("paths", ["by_size", "large_mesh_paths", "long_row_trips", "int32_columns"])
+@pytest.mark.parametrize("paths", ["by_size", "large_mesh_paths", "long_row_trips", "int32_columns", "csr_planes"])
 @pytest.mark.parametrize("scale", [(1.0, 1.0), (1.6, 1.8)])
 def test_vcycles_match_oracle(name, paths, scale):
     from paper_1911_10814_amd import SolveOptions
@@ -194,7 +199,7 @@ def test_nested_solve_fp64_replay_and_tolerance(name):
 
 
 @pytest.mark.parametrize("name", ["pipe_tiny", "ybif_small", "conexp_small", "unstr_channel"])
-@pytest.mark.parametrize("paths", ["large_mesh_paths", "long_row_trips", "int32_columns"])
+@pytest.mark.parametrize("paths", ["large_mesh_paths", "long_row_trips", "int32_columns", "csr_planes"])
 def test_nested_solve_replay_on_large_mesh_paths(name, paths):
     """The whole FP64 nested solve through the kernel paths the large meshes
     take (separate prolongation pass on the finest A level, block SpMVs without
@@ -463,6 +468,35 @@ def test_sampled_kernel_timing():
         n3, ms3, b3 = counts[3][k]
         assert n1 > 10 and abs(n3 - n1 / 3) <= 1, (k, n1, n3)
         assert ms1 > 0 and ms3 > 0 and b1 > 0 and b3 > 0
+
+
+@pytest.mark.parametrize("name", ["conexp_small", "pipe_tiny"])
+def test_fixed_width_planes_match_row_layout_bitwise(name):
+    """The FP32 planes in fixed-width rows (zero blocks padding each row to the
+    longest) give the same values, bit for bit, as the node graph's row layout:
+    each operator and V-cycle, and the FP32-inner solve and adjoint with their
+    iteration counts.  Both meshes have no row longer than 16 blocks."""
+    from paper_1911_10814_amd import SolveOptions
+    ell = ctx_for(name)
+    csr = ctx_forced(name, CSR32)
+    o = SolveOptions(precision="fp32_inner")
+    rng = np.random.default_rng(5)
+    N = ell.N
+    for op, n in (("full", 4 * N), ("A", 3 * N), ("B", N), ("C", 3 * N), ("D", N), ("shat", N),
+                  ("vcycle_A", 3 * N), ("vcycle_S", N)):
+        x = rng.standard_normal(n)
+        ye, _ = ell.apply(op, x, o)
+        yc, _ = csr.apply(op, x, o)
+        torch.cuda.synchronize()
+        assert torch.equal(ye, yc), op
+    xe, ie = ell.solve(ell._rhs, o)
+    xc, ic = csr.solve(csr._rhs, o)
+    torch.cuda.synchronize()
+    assert ie["schedule"] == ic["schedule"] and torch.equal(xe, xc)
+    le, _ = ell.adjoint(ell._rhs, o)
+    lc, _ = csr.adjoint(csr._rhs, o)
+    torch.cuda.synchronize()
+    assert torch.equal(le, lc)
 
 
 @pytest.mark.parametrize("name", ["channel2", "plate_small"])
