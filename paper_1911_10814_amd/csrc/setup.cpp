@@ -192,10 +192,10 @@ std::string build_symbolic(const ns_mesh* m, const ns_ctx_opts& o, Symbolic& S) 
                 for (int k = g.rp[i]; k < g.rp[i + 1]; ++k) S.dcol[k] = (int16_t)(g.col[k] - i);
         }
         // fixed-width rows (no row-pointer load in the FP32 products) when no
-        // row is longer than 16 blocks
+        // row is longer than 16 blocks and the slots still have 32-bit indices
         int wmax = 0;
         for (int i = 0; i < N; ++i) wmax = std::max(wmax, g.rp[i + 1] - g.rp[i]);
-        S.ell = (fits && wmax <= 16) ? wmax : 0;
+        S.ell = (fits && wmax <= 16 && (int64_t)N * wmax <= INT32_MAX) ? wmax : 0;
         S.dcol_ell.clear();
         if (S.ell > 0) {
             S.dcol_ell.assign((size_t)N * S.ell, 0);
