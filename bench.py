@@ -123,6 +123,13 @@ def stream_ceiling(dev):
     return {k: round(v, 1) if isinstance(v, float) else v for k, v in out.items()}
 
 
+def layout_note(lay):
+    """How the bound context stores the finest-level FP32 planes and column indices."""
+    rows = f"fixed-width rows of {lay['ell']} blocks" if lay["ell_bound"] else "the node graph's rows"
+    cols = "16-bit column offsets" if lay["col16_bound"] else "32-bit column indices"
+    return f"FP32 tangent planes in {rows}; {cols}"
+
+
 def kernels_mode(args):
     """Finest-level kernels launched on their own (the A operator SpMV, one
     AMG V-cycle of A, one V-cycle of S_hat with its factored finest level, one
@@ -316,6 +323,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": describe(case, ctx.nnzb), "rtol": 1e-8, "rtol_A": 1e-3, "rtol_S": 1e-3,
                    "rtol_I": 1e-3, "P_A": args.pc_A, "P_S": "AMG(S_hat) V-cycle"},
+        "matrix_layout": layout_note(ctx.layout()),
         "fp64_solve_ms": round(solve64, 3),
         "speedup_fp32_inner_vs_fp64": round(solve64 / solve32, 3),
         "fp32_inner_vs_fp64_rel_err": {"v": err_v, "p": err_p},

@@ -445,6 +445,15 @@ ns_status ns_stream_bench(int32_t mode, const void* d_src, void* d_dst, size_t b
  * nodes, [5] AMG levels (including the coarsest). */
 ns_status ns_query(const ns_ctx* ctx, int64_t* h_sizes6);
 
+/* Layout of the finest-level matrix data: [0] the width of the fixed-width
+ * rows the FP32 planes may take (the longest row, when no row is longer than
+ * 16 blocks and the 16-bit offsets apply; 0 otherwise), [1] 1 when every
+ * column lies within 32767 of its row (16-bit offsets available); both known
+ * from ns_ctx_create on.  [2] and [3]: 1 when the bound context uses the
+ * fixed-width FP32 rows and the 16-bit offsets (ns_ctx_bind may switch either
+ * off: NS_ELL=0, NS_COL16=0); 0 before the first bind.  Host only. */
+ns_status ns_query_layout(const ns_ctx* ctx, int32_t* h_out4);
+
 /* Node-graph pattern: h_row_ptr [n_nodes + 1], h_col [nnzb] (sorted). */
 ns_status ns_export_pattern(const ns_ctx* ctx, int32_t* h_row_ptr, int32_t* h_col);
 

@@ -105,6 +105,7 @@ SIGNATURES = {
                                C.POINTER(NsSolveOpts), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                C.POINTER(NsStepStats), C.c_void_p]),
     "ns_query": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
+    "ns_query_layout": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32)]),
     "ns_kernel_timing": (C.c_int, [C.c_void_p, C.c_int32]),
     "ns_kernel_timing_period": (C.c_int, [C.c_void_p, C.c_int32]),
     "ns_kernel_timing_read": (C.c_int, [C.c_void_p, C.c_int32, PD]),

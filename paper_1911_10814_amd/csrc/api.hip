@@ -1953,6 +1953,15 @@ ns_status ns_query(const ns_ctx* c, int64_t* h) {
     return NS_OK;
 }
 
+ns_status ns_query_layout(const ns_ctx* c, int32_t* h) {
+    if (!c || !h) return NS_ERR_ARG;
+    h[0] = c->sym.ell;
+    h[1] = c->sym.dcol.empty() ? 0 : 1;
+    h[2] = c->bound && c->ell32 ? 1 : 0;
+    h[3] = c->bound && c->col16 ? 1 : 0;
+    return NS_OK;
+}
+
 ns_status ns_export_pattern(const ns_ctx* c, int32_t* rp, int32_t* col) {
     if (!c || !rp || !col) return NS_ERR_ARG;
     std::copy(c->sym.g.rp.begin(), c->sym.g.rp.end(), rp);

@@ -123,6 +123,14 @@ class NsContext:
         self._check(self.lib.ns_query(self.h, out))
         return list(out)
 
+    def layout(self):
+        """Finest-level layout: dict with the fixed-width row width the FP32 planes may take
+        (0: none), whether 16-bit column offsets are available, and what the bound context uses."""
+        out = (C.c_int32 * 4)()
+        self._check(self.lib.ns_query_layout(self.h, out))
+        return {"ell": out[0], "col16_available": bool(out[1]), "ell_bound": bool(out[2]),
+                "col16_bound": bool(out[3])}
+
     def bind(self):
         """Allocate the device workspace (one uint8 tensor) and upload the mesh."""
         if self.ws is not None:

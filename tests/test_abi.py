@@ -61,6 +61,28 @@ def test_symbolic_setup_matches_oracle(name):
             assert np.bincount(a).max() <= (2 if lev == 0 else 2 ** (cm - 1)) * 2
 
 
+@pytest.mark.parametrize("name", ["cube", "pipe_tiny", "unstr_channel"])
+def test_layout_choice_follows_the_pattern(name):
+    """The fixed-width FP32 rows take the longest row's width exactly when no
+    row is longer than 16 blocks and every column lies within 32767 of its row
+    (the 16-bit offsets); the unstructured channel has longer rows.  Nothing is
+    in use before a bind."""
+    from paper_1911_10814_amd import NsContext
+    ctx = NsContext(get_case(name))
+    rp, col = ctx.pattern()
+    lengths = np.diff(rp)
+    rows = np.repeat(np.arange(len(lengths)), lengths)
+    fits = int(np.abs(col.astype(np.int64) - rows).max()) <= 32767
+    lay = ctx.layout()
+    assert lay["col16_available"] == fits
+    assert lay["ell"] == (int(lengths.max()) if fits and lengths.max() <= 16 else 0)
+    assert not lay["ell_bound"] and not lay["col16_bound"]
+    if name == "unstr_channel":
+        assert lay["ell"] == 0 and lengths.max() > 16
+    else:
+        assert lay["ell"] == lengths.max() and lay["ell"] <= 16
+
+
 def test_invalid_mesh_is_rejected():
     from paper_1911_10814_amd import NsContext, NsError
     c = get_case("channel2")

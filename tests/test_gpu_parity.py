@@ -479,6 +479,8 @@ def test_fixed_width_planes_match_row_layout_bitwise(name):
     from paper_1911_10814_amd import SolveOptions
     ell = ctx_for(name)
     csr = ctx_forced(name, CSR32)
+    assert ell.layout()["ell_bound"] and not csr.layout()["ell_bound"]
+    assert ell.layout()["col16_bound"] and csr.layout()["col16_bound"]
     o = SolveOptions(precision="fp32_inner")
     rng = np.random.default_rng(5)
     N = ell.N
