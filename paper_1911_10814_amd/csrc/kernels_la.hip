@@ -369,8 +369,28 @@ __global__ __launch_bounds__(kBlock) void k_outlet_dot(const int32_t* optr, cons
                                                        const T* c, const T* x, T* s) {
     __shared__ T lds[4];
     const int k = blockIdx.x;
+    const int end = optr[k + 1];
     T acc = 0;
-    for (int sl = optr[k] + threadIdx.x; sl < optr[k + 1]; sl += kBlock) {
+    // four slots per trip, all loads issued before the first sum; the slots
+    // are still added one by one in the order of sl
+    int sl = optr[k] + threadIdx.x;
+    for (; sl + 3 * kBlock < end; sl += 4 * kBlock) {
+        int64_t nd[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) nd[u] = onode[sl + u * kBlock];
+        T a[4][3], xv[4][3];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) a[u][c] = aval[3 * (int64_t)(sl + u * kBlock) + c];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) xv[u][c] = x[3 * nd[u] + c];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc += a[u][0] * xv[u][0] + a[u][1] * xv[u][1] + a[u][2] * xv[u][2];
+    }
+    for (; sl < end; sl += kBlock) {
         const int64_t nd = onode[sl];
         acc += aval[3 * (int64_t)sl] * x[3 * nd] + aval[3 * (int64_t)sl + 1] * x[3 * nd + 1] +
                aval[3 * (int64_t)sl + 2] * x[3 * nd + 2];
@@ -471,6 +491,19 @@ __device__ inline Pk<T> ld_pk(const T* __restrict__ p, int64_t q, int64_t n) {
             if (q * W + e >= n) v.e[e] = T(0);
     }
     return v;
+}
+// A run of pack loads issued back to back (no branch between them), the
+// tail of the last pack of the vectors zeroed afterwards: raw loads, then
+// pk_tail on each.
+template <typename T>
+__device__ inline Pk<T> ld_pk_raw(const T* __restrict__ p, int64_t q) {
+    return reinterpret_cast<const Pk<T>*>(p)[q];
+}
+template <typename T>
+__device__ inline void pk_tail(Pk<T>& v, int64_t q, int64_t n) {
+#pragma unroll
+    for (int e = 0; e < Pk<T>::W; ++e)
+        if (q * Pk<T>::W + e >= n) v.e[e] = T(0);
 }
 template <typename T>
 __device__ inline T pk_dot(const Pk<T>& a, const Pk<T>& b) {
@@ -601,11 +634,21 @@ __global__ __launch_bounds__(kCgsBlock) void k_multidot(int64_t n, int k, const 
 #pragma unroll
     for (int g = 0; g < kDotGroup; ++g) acc[g] = 0;
     for (int64_t q = (int64_t)blockIdx.x * kCgsBlock + threadIdx.x; q < np; q += (int64_t)gridDim.x * kCgsBlock) {
-        const Pk<T> wp = ld_pk(w, q, n);
+        // every pack of the group is loaded before the first is used
+        Pk<T> wp = ld_pk_raw(w, q);
+        Pk<T> v[kDotGroup];
+#pragma unroll
+        for (int g = 0; g < kDotGroup; ++g)
+            if (i0 + g < k) v[g] = ld_pk_raw(V + (int64_t)(i0 + g) * ldv, q);
+        if ((q + 1) * Pk<T>::W > n) {
+            pk_tail(wp, q, n);
+#pragma unroll
+            for (int g = 0; g < kDotGroup; ++g) pk_tail(v[g], q, n);
+        }
 #pragma unroll
         for (int g = 0; g < kDotGroup; ++g) {
             const int i = i0 + g;
-            if (i < k) acc[g] += pk_dot(ld_pk(V + (int64_t)i * ldv, q, n), wp);
+            if (i < k) acc[g] += pk_dot(v[g], wp);
             else if (i == k) acc[g] += pk_dot(wp, wp);
         }
     }
@@ -614,6 +657,7 @@ __global__ __launch_bounds__(kCgsBlock) void k_multidot(int64_t n, int k, const 
 
 // w -= sum_{i<k} V_i hs_i over this block's packs; returns the sum of the
 // squares of the updated entries this thread owns.
+constexpr int kSubLoads = 8;
 template <typename T>
 __device__ inline T orth_subtract(int64_t n, int k, const T* __restrict__ V, int64_t ldv, const T* hs,
                                   T* __restrict__ w) {
@@ -623,11 +667,23 @@ __device__ inline T orth_subtract(int64_t n, int k, const T* __restrict__ V, int
         Pk<T> s;
 #pragma unroll
         for (int e = 0; e < Pk<T>::W; ++e) s.e[e] = 0;
-        for (int i = 0; i < k; ++i) {
-            const Pk<T> v = ld_pk(V + (int64_t)i * ldv, q, n);
-            const T h = hs[i];
+        // kSubLoads packs in flight at a time, added in the order of i
+        for (int i0 = 0; i0 < k; i0 += kSubLoads) {
+            Pk<T> v[kSubLoads];
 #pragma unroll
-            for (int e = 0; e < Pk<T>::W; ++e) s.e[e] += v.e[e] * h;
+            for (int u = 0; u < kSubLoads; ++u)
+                if (i0 + u < k) v[u] = ld_pk_raw(V + (int64_t)(i0 + u) * ldv, q);
+            if ((q + 1) * Pk<T>::W > n) {
+#pragma unroll
+                for (int u = 0; u < kSubLoads; ++u) pk_tail(v[u], q, n);
+            }
+#pragma unroll
+            for (int u = 0; u < kSubLoads; ++u)
+                if (i0 + u < k) {
+                    const T h = hs[i0 + u];
+#pragma unroll
+                    for (int e = 0; e < Pk<T>::W; ++e) s.e[e] += v[u].e[e] * h;
+                }
         }
         Pk<T> wp = ld_pk(w, q, n);
 #pragma unroll
@@ -698,10 +754,19 @@ __global__ __launch_bounds__(kCgsBlock) void k_orth_dot(int64_t n, int k, const 
         for (int g = 0; g < kDotGroup; ++g) acc[g] = 0;
         for (int64_t q = (int64_t)blockIdx.x * kCgsBlock + threadIdx.x; q < np;
              q += (int64_t)gridDim.x * kCgsBlock) {
-            const Pk<T> wp = ld_pk(w, q, n);
+            Pk<T> wp = ld_pk_raw(w, q);
+            Pk<T> v[kDotGroup];
 #pragma unroll
             for (int g = 0; g < kDotGroup; ++g)
-                if (i0 + g < k) acc[g] += pk_dot(ld_pk(V + (int64_t)(i0 + g) * ldv, q, n), wp);
+                if (i0 + g < k) v[g] = ld_pk_raw(V + (int64_t)(i0 + g) * ldv, q);
+            if ((q + 1) * Pk<T>::W > n) {
+                pk_tail(wp, q, n);
+#pragma unroll
+                for (int g = 0; g < kDotGroup; ++g) pk_tail(v[g], q, n);
+            }
+#pragma unroll
+            for (int g = 0; g < kDotGroup; ++g)
+                if (i0 + g < k) acc[g] += pk_dot(v[g], wp);
         }
         block_partials<T, kDotGroup>(acc, min(kDotGroup, k - i0), lds, red2 + (int64_t)i0 * gridDim.x);
     }
@@ -824,7 +889,11 @@ __global__ __launch_bounds__(kBlock) void k_combine(int64_t n, int k, const T* _
                 for (; i + kCombineUnroll <= cnt; i += kCombineUnroll) {
                     Pk<T> v[kCombineUnroll];
 #pragma unroll
-                    for (int u = 0; u < kCombineUnroll; ++u) v[u] = ld_pk(V + (int64_t)(c0 + i + u) * ldv, q, n);
+                    for (int u = 0; u < kCombineUnroll; ++u) v[u] = ld_pk_raw(V + (int64_t)(c0 + i + u) * ldv, q);
+                    if ((q + 1) * W > n) {
+#pragma unroll
+                        for (int u = 0; u < kCombineUnroll; ++u) pk_tail(v[u], q, n);
+                    }
 #pragma unroll
                     for (int u = 0; u < kCombineUnroll; ++u)
 #pragma unroll
