@@ -802,7 +802,24 @@ __global__ __launch_bounds__(kCgsBlock) void k_finish(int64_t n, T* __restrict__
     if (!(hn > 1e-14 * wpre)) return;
     const T s = (T)(1.0 / hn);
     const int64_t np = n_packs<T>(n);
-    for (int64_t q = (int64_t)blockIdx.x * kCgsBlock + threadIdx.x; q < np; q += (int64_t)gridDim.x * kCgsBlock) {
+    const int64_t stride = (int64_t)gridDim.x * kCgsBlock;
+    int64_t q = (int64_t)blockIdx.x * kCgsBlock + threadIdx.x;
+    // four packs per trip, loaded together
+    for (; q + 3 * stride < np; q += 4 * stride) {
+        Pk<T> wp[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) wp[u] = ld_pk_raw(w, q + u * stride);
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if ((q + u * stride + 1) * Pk<T>::W > n) pk_tail(wp[u], q + u * stride, n);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+#pragma unroll
+            for (int e = 0; e < Pk<T>::W; ++e) wp[u].e[e] *= s;
+            reinterpret_cast<Pk<T>*>(w)[q + u * stride] = wp[u];
+        }
+    }
+    for (; q < np; q += stride) {
         Pk<T> wp = ld_pk(w, q, n);
 #pragma unroll
         for (int e = 0; e < Pk<T>::W; ++e) wp.e[e] *= s;
@@ -1413,15 +1430,37 @@ __global__ __launch_bounds__(kBlock) void k_resid_restrict(BlockOp<T> M, const T
         for (int q = aptr[I] + sub; q < q1; q += kAggMax) {
             const int row = anodes[q];
             const int k1 = M.rp[row + 1];
-            for (int k = M.rp[row] + l; k < k1; k += kRowLanes) {
-                const int j = M.col[k];
-                T xj[BS];
+            // four blocks per lane per trip, every load of the trip issued
+            // before the first sum; a block past the row end loads the trip's
+            // first again and adds nothing, so the sums are those of one block
+            // at a time
+            for (int k0 = M.rp[row] + l; k0 < k1; k0 += 4 * kRowLanes) {
+                int kk[4];
+                bool on[4];
+                trip_blocks<4>(k0, k1, kRowLanes, kk, on);
+                int j[4];
 #pragma unroll
-                for (int c = 0; c < BS; ++c) xj[c] = x[(int64_t)BS * j + c];
+                for (int u = 0; u < 4; ++u) j[u] = M.col[kk[u]];
+                T v[4][BS * BS];
 #pragma unroll
-                for (int r = 0; r < BS; ++r)
+                for (int u = 0; u < 4; ++u)
 #pragma unroll
-                    for (int c = 0; c < BS; ++c) acc[r] += M.v[r * M.rs + c * M.cs + k] * xj[c];
+                    for (int r = 0; r < BS; ++r)
+#pragma unroll
+                        for (int c = 0; c < BS; ++c) v[u][r * BS + c] = M.v[r * M.rs + c * M.cs + kk[u]];
+                T xj[4][BS];
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+#pragma unroll
+                    for (int c = 0; c < BS; ++c) xj[u][c] = x[(int64_t)BS * j[u] + c];
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    if (on[u]) {
+#pragma unroll
+                        for (int r = 0; r < BS; ++r)
+#pragma unroll
+                            for (int c = 0; c < BS; ++c) acc[r] += v[u][r * BS + c] * xj[u][c];
+                    }
             }
             if (l < BS) {
                 const int64_t i = (int64_t)BS * row + l;
