@@ -1430,31 +1430,34 @@ __global__ __launch_bounds__(kBlock) void k_resid_restrict(BlockOp<T> M, const T
         for (int q = aptr[I] + sub; q < q1; q += kAggMax) {
             const int row = anodes[q];
             const int k1 = M.rp[row + 1];
-            // four blocks per lane per trip, every load of the trip issued
-            // before the first sum; a block past the row end loads the trip's
-            // first again and adds nothing, so the sums are those of one block
-            // at a time
-            for (int k0 = M.rp[row] + l; k0 < k1; k0 += 4 * kRowLanes) {
-                int kk[4];
-                bool on[4];
-                trip_blocks<4>(k0, k1, kRowLanes, kk, on);
-                int j[4];
+            // U blocks per lane per trip, every load of the trip issued before
+            // the first sum; a block past the row end loads the trip's first
+            // again and adds nothing, so the sums are those of one block at a
+            // time.  Scalar rows take four (measured 36.3 -> 32.5 us on the
+            // 4e6-node contraction-expansion's level-1 S_hat); 3x3 blocks one,
+            // as four would hold 116 registers (172 -> 249 us on level 1 of A)
+            constexpr int U = BS == 1 ? 4 : 1;
+            for (int k0 = M.rp[row] + l; k0 < k1; k0 += U * kRowLanes) {
+                int kk[U];
+                bool on[U];
+                trip_blocks<U>(k0, k1, kRowLanes, kk, on);
+                int j[U];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) j[u] = M.col[kk[u]];
-                T v[4][BS * BS];
+                for (int u = 0; u < U; ++u) j[u] = M.col[kk[u]];
+                T v[U][BS * BS];
 #pragma unroll
-                for (int u = 0; u < 4; ++u)
+                for (int u = 0; u < U; ++u)
 #pragma unroll
                     for (int r = 0; r < BS; ++r)
 #pragma unroll
                         for (int c = 0; c < BS; ++c) v[u][r * BS + c] = M.v[r * M.rs + c * M.cs + kk[u]];
-                T xj[4][BS];
+                T xj[U][BS];
 #pragma unroll
-                for (int u = 0; u < 4; ++u)
+                for (int u = 0; u < U; ++u)
 #pragma unroll
                     for (int c = 0; c < BS; ++c) xj[u][c] = x[(int64_t)BS * j[u] + c];
 #pragma unroll
-                for (int u = 0; u < 4; ++u)
+                for (int u = 0; u < U; ++u)
                     if (on[u]) {
 #pragma unroll
                         for (int r = 0; r < BS; ++r)
