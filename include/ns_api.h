@@ -457,6 +457,12 @@ ns_status ns_query_layout(const ns_ctx* ctx, int32_t* h_out4);
 /* Node-graph pattern: h_row_ptr [n_nodes + 1], h_col [nnzb] (sorted). */
 ns_status ns_export_pattern(const ns_ctx* ctx, int32_t* h_row_ptr, int32_t* h_col);
 
+/* Column offsets of the fixed-width rows (width w = ns_query_layout()[0]):
+ * h_dcol [n_nodes * w], slot l of row i at i*w + l holding col - i, 0 past
+ * the row's end.  NS_ERR_ARG when the pattern has no fixed-width rows.
+ * Host only. */
+ns_status ns_export_fixed_width_offsets(const ns_ctx* ctx, int16_t* h_dcol);
+
 /* Aggregate map of AMG level `level` (fine node -> coarse node), [nodes of
  * that level]. */
 ns_status ns_export_aggregates(const ns_ctx* ctx, int32_t level, int32_t* h_agg);

@@ -110,6 +110,7 @@ SIGNATURES = {
     "ns_kernel_timing_period": (C.c_int, [C.c_void_p, C.c_int32]),
     "ns_kernel_timing_read": (C.c_int, [C.c_void_p, C.c_int32, PD]),
     "ns_export_pattern": (C.c_int, [C.c_void_p, PI, PI]),
+    "ns_export_fixed_width_offsets": (C.c_int, [C.c_void_p, C.POINTER(C.c_int16)]),
     "ns_export_aggregates": (C.c_int, [C.c_void_p, C.c_int32, PI]),
     "ns_export_colors": (C.c_int, [C.c_void_p, PI]),
     "ns_export_bsr": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),

@@ -1962,6 +1962,12 @@ ns_status ns_query_layout(const ns_ctx* c, int32_t* h) {
     return NS_OK;
 }
 
+ns_status ns_export_fixed_width_offsets(const ns_ctx* c, int16_t* h) {
+    if (!c || !h || c->sym.ell == 0) return NS_ERR_ARG;
+    std::copy(c->sym.dcol_ell.begin(), c->sym.dcol_ell.end(), h);
+    return NS_OK;
+}
+
 ns_status ns_export_pattern(const ns_ctx* c, int32_t* rp, int32_t* col) {
     if (!c || !rp || !col) return NS_ERR_ARG;
     std::copy(c->sym.g.rp.begin(), c->sym.g.rp.end(), rp);

@@ -164,6 +164,13 @@ class NsContext:
         self._check(self.lib.ns_export_pattern(self.h, rp.ctypes.data_as(_lib.PI), col.ctypes.data_as(_lib.PI)))
         return rp, col
 
+    def fixed_width_offsets(self):
+        """[N, w] column offsets (col - row) of the fixed-width rows, 0 past each row's end."""
+        w = self.layout()["ell"]
+        out = np.zeros(self.N * w, np.int16)
+        self._check(self.lib.ns_export_fixed_width_offsets(self.h, out.ctypes.data_as(C.POINTER(C.c_int16))))
+        return out.reshape(self.N, w)
+
     def aggregates(self, level):
         n = self.N
         for lev in range(level):

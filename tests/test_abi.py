@@ -65,9 +65,10 @@ def test_symbolic_setup_matches_oracle(name):
 def test_layout_choice_follows_the_pattern(name):
     """The fixed-width FP32 rows take the longest row's width exactly when no
     row is longer than 16 blocks and every column lies within 32767 of its row
-    (the 16-bit offsets); the unstructured channel has longer rows.  Nothing is
-    in use before a bind."""
-    from paper_1911_10814_amd import NsContext
+    (the 16-bit offsets); the unstructured channel has longer rows.  Their
+    offsets are the pattern's, row by row, zero-padded.  Nothing is in use
+    before a bind."""
+    from paper_1911_10814_amd import NsContext, NsError
     ctx = NsContext(get_case(name))
     rp, col = ctx.pattern()
     lengths = np.diff(rp)
@@ -79,8 +80,16 @@ def test_layout_choice_follows_the_pattern(name):
     assert not lay["ell_bound"] and not lay["col16_bound"]
     if name == "unstr_channel":
         assert lay["ell"] == 0 and lengths.max() > 16
+        with pytest.raises(NsError):
+            ctx.fixed_width_offsets()
     else:
         assert lay["ell"] == lengths.max() and lay["ell"] <= 16
+        # slot l of row i holds col - i for l below the row's length, 0 after it
+        off = ctx.fixed_width_offsets()
+        want = np.zeros_like(off)
+        for i in range(len(lengths)):
+            want[i, :lengths[i]] = col[rp[i]:rp[i + 1]] - i
+        assert np.array_equal(off, want)
 
 
 def test_invalid_mesh_is_rejected():
